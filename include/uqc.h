@@ -1,0 +1,192 @@
+/* uqc: two-electron repulsion integrals and Coulomb/exchange (Fock) builds on the AMD MI355X (gfx950).
+ *
+ * What is computed (arXiv:1303.4916, Sec. "Implementation details" and Sec. "Technical details"):
+ *   - basis functions are contracted Cartesian Gaussians, Eq. (1): phi_i = sum_n d_in x^L y^M z^N exp(-alpha_n r^2),
+ *     one exponent per primitive shared by all Cartesian components of a shell;
+ *   - electron-repulsion integrals (ij|kl), Eq. (5), in chemists' notation;
+ *   - J_ij = sum_kl (ij|kl) D_kl and K_il = sum_jk (ij|kl) D_jk, Eq. (12), for a symmetric density D;
+ *   - G = J - K/2 and E2 = 1/2 sum_ij D_ij G_ij (closed-shell convention; D is the total density).
+ *
+ * Conventions:
+ *   - units: bohr (positions) and hartree (integrals);
+ *   - l = 0, 1, 2 only (s, p, Cartesian d); contraction depth 1..16;
+ *   - coefficients refer to normalised primitives; the library normalises primitives and then every Cartesian
+ *     component of every contracted function to unit self-overlap;
+ *   - basis functions are numbered shell by shell in input order; inside a shell the Cartesian components are
+ *     ordered by descending x power, then descending y power: p = x, y, z; d = xx, xy, xz, yy, yz, zz;
+ *   - matrices are nbf x nbf, row-major, FP64;
+ *   - Schwarz screening: a shell quartet (ab|cd) is computed iff Q_ab * Q_cd >= tau with
+ *     Q_ab = sqrt(max_{i in a, j in b} (ij|ij)); tau = 0 computes every quartet.
+ *
+ * Errors: every call returns a uqc_status; nothing aborts.  The message of the last failing call on the calling
+ * thread is available from uqc_last_error().
+ *
+ * Threading: one uqc_ctx per device; a context and the objects made from it must not be used by two host threads
+ * at once, except uqc_submit / uqc_poll on a server, which are thread-safe.
+ */
+#ifndef UQC_H
+#define UQC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct uqc_ctx uqc_ctx;
+typedef struct uqc_basis uqc_basis;
+typedef struct uqc_server uqc_server;
+
+typedef enum {
+    UQC_OK = 0,
+    UQC_PENDING = 1,            /* uqc_poll: request not finished yet */
+    UQC_E_ARG = -1,             /* invalid argument (null pointer, index out of range, non-finite value, ...) */
+    UQC_E_UNSUPPORTED = -2,     /* l > 2 or contraction depth > 16 */
+    UQC_E_NOMEM = -3,           /* device allocation failed, or a request exceeds the whole HBM budget */
+    UQC_E_DEVICE = -4,          /* a HIP runtime call failed */
+    UQC_E_NOT_SYMMETRIC = -5,   /* max|D - D^T| > 1e-12 max|D| */
+    UQC_E_NOT_FOUND = -6,       /* unknown ticket */
+    UQC_E_BUSY = -7             /* server is shutting down */
+} uqc_status;
+
+typedef enum { UQC_FP64 = 0, UQC_MIXED = 1 } uqc_precision;
+
+/* Options of a Fock build.  Call uqc_fock_opts_default() first. */
+typedef struct {
+    double schwarz_tau;   /* screening threshold tau (>= 0) */
+    int precision;        /* uqc_precision.  UQC_MIXED: primitive recursions in FP32 with FP64 accumulation, except
+                             quartets with Q_ab Q_cd > fp64_bound (whole quartet in FP64) and Boys arguments
+                             T > 30 (Boys function evaluated in FP64); J, K, G, E2 always accumulated in FP64 */
+    double fp64_bound;    /* default 1e-3 */
+    int timing;           /* 1: time every class launch with HIP events (reported in uqc_stats) */
+} uqc_fock_opts;
+
+#define UQC_MAX_CLASS_STATS 96
+
+/* Per-build statistics.  Counts are of canonical shell quartets (a>=b, c>=d, ab>=cd). */
+typedef struct {
+    double E2;                      /* 1/2 sum D G */
+    long long quartets;             /* shell quartets computed (after screening) */
+    long long quartets_screened;    /* canonical shell quartets skipped by screening */
+    long long prim_quartets;        /* primitive quartets computed */
+    long long fp64_quartets;        /* shell quartets computed with FP64 recursions */
+    double flops;                   /* algorithmic FLOPs of the build (frozen per-class operation counts) */
+    double ms;                      /* host wall time of the call */
+    double eri_ms;                  /* sum of ERI class-kernel times (timing = 1 only) */
+    int nclass;                     /* number of class launches reported below (timing = 1 only) */
+    int class_id[UQC_MAX_CLASS_STATS];      /* la*1000 + lb*100 + lc*10 + ld; +10000 if FP32 recursions */
+    double class_ms[UQC_MAX_CLASS_STATS];
+    double class_flops[UQC_MAX_CLASS_STATS];
+    long long class_quartets[UQC_MAX_CLASS_STATS];
+} uqc_stats;
+
+/* Fills *o with: tau = 1e-12, precision = UQC_FP64, fp64_bound = 1e-3, timing = 0. */
+void uqc_fock_opts_default(uqc_fock_opts* o);
+
+/* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t the library launches on (NULL: the
+ * library creates its own stream and destroys it in uqc_finalize).  The caller keeps ownership of its stream. */
+uqc_status uqc_init(int device, void* hip_stream, uqc_ctx** out);
+/* Destroys the context.  Every basis and server made from it must have been destroyed first. */
+uqc_status uqc_finalize(uqc_ctx* ctx);
+
+/* Message of the last non-OK status returned on this thread ("" if none).  Valid until the next uqc call. */
+const char* uqc_last_error(void);
+
+/* Builds a basis (Eq. 1) and its screening plan: normalisation, primitive-pair data, Schwarz bounds (on the GPU),
+ * pairs sorted by bound inside (l_a, l_b, K_a, K_b) bins.  Arrays are copied; the caller keeps ownership.
+ *   l[nshell]            angular momentum 0..2
+ *   nprim[nshell]        contraction depth 1..16
+ *   center[nshell*3]     shell centres (bohr)
+ *   alpha[sum nprim]     primitive exponents (> 0), shell by shell
+ *   coef[sum nprim]      contraction coefficients for normalised primitives
+ * Errors: UQC_E_ARG, UQC_E_UNSUPPORTED, UQC_E_NOMEM, UQC_E_DEVICE. */
+uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* nprim, const double* center,
+                            const double* alpha, const double* coef, uqc_basis** out);
+uqc_status uqc_basis_destroy(uqc_basis* b);
+
+/* Number of basis functions and (optionally, may be NULL) the first basis-function index of every shell. */
+uqc_status uqc_basis_info(const uqc_basis* b, int* nbf, int* shell_offset);
+
+/* Schwarz bounds Q_ab (host array nshell*nshell, symmetric), as computed on the GPU at basis creation. */
+uqc_status uqc_schwarz(const uqc_basis* b, double* Q);
+
+/* One contracted block (ab|cd), Eq. (5): n_a*n_b*n_c*n_d doubles written to host memory `out`, row-major [i][j][k][l]
+ * over the Cartesian components of shells a, b, c, d (any order of the four shell indices).  precision selects the
+ * recursions' arithmetic (UQC_MIXED: FP32 recursions, FP64 contraction).  Never screened. */
+uqc_status uqc_eri_block(uqc_basis* b, int a, int bb, int c, int d, int precision, double* out);
+
+/* n blocks at once: quartets[4*q .. 4*q+3] = (a, b, c, d); blocks are written one after another to `out` (host),
+ * each laid out as in uqc_eri_block. */
+uqc_status uqc_eri_blocks(uqc_basis* b, int n, const int* quartets, int precision, double* out);
+
+/* Fock build, Eq. (12): J(D), K(D), G = J - K/2 and E2 for a symmetric density D (nbf*nbf, row-major).
+ * D, J, K, G are either all device pointers (e.g. torch tensors on the context's device; the work is ordered on the
+ * context's stream and the call returns after it completes) or all host pointers (copied in and out).  Any of J,
+ * K, G may be NULL.  `stats` may be NULL.
+ * Errors: UQC_E_ARG, UQC_E_NOT_SYMMETRIC, UQC_E_NOMEM, UQC_E_DEVICE. */
+uqc_status uqc_fock_build(uqc_basis* b, const double* D, double* J, double* K, double* G, const uqc_fock_opts* opts,
+                          uqc_stats* stats);
+
+/* Device Boys function, for verification: F_0..F_mmax (mmax <= 8) at n arguments T (host arrays; out is
+ * n*(mmax+1), row-major).  precision UQC_FP64: tabulated Taylor grid + downward recursion (asymptotic form with
+ * upward recursion beyond the grid); UQC_MIXED: the FP32 evaluation used for T <= 30 in mixed mode. */
+uqc_status uqc_boys(uqc_ctx* ctx, int precision, int mmax, int n, const double* T, double* out);
+
+/* ------------------------------------------------------------------------------------------------------------
+ * Serving: a request loop that admits Fock-build requests for molecules of different sizes as they arrive,
+ * subject to an HBM budget and a slot limit, keeps each request's basis plan and density resident on the device
+ * between iterations, and runs the quartet classes of all admitted requests together, one launch per class.
+ *
+ * A request runs n_iter builds.  Iteration t uses density D_t; after it, D_{t+1} = (1-eps) D_t + eps R_t R_t^T
+ * rescaled to tr(D_0), with R_t an nbf x ncol matrix of standard normal numbers drawn on the device from a
+ * counter-based generator keyed by (seed, t) (SplitMix64 finaliser, Box-Muller).
+ * ------------------------------------------------------------------------------------------------------------ */
+typedef struct {
+    int nshell;
+    const int* l;
+    const int* nprim;
+    const double* center;
+    const double* alpha;
+    const double* coef;
+    const double* D0;           /* nbf*nbf host, symmetric */
+    int n_iter;                 /* 1..64 */
+    int ncol;                   /* columns of R_t (>= 1) */
+    double eps;                 /* perturbation weight in [0, 1] */
+    unsigned long long seed;
+    uqc_fock_opts opts;
+    double arrival_ms;          /* arrival time stamp on the caller's clock (reported back; informational) */
+} uqc_request;
+
+#define UQC_MAX_ITER 64
+
+typedef struct {
+    int n_iter;
+    int nbf;
+    double E2[UQC_MAX_ITER];    /* E2 of every iteration */
+    double submit_ms;           /* server clock (ms since server creation) at submit */
+    double admit_ms;            /* ... when admitted to the device */
+    double finish_ms;           /* ... when the last iteration completed */
+    long long quartets;         /* shell quartets computed over all iterations */
+    double* J;                  /* optional host outputs (nbf*nbf) of the LAST iteration: set to caller memory or */
+    double* K;                  /* NULL before calling uqc_poll; filled when the request is done */
+    double* G;
+    double* D;                  /* density of the last iteration */
+} uqc_result;
+
+/* hbm_budget_bytes: device memory the server may hold for admitted requests; max_slots: admitted at once. */
+uqc_status uqc_server_create(uqc_ctx* ctx, size_t hbm_budget_bytes, int max_slots, uqc_server** out);
+/* Copies the request; returns a ticket.  UQC_E_NOMEM if the request alone exceeds the budget. */
+uqc_status uqc_submit(uqc_server* s, const uqc_request* req, long long* ticket);
+/* UQC_PENDING while queued or running; UQC_OK once finished (result filled, ticket released);
+ * UQC_E_NOT_FOUND for an unknown or already collected ticket. */
+uqc_status uqc_poll(uqc_server* s, long long ticket, uqc_result* res);
+/* Runs the server loop on the calling thread until every submitted request is finished (for callers without a
+ * background thread); returns immediately if the server has its own thread. */
+uqc_status uqc_server_drain(uqc_server* s);
+/* Stops accepting work, finishes outstanding requests, frees everything. */
+uqc_status uqc_server_destroy(uqc_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UQC_H */

@@ -1,0 +1,902 @@
+// Host side of libuqc: contexts, basis plans (normalisation, primitive-pair data, Schwarz bounds, pair bins and
+// screened work lists), the ERI-block and Fock-build entry points of include/uqc.h.
+#include "uqc_api_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+using namespace uqc;
+
+namespace {
+thread_local std::string g_err;
+}
+
+uqc_status uqc_fail(uqc_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+const char* uqc_last_error(void) { return g_err.c_str(); }
+
+void uqc_fock_opts_default(uqc_fock_opts* o) {
+    if (!o) return;
+    o->schwarz_tau = 1e-12;
+    o->precision = UQC_FP64;
+    o->fp64_bound = 1e-3;
+    o->timing = 0;
+}
+
+// ---------------------------------------------------------------------------------------------- Boys table
+// F_n(T_g), n = 0..15, T_g = g/10 for g = 0..400, from Gauss-Legendre quadrature (long double, 96 nodes) of the
+// defining integral F_n(T) = int_0^1 t^{2n} exp(-T t^2) dt; the integrand is entire, so the rule converges to the
+// working precision for T <= 40.
+static void legendre_nodes(int n, std::vector<long double>& x, std::vector<long double>& w) {
+    x.resize(n);
+    w.resize(n);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < n; ++i) {
+        long double z = std::cos(pi * (i + 0.75L) / (n + 0.5L));
+        long double dp = 0;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1);
+            const long double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-21L) break;
+        }
+        long double p0 = 1, p1 = z;
+        for (int k = 2; k <= n; ++k) {
+            long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1);
+        x[i] = z;
+        w[i] = 2 / ((1 - z * z) * dp * dp);
+    }
+}
+
+static void build_boys_table(std::vector<double>& tab) {
+    std::vector<long double> x, w;
+    legendre_nodes(96, x, w);
+    tab.assign((size_t)kBoysNg * kBoysNm, 0.0);
+    for (int g = 0; g < kBoysNg; ++g) {
+        const long double T = (long double)((double)g * 0.1);
+        for (int n = 0; n < kBoysNm; ++n) {
+            long double s = 0;
+            for (size_t i = 0; i < x.size(); ++i) {
+                const long double t = 0.5L * (x[i] + 1);  // map [-1, 1] -> [0, 1]
+                long double tp = 1;
+                for (int k = 0; k < n; ++k) tp *= t * t;
+                s += w[i] * tp * std::exp(-T * t * t);
+            }
+            tab[(size_t)g * kBoysNm + n] = (double)(0.5L * s);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------- context
+uqc_status uqc_init(int device, void* hip_stream, uqc_ctx** out) {
+    if (!out) return uqc_fail(UQC_E_ARG, "uqc_init: out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return uqc_fail(UQC_E_DEVICE, "uqc_init: no HIP device");
+    if (device < 0 || device >= ndev) return uqc_fail(UQC_E_ARG, "uqc_init: device index out of range");
+    UQC_HIP(hipSetDevice(device));
+    uqc_ctx* c = new uqc_ctx();
+    c->device = device;
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+        c->own_stream = false;
+    } else {
+        if (hipStreamCreate(&c->stream) != hipSuccess) {  // blocking: ordered after work on the null stream
+            delete c;
+            return uqc_fail(UQC_E_DEVICE, "uqc_init: hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    std::vector<double> tab;
+    build_boys_table(tab);
+    std::vector<float> tab32(tab.size());
+    for (size_t i = 0; i < tab.size(); ++i) tab32[i] = (float)tab[i];
+    if (hipMalloc(&c->boys64, tab.size() * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->boys32, tab32.size() * sizeof(float)) != hipSuccess) {
+        uqc_finalize(c);
+        return uqc_fail(UQC_E_NOMEM, "uqc_init: cannot allocate the Boys table");
+    }
+    if (hipMemcpy(c->boys64, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->boys32, tab32.data(), tab32.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        uqc_finalize(c);
+        return uqc_fail(UQC_E_DEVICE, "uqc_init: cannot upload the Boys table");
+    }
+    *out = c;
+    return UQC_OK;
+}
+
+uqc_status uqc_finalize(uqc_ctx* c) {
+    if (!c) return uqc_fail(UQC_E_ARG, "uqc_finalize: NULL context");
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& e : c->events) (void)hipEventDestroy(e);
+    if (c->boys64) (void)hipFree(c->boys64);
+    if (c->boys32) (void)hipFree(c->boys32);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return UQC_OK;
+}
+
+hipEvent_t ctx_event(uqc_ctx* c, size_t i) {
+    while (c->events.size() <= i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->events.push_back(e);
+    }
+    return c->events[i];
+}
+
+// ---------------------------------------------------------------------------------------------- basis
+static int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+static int pclass(int la, int lb) {
+    static const int tab[3][3] = {{0, -1, -1}, {1, 2, -1}, {3, 4, 5}};
+    return tab[la][lb];
+}
+
+uqc_basis::~uqc_basis() {
+    (void)hipSetDevice(ctx->device);
+    for (auto& b : bins) {
+        if (b.d_mem) (void)hipFree(b.d_mem);
+    }
+    for (auto& kv : plans) free_plan(kv.second);
+    if (d_work) (void)hipFree(d_work);
+}
+
+void uqc::free_plan(Plan& p) {
+    if (p.d_mem) (void)hipFree(p.d_mem);
+    p.d_mem = nullptr;
+}
+
+// Device arrays of a bin in one allocation: prim [kNumFields*K*np], AB [3*np], sdeg [np], off_a [np], off_b [np].
+static uqc_status upload_bin(Bin& b) {
+    const size_t np = b.np, K = b.K;
+    const size_t nd = kNumFields * K * np + 3 * np + np;
+    const size_t bytes = nd * sizeof(double) + 2 * np * sizeof(int);
+    if (!b.d_mem) {
+        if (hipMalloc(&b.d_mem, bytes) != hipSuccess) return uqc_fail(UQC_E_NOMEM, "basis: bin allocation failed");
+    }
+    std::vector<char> host(bytes);
+    double* hd = (double*)host.data();
+    std::memcpy(hd, b.prim.data(), kNumFields * K * np * sizeof(double));
+    std::memcpy(hd + kNumFields * K * np, b.AB.data(), 3 * np * sizeof(double));
+    std::memcpy(hd + kNumFields * K * np + 3 * np, b.sdeg.data(), np * sizeof(double));
+    int* hi = (int*)(hd + nd);
+    std::memcpy(hi, b.off_a.data(), np * sizeof(int));
+    std::memcpy(hi + np, b.off_b.data(), np * sizeof(int));
+    UQC_HIP(hipMemcpy(b.d_mem, host.data(), bytes, hipMemcpyHostToDevice));
+    double* dd = (double*)b.d_mem;
+    int* di = (int*)(dd + nd);
+    b.dev.prim = dd;
+    b.dev.AB = dd + kNumFields * K * np;
+    b.dev.sdeg = dd + kNumFields * K * np + 3 * np;
+    b.dev.off_a = di;
+    b.dev.off_b = di + np;
+    b.dev.np = (int)np;
+    b.dev.K = (int)K;
+    return UQC_OK;
+}
+
+// Reorders the host arrays of a bin by the permutation `perm` (new position i takes old perm[i]).
+static void permute_bin(Bin& b, const std::vector<int>& perm) {
+    const size_t np = b.np, K = b.K;
+    std::vector<double> prim(b.prim.size()), AB(b.AB.size()), sdeg(np), Q(np);
+    std::vector<int> oa(np), ob(np), sa(np), sb(np);
+    for (size_t i = 0; i < np; ++i) {
+        const size_t o = perm[i];
+        for (size_t f = 0; f < (size_t)kNumFields; ++f)
+            for (size_t k = 0; k < K; ++k) prim[(f * K + k) * np + i] = b.prim[(f * K + k) * np + o];
+        for (int x = 0; x < 3; ++x) AB[x * np + i] = b.AB[x * np + o];
+        sdeg[i] = b.sdeg[o];
+        Q[i] = b.Q[o];
+        oa[i] = b.off_a[o];
+        ob[i] = b.off_b[o];
+        sa[i] = b.sa[o];
+        sb[i] = b.sb[o];
+    }
+    b.prim.swap(prim);
+    b.AB.swap(AB);
+    b.sdeg.swap(sdeg);
+    b.Q.swap(Q);
+    b.off_a.swap(oa);
+    b.off_b.swap(ob);
+    b.sa.swap(sa);
+    b.sb.swap(sb);
+}
+
+uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* nprim, const double* center,
+                            const double* alpha, const double* coef, uqc_basis** out) {
+    if (!ctx || !out || !l || !nprim || !center || !alpha || !coef)
+        return uqc_fail(UQC_E_ARG, "uqc_basis_create: NULL argument");
+    *out = nullptr;
+    if (nshell <= 0) return uqc_fail(UQC_E_ARG, "uqc_basis_create: nshell must be positive");
+    size_t nprim_tot = 0;
+    for (int s = 0; s < nshell; ++s) {
+        if (l[s] < 0 || nprim[s] < 1) return uqc_fail(UQC_E_ARG, "uqc_basis_create: l < 0 or nprim < 1");
+        if (l[s] > 2) return uqc_fail(UQC_E_UNSUPPORTED, "uqc_basis_create: l > 2 is not supported");
+        if (nprim[s] > kMaxK) return uqc_fail(UQC_E_UNSUPPORTED, "uqc_basis_create: contraction depth > 16");
+        for (int x = 0; x < 3; ++x)
+            if (!std::isfinite(center[3 * s + x])) return uqc_fail(UQC_E_ARG, "uqc_basis_create: non-finite centre");
+        nprim_tot += nprim[s];
+    }
+    for (size_t p = 0; p < nprim_tot; ++p)
+        if (!(alpha[p] > 0) || !std::isfinite(alpha[p]) || !std::isfinite(coef[p]))
+            return uqc_fail(UQC_E_ARG, "uqc_basis_create: exponents must be positive and finite, coefficients finite");
+    UQC_HIP(hipSetDevice(ctx->device));
+
+    uqc_basis* B = new uqc_basis();
+    B->ctx = ctx;
+    B->nshell = nshell;
+    B->shells.resize(nshell);
+    const double pi = 3.14159265358979323846;
+    int off = 0;
+    size_t p = 0;
+    for (int s = 0; s < nshell; ++s) {
+        ShellH& sh = B->shells[s];
+        sh.l = l[s];
+        sh.K = nprim[s];
+        for (int x = 0; x < 3; ++x) sh.A[x] = center[3 * s + x];
+        sh.alpha.assign(alpha + p, alpha + p + sh.K);
+        // radial normalisation N_r(a) = (2a/pi)^{3/4} (4a)^{l/2}; contracted renormalisation from the self-overlap
+        // of the axis component, sum_pq d_p d_q N_r N_r (pi/g)^{3/2} / (2g)^l with g = a_p + a_q
+        std::vector<double> nr(sh.K);
+        for (int k = 0; k < sh.K; ++k)
+            nr[k] = std::pow(2.0 * sh.alpha[k] / pi, 0.75) * std::pow(4.0 * sh.alpha[k], 0.5 * sh.l);
+        double S = 0.0;
+        for (int i = 0; i < sh.K; ++i)
+            for (int j = 0; j < sh.K; ++j) {
+                const double g = sh.alpha[i] + sh.alpha[j];
+                S += coef[p + i] * coef[p + j] * nr[i] * nr[j] * std::pow(pi / g, 1.5) / std::pow(2.0 * g, sh.l);
+            }
+        if (!(S > 0) || !std::isfinite(S)) {
+            delete B;
+            return uqc_fail(UQC_E_ARG, "uqc_basis_create: contracted shell has zero or invalid norm");
+        }
+        sh.c.resize(sh.K);
+        for (int k = 0; k < sh.K; ++k) sh.c[k] = coef[p + k] * nr[k] / std::sqrt(S);
+        sh.off = off;
+        off += ncart(sh.l);
+        p += sh.K;
+    }
+    B->nbf = off;
+    B->fcomp.resize(B->nbf);
+    for (int s = 0; s < nshell; ++s)
+        for (int c = 0; c < ncart(B->shells[s].l); ++c)
+            B->fcomp[B->shells[s].off + c] = (B->shells[s].l == 2 && (c == 0 || c == 3 || c == 5))
+                                                 ? 0.57735026918962576451 : 1.0;
+
+    // shell pairs, oriented so that the first shell has the higher l (then the deeper contraction, then the larger
+    // index), binned by (l1, l2, K1, K2)
+    struct Key { int l1, l2, K1, K2; };
+    std::vector<Key> keys;
+    B->pair_bin.assign((size_t)nshell * nshell, -1);
+    B->pair_pos.assign((size_t)nshell * nshell, -1);
+    B->pair_first.assign((size_t)nshell * nshell, -1);
+    std::vector<std::vector<std::pair<int, int>>> members;
+    for (int a = 0; a < nshell; ++a)
+        for (int b = 0; b <= a; ++b) {
+            const ShellH &sa = B->shells[a], &sb = B->shells[b];
+            int f = a, s = b;
+            if (sb.l > sa.l || (sb.l == sa.l && (sb.K > sa.K || (sb.K == sa.K && b > a)))) { f = b; s = a; }
+            const ShellH &F = B->shells[f], &Sx = B->shells[s];
+            int bi = -1;
+            for (size_t k = 0; k < keys.size(); ++k)
+                if (keys[k].l1 == F.l && keys[k].l2 == Sx.l && keys[k].K1 == F.K && keys[k].K2 == Sx.K) bi = (int)k;
+            if (bi < 0) {
+                keys.push_back({F.l, Sx.l, F.K, Sx.K});
+                members.emplace_back();
+                bi = (int)keys.size() - 1;
+            }
+            members[bi].push_back({f, s});
+        }
+    // bin order: pair class, then K1, K2 (a class kernel (X|Y) needs class(X) >= class(Y) for X >= Y)
+    std::vector<int> order(keys.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+        const int px = pclass(keys[x].l1, keys[x].l2), py = pclass(keys[y].l1, keys[y].l2);
+        if (px != py) return px < py;
+        if (keys[x].K1 != keys[y].K1) return keys[x].K1 < keys[y].K1;
+        return keys[x].K2 < keys[y].K2;
+    });
+    B->bins.resize(keys.size());
+    for (size_t bo = 0; bo < order.size(); ++bo) {
+        const Key& k = keys[order[bo]];
+        Bin& bn = B->bins[bo];
+        bn.la = k.l1;
+        bn.lb = k.l2;
+        bn.Ka = k.K1;
+        bn.Kb = k.K2;
+        bn.K = k.K1 * k.K2;
+        const auto& mem = members[order[bo]];
+        bn.np = (int)mem.size();
+        const size_t np = bn.np, K = bn.K;
+        bn.prim.assign(kNumFields * K * np, 0.0);
+        bn.AB.assign(3 * np, 0.0);
+        bn.sdeg.assign(np, 1.0);
+        bn.Q.assign(np, 0.0);
+        bn.off_a.resize(np);
+        bn.off_b.resize(np);
+        bn.sa.resize(np);
+        bn.sb.resize(np);
+        for (size_t i = 0; i < np; ++i) {
+            const ShellH& A = B->shells[mem[i].first];
+            const ShellH& Bs = B->shells[mem[i].second];
+            bn.sa[i] = mem[i].first;
+            bn.sb[i] = mem[i].second;
+            bn.off_a[i] = A.off;
+            bn.off_b[i] = Bs.off;
+            bn.sdeg[i] = (mem[i].first == mem[i].second) ? 0.5 : 1.0;
+            double AB[3], AB2 = 0.0;
+            for (int x = 0; x < 3; ++x) {
+                AB[x] = A.A[x] - Bs.A[x];
+                AB2 += AB[x] * AB[x];
+                bn.AB[x * np + i] = AB[x];
+            }
+            const double c0 = std::sqrt(2.0) * std::pow(pi, 1.25);
+            for (int ia = 0; ia < A.K; ++ia)
+                for (int ib = 0; ib < Bs.K; ++ib) {
+                    const size_t kk = (size_t)ia * Bs.K + ib;
+                    const double al = A.alpha[ia], be = Bs.alpha[ib];
+                    const double z = al + be;
+                    auto put = [&](int f, double v) { bn.prim[((size_t)f * K + kk) * np + i] = v; };
+                    put(F_Z, z);
+                    double P[3];
+                    for (int x = 0; x < 3; ++x) P[x] = (al * A.A[x] + be * Bs.A[x]) / z;
+                    put(F_PX, P[0]);
+                    put(F_PY, P[1]);
+                    put(F_PZ, P[2]);
+                    put(F_PAX, P[0] - A.A[0]);
+                    put(F_PAY, P[1] - A.A[1]);
+                    put(F_PAZ, P[2] - A.A[2]);
+                    put(F_PREF, A.c[ia] * Bs.c[ib] * std::exp(-al * be / z * AB2) * c0 / z);
+                    put(F_O2Z, 0.5 / z);
+                }
+        }
+        uqc_status st = upload_bin(bn);
+        if (st != UQC_OK) { delete B; return st; }
+    }
+
+    // Schwarz bounds on the GPU: diagonal quartets (ab|ab) of every bin
+    {
+        size_t maxnp = 0;
+        for (auto& bn : B->bins) maxnp = std::max(maxnp, (size_t)bn.np);
+        void* tmp = nullptr;
+        if (hipMalloc(&tmp, maxnp * (2 * sizeof(int) + sizeof(double))) != hipSuccess) {
+            delete B;
+            return uqc_fail(UQC_E_NOMEM, "basis: Schwarz scratch allocation failed");
+        }
+        std::vector<int> idx(maxnp);
+        std::iota(idx.begin(), idx.end(), 0);
+        int* didx = (int*)tmp;
+        double* dq = (double*)(didx + 2 * maxnp);
+        uqc_status st = UQC_OK;
+        if (hipMemcpy(didx, idx.data(), maxnp * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+            st = uqc_fail(UQC_E_DEVICE, "basis: upload failed");
+        for (size_t bi = 0; bi < B->bins.size() && st == UQC_OK; ++bi) {
+            Bin& bn = B->bins[bi];
+            ListDev L;
+            L.bra = bn.dev;
+            L.ket = bn.dev;
+            L.bra_idx = didx;
+            L.ket_idx = didx;
+            L.n = bn.np;
+            L.out = dq;
+            const int cls = class_index(bn.la, bn.lb, bn.la, bn.lb);
+            if (launch_list(cls, false, MODE_SCHWARZ, L, ctx->boys64, ctx->boys32, ctx->stream) != hipSuccess ||
+                hipMemcpyAsync(bn.Q.data(), dq, bn.np * sizeof(double), hipMemcpyDeviceToHost, ctx->stream) !=
+                    hipSuccess ||
+                hipStreamSynchronize(ctx->stream) != hipSuccess)
+                st = uqc_fail(UQC_E_DEVICE, "basis: Schwarz kernel failed");
+        }
+        (void)hipFree(tmp);
+        if (st != UQC_OK) { delete B; return st; }
+    }
+    // sort each bin by bound (descending) and re-upload; record where every shell pair landed
+    B->Qfull.assign((size_t)nshell * nshell, 0.0);
+    for (size_t bi = 0; bi < B->bins.size(); ++bi) {
+        Bin& bn = B->bins[bi];
+        std::vector<int> perm(bn.np);
+        std::iota(perm.begin(), perm.end(), 0);
+        std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return bn.Q[x] > bn.Q[y]; });
+        permute_bin(bn, perm);
+        uqc_status st = upload_bin(bn);
+        if (st != UQC_OK) { delete B; return st; }
+        for (int i = 0; i < bn.np; ++i) {
+            const int a = bn.sa[i], b = bn.sb[i];
+            for (auto key : {(size_t)a * nshell + b, (size_t)b * nshell + a}) {
+                B->pair_bin[key] = (int)bi;
+                B->pair_pos[key] = i;
+                B->pair_first[key] = a;
+            }
+            B->Qfull[(size_t)a * nshell + b] = B->Qfull[(size_t)b * nshell + a] = bn.Q[i];
+        }
+        B->qmax = std::max(B->qmax, bn.np ? bn.Q[0] : 0.0);
+    }
+    // workspace: f[nbf], D', J, K accumulators, E2 + symmetry scalars, host-pointer staging for D, J, K, G
+    {
+        const size_t N = B->nbf, NN = N * N;
+        const size_t bytes = (N + 3 * NN + 8 + 4 * NN) * sizeof(double);
+        if (hipMalloc(&B->d_work, bytes) != hipSuccess) {
+            delete B;
+            return uqc_fail(UQC_E_NOMEM, "basis: workspace allocation failed");
+        }
+        double* w = (double*)B->d_work;
+        B->d_f = w;
+        B->d_Dp = w + N;
+        B->d_J = B->d_Dp + NN;
+        B->d_K = B->d_J + NN;
+        B->d_scal = B->d_K + NN;
+        B->d_io = B->d_scal + 8;
+        B->work_bytes = bytes;
+        if (hipMemcpy(B->d_f, B->fcomp.data(), N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+            delete B;
+            return uqc_fail(UQC_E_DEVICE, "basis: upload failed");
+        }
+    }
+    *out = B;
+    return UQC_OK;
+}
+
+uqc_status uqc_basis_destroy(uqc_basis* b) {
+    if (!b) return uqc_fail(UQC_E_ARG, "uqc_basis_destroy: NULL basis");
+    (void)hipStreamSynchronize(b->ctx->stream);
+    delete b;
+    return UQC_OK;
+}
+
+uqc_status uqc_basis_info(const uqc_basis* b, int* nbf, int* shell_offset) {
+    if (!b) return uqc_fail(UQC_E_ARG, "uqc_basis_info: NULL basis");
+    if (nbf) *nbf = b->nbf;
+    if (shell_offset)
+        for (int s = 0; s < b->nshell; ++s) shell_offset[s] = b->shells[s].off;
+    return UQC_OK;
+}
+
+uqc_status uqc_schwarz(const uqc_basis* b, double* Q) {
+    if (!b || !Q) return uqc_fail(UQC_E_ARG, "uqc_schwarz: NULL argument");
+    std::memcpy(Q, b->Qfull.data(), b->Qfull.size() * sizeof(double));
+    return UQC_OK;
+}
+
+// ---------------------------------------------------------------------------------------------- screened plan
+// For every bin pair (X >= Y) the canonical quartets are, per bra pair i of X, the kets j of Y with
+// Q_i Q_j >= tau (a prefix, Y being sorted by bound) and, if X == Y, j <= i.  In mixed precision the prefix with
+// Q_i Q_j > bound forms the FP64 task, the rest the FP32-recursion task.
+Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st) {
+    for (auto& kv : B->plans)
+        if (kv.first.tau == tau && kv.first.prec == prec && (prec == UQC_FP64 || kv.first.bound == bound))
+            return &kv.second;
+    PlanKey key{tau, prec, prec == UQC_FP64 ? 0.0 : bound};
+    Plan plan;
+    struct HostTask {
+        int cls, mixed, X, Y, same;
+        std::vector<int> lo, hi;
+        std::vector<long long> off;
+        long long nitems, quartets, prim;
+    };
+    std::vector<HostTask> tasks;
+    const int nb = (int)B->bins.size();
+    long long total_canonical = 0;
+    {
+        const long long npair = (long long)B->nshell * (B->nshell + 1) / 2;
+        total_canonical = npair * (npair + 1) / 2;
+    }
+    long long kept = 0;
+    for (int X = 0; X < nb; ++X)
+        for (int Y = 0; Y <= X; ++Y) {
+            const Bin &bx = B->bins[X], &by = B->bins[Y];
+            const int cls = class_index(bx.la, bx.lb, by.la, by.lb);
+            HostTask t64{cls, 0, X, Y, X == Y, {}, {}, {}, 0, 0, 0};
+            HostTask t32{cls, 1, X, Y, X == Y, {}, {}, {}, 0, 0, 0};
+            for (int i = 0; i < bx.np; ++i) {
+                const double qi = bx.Q[i];
+                auto count_if_prefix = [&](auto pred) {
+                    int lo = 0, hi = by.np;  // first j where pred fails
+                    while (lo < hi) {
+                        const int mid = (lo + hi) / 2;
+                        if (pred(by.Q[mid])) lo = mid + 1; else hi = mid;
+                    }
+                    return lo;
+                };
+                int h = tau > 0 ? count_if_prefix([&](double qj) { return qi * qj >= tau; }) : by.np;
+                if (X == Y) h = std::min(h, i + 1);
+                int n64 = h;
+                if (prec == UQC_MIXED) n64 = std::min(h, count_if_prefix([&](double qj) { return qi * qj > bound; }));
+                t64.lo.push_back(0);
+                t64.hi.push_back(n64);
+                t32.lo.push_back(n64);
+                t32.hi.push_back(h);
+                kept += h;
+            }
+            for (HostTask* t : {&t64, &t32}) {
+                if (t->mixed && prec != UQC_MIXED) continue;
+                t->off.resize(bx.np + 1);
+                long long acc = 0, q = 0;
+                for (int i = 0; i < bx.np; ++i) {
+                    t->off[i] = acc;
+                    const int n = t->hi[i] - t->lo[i];
+                    acc += (n + kWave - 1) / kWave;
+                    q += n;
+                }
+                t->off[bx.np] = acc;
+                t->nitems = acc;
+                t->quartets = q;
+                t->prim = q * (long long)bx.K * by.K;
+                if (q > 0) tasks.push_back(std::move(*t));
+            }
+        }
+    plan.quartets = kept;
+    plan.screened = total_canonical - kept;
+    // group tasks into one launch per (class, precision)
+    std::vector<std::pair<int, int>> gkeys;
+    for (auto& t : tasks) {
+        std::pair<int, int> k{t.cls, t.mixed};
+        if (std::find(gkeys.begin(), gkeys.end(), k) == gkeys.end()) gkeys.push_back(k);
+    }
+    std::sort(gkeys.begin(), gkeys.end());
+    // device memory: per task lo/hi/off; per group TaskDev array + task_begin
+    size_t bytes = 0;
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    for (auto& t : tasks) {
+        const size_t n = B->bins[t.X].np;
+        bytes += align(n * sizeof(int)) * 2 + align((n + 1) * sizeof(long long));
+    }
+    for (size_t g = 0; g < gkeys.size(); ++g) bytes += align(tasks.size() * sizeof(TaskDev)) + align(tasks.size() * 8);
+    std::vector<char> host(bytes);
+    if (hipMalloc(&plan.d_mem, std::max(bytes, (size_t)256)) != hipSuccess) {
+        *st = uqc_fail(UQC_E_NOMEM, "plan: allocation failed");
+        return nullptr;
+    }
+    char* dbase = (char*)plan.d_mem;
+    size_t pos = 0;
+    std::vector<TaskDev> tdev(tasks.size());
+    for (size_t ti = 0; ti < tasks.size(); ++ti) {
+        auto& t = tasks[ti];
+        const size_t n = B->bins[t.X].np;
+        std::memcpy(host.data() + pos, t.lo.data(), n * sizeof(int));
+        const int* dlo = (const int*)(dbase + pos);
+        pos += align(n * sizeof(int));
+        std::memcpy(host.data() + pos, t.hi.data(), n * sizeof(int));
+        const int* dhi = (const int*)(dbase + pos);
+        pos += align(n * sizeof(int));
+        std::memcpy(host.data() + pos, t.off.data(), (n + 1) * sizeof(long long));
+        const long long* doff = (const long long*)(dbase + pos);
+        pos += align((n + 1) * sizeof(long long));
+        TaskDev& d = tdev[ti];
+        d.bra = B->bins[t.X].dev;
+        d.ket = B->bins[t.Y].dev;
+        d.lo = dlo;
+        d.hi = dhi;
+        d.item_off = doff;
+        d.item_begin = 0;
+        d.nitems = t.nitems;
+        d.nbra = (int)n;
+        d.same = t.same;
+        d.D = B->d_Dp;
+        d.J = B->d_J;
+        d.K = B->d_K;
+        d.nbf = B->nbf;
+    }
+    for (auto& gk : gkeys) {
+        LaunchGroup G;
+        G.cls = gk.first;
+        G.mixed = gk.second;
+        std::vector<TaskDev> gt;
+        std::vector<long long> begin;
+        long long items = 0;
+        for (size_t ti = 0; ti < tasks.size(); ++ti) {
+            if (tasks[ti].cls != gk.first || tasks[ti].mixed != gk.second) continue;
+            TaskDev d = tdev[ti];
+            d.item_begin = items;
+            begin.push_back(items);
+            items += d.nitems;
+            gt.push_back(d);
+            G.quartets += tasks[ti].quartets;
+            G.prim_quartets += tasks[ti].prim;
+        }
+        G.ntask = (int)gt.size();
+        G.nitems = items;
+        std::memcpy(host.data() + pos, gt.data(), gt.size() * sizeof(TaskDev));
+        G.d_tasks = (const TaskDev*)(dbase + pos);
+        pos += align(tasks.size() * sizeof(TaskDev));
+        std::memcpy(host.data() + pos, begin.data(), begin.size() * sizeof(long long));
+        G.d_begin = (const long long*)(dbase + pos);
+        pos += align(tasks.size() * 8);
+        G.flops = (double)G.prim_quartets * class_flops_prim(G.cls) + (double)G.quartets * class_flops_contr(G.cls);
+        G.host_tasks = gt;
+        G.host_begin = begin;
+        plan.prim_quartets += G.prim_quartets;
+        if (!G.mixed) plan.fp64_quartets += G.quartets;
+        plan.flops += G.flops;
+        plan.groups.push_back(G);
+    }
+    if (bytes && hipMemcpy(plan.d_mem, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        free_plan(plan);
+        *st = uqc_fail(UQC_E_DEVICE, "plan: upload failed");
+        return nullptr;
+    }
+    B->plans.push_back({key, plan});
+    return &B->plans.back().second;
+}
+
+// ---------------------------------------------------------------------------------------------- ERI blocks
+static bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+uqc_status uqc_eri_blocks(uqc_basis* B, int n, const int* q, int precision, double* out) {
+    if (!B || (n > 0 && (!q || !out))) return uqc_fail(UQC_E_ARG, "uqc_eri_blocks: NULL argument");
+    if (n < 0) return uqc_fail(UQC_E_ARG, "uqc_eri_blocks: negative count");
+    if (precision != UQC_FP64 && precision != UQC_MIXED) return uqc_fail(UQC_E_ARG, "uqc_eri_blocks: bad precision");
+    if (n == 0) return UQC_OK;
+    const int ns = B->nshell;
+    struct Item {
+        int cls, bra_bin, ket_bin, bra, ket;
+        int slot[4];   // kernel slot (0..3 = first/second of bra, first/second of ket) of requested shell 0..3
+        size_t out_off;
+        int dims[4];   // component counts of the kernel slots
+    };
+    std::vector<Item> items(n);
+    size_t total_out = 0;
+    for (int x = 0; x < n; ++x) {
+        int s[4];
+        for (int y = 0; y < 4; ++y) {
+            s[y] = q[4 * x + y];
+            if (s[y] < 0 || s[y] >= ns) return uqc_fail(UQC_E_ARG, "uqc_eri_blocks: shell index out of range");
+        }
+        const size_t k1 = (size_t)s[0] * ns + s[1], k2 = (size_t)s[2] * ns + s[3];
+        int b1 = B->pair_bin[k1], b2 = B->pair_bin[k2];
+        const bool swap_bk = b1 < b2;  // the pair with the higher bin is the bra
+        Item& it = items[x];
+        const size_t kb = swap_bk ? k2 : k1, kk = swap_bk ? k1 : k2;
+        it.bra_bin = B->pair_bin[kb];
+        it.ket_bin = B->pair_bin[kk];
+        it.bra = B->pair_pos[kb];
+        it.ket = B->pair_pos[kk];
+        const Bin &bb = B->bins[it.bra_bin], &kb_ = B->bins[it.ket_bin];
+        it.cls = class_index(bb.la, bb.lb, kb_.la, kb_.lb);
+        // requested slots 0,1 form pair k1; slots 2,3 pair k2
+        const int base1 = swap_bk ? 2 : 0, base2 = swap_bk ? 0 : 2;
+        const int first1 = B->pair_first[k1], first2 = B->pair_first[k2];
+        it.slot[0] = base1 + (s[0] == first1 ? 0 : 1);
+        it.slot[1] = base1 + (s[0] == first1 ? 1 : 0);
+        if (s[0] == s[1]) { it.slot[0] = base1; it.slot[1] = base1 + 1; }
+        it.slot[2] = base2 + (s[2] == first2 ? 0 : 1);
+        it.slot[3] = base2 + (s[2] == first2 ? 1 : 0);
+        if (s[2] == s[3]) { it.slot[2] = base2; it.slot[3] = base2 + 1; }
+        it.dims[0] = ncart(bb.la);
+        it.dims[1] = ncart(bb.lb);
+        it.dims[2] = ncart(kb_.la);
+        it.dims[3] = ncart(kb_.lb);
+        it.out_off = total_out;
+        total_out += (size_t)it.dims[0] * it.dims[1] * it.dims[2] * it.dims[3];
+    }
+    uqc_ctx* ctx = B->ctx;
+    UQC_HIP(hipSetDevice(ctx->device));
+    // one launch per (class, bra bin, ket bin)
+    std::vector<int> ord(n);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+        const Item &x = items[a], &y = items[b];
+        if (x.bra_bin != y.bra_bin) return x.bra_bin < y.bra_bin;
+        return x.ket_bin < y.ket_bin;
+    });
+    void* dmem = nullptr;
+    const size_t bytes = total_out * sizeof(double) + 2 * (size_t)n * sizeof(int) + 256;
+    if (hipMalloc(&dmem, bytes) != hipSuccess) return uqc_fail(UQC_E_NOMEM, "uqc_eri_blocks: allocation failed");
+    double* dout = (double*)dmem;
+    int* didx = (int*)(dout + total_out);
+    // kernel output is grouped by launch; keep the device offset of each item
+    std::vector<int> hidx(2 * (size_t)n);
+    std::vector<size_t> dev_off(n);
+    size_t dpos = 0;
+    struct Launch { int cls, bra_bin, ket_bin, first, count; size_t out; };
+    std::vector<Launch> launches;
+    for (int r = 0; r < n;) {
+        const Item& it0 = items[ord[r]];
+        int e = r;
+        Launch L{it0.cls, it0.bra_bin, it0.ket_bin, r, 0, dpos};
+        while (e < n && items[ord[e]].bra_bin == it0.bra_bin && items[ord[e]].ket_bin == it0.ket_bin) {
+            const Item& it = items[ord[e]];
+            hidx[e] = it.bra;
+            hidx[n + e] = it.ket;
+            dev_off[ord[e]] = dpos;
+            dpos += (size_t)it.dims[0] * it.dims[1] * it.dims[2] * it.dims[3];
+            ++e;
+        }
+        L.count = e - r;
+        launches.push_back(L);
+        r = e;
+    }
+    uqc_status st = UQC_OK;
+    if (hipMemcpyAsync(didx, hidx.data(), 2 * (size_t)n * sizeof(int), hipMemcpyHostToDevice, ctx->stream) !=
+        hipSuccess)
+        st = uqc_fail(UQC_E_DEVICE, "uqc_eri_blocks: upload failed");
+    for (auto& L : launches) {
+        if (st != UQC_OK) break;
+        ListDev ld;
+        ld.bra = B->bins[L.bra_bin].dev;
+        ld.ket = B->bins[L.ket_bin].dev;
+        ld.bra_idx = didx + L.first;
+        ld.ket_idx = didx + n + L.first;
+        ld.n = L.count;
+        ld.out = dout + L.out;
+        if (launch_list(L.cls, precision == UQC_MIXED, MODE_STORE, ld, ctx->boys64, ctx->boys32, ctx->stream) !=
+            hipSuccess)
+            st = uqc_fail(UQC_E_DEVICE, "uqc_eri_blocks: kernel launch failed");
+    }
+    std::vector<double> hout(total_out);
+    if (st == UQC_OK && (hipMemcpyAsync(hout.data(), dout, total_out * sizeof(double), hipMemcpyDeviceToHost,
+                                        ctx->stream) != hipSuccess ||
+                         hipStreamSynchronize(ctx->stream) != hipSuccess))
+        st = uqc_fail(UQC_E_DEVICE, "uqc_eri_blocks: kernel or copy failed");
+    (void)hipFree(dmem);
+    if (st != UQC_OK) return st;
+    // permute every block into the requested (a, b, c, d) order
+    for (int x = 0; x < n; ++x) {
+        const Item& it = items[x];
+        const double* src = hout.data() + dev_off[x];
+        double* dst = out + it.out_off;
+        int rd[4];
+        for (int y = 0; y < 4; ++y) rd[y] = it.dims[it.slot[y]];
+        int idx[4];
+        for (int i = 0; i < rd[0]; ++i)
+            for (int j = 0; j < rd[1]; ++j)
+                for (int k = 0; k < rd[2]; ++k)
+                    for (int l = 0; l < rd[3]; ++l) {
+                        idx[it.slot[0]] = i;
+                        idx[it.slot[1]] = j;
+                        idx[it.slot[2]] = k;
+                        idx[it.slot[3]] = l;
+                        const size_t s = ((size_t)(idx[0] * it.dims[1] + idx[1]) * it.dims[2] + idx[2]) * it.dims[3] +
+                                         idx[3];
+                        *dst++ = src[s];
+                    }
+    }
+    return UQC_OK;
+}
+
+uqc_status uqc_eri_block(uqc_basis* B, int a, int b, int c, int d, int precision, double* out) {
+    const int q[4] = {a, b, c, d};
+    return uqc_eri_blocks(B, 1, q, precision, out);
+}
+
+// ---------------------------------------------------------------------------------------------- Fock build
+uqc_status uqc_fock_build(uqc_basis* B, const double* D, double* J, double* K, double* G, const uqc_fock_opts* opts,
+                          uqc_stats* stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!B || !D) return uqc_fail(UQC_E_ARG, "uqc_fock_build: NULL basis or density");
+    uqc_fock_opts o;
+    uqc_fock_opts_default(&o);
+    if (opts) o = *opts;
+    if (!(o.schwarz_tau >= 0) || !std::isfinite(o.schwarz_tau)) return uqc_fail(UQC_E_ARG, "uqc_fock_build: bad tau");
+    if (o.precision != UQC_FP64 && o.precision != UQC_MIXED)
+        return uqc_fail(UQC_E_ARG, "uqc_fock_build: bad precision");
+    if (o.precision == UQC_MIXED && !(o.fp64_bound >= 0)) return uqc_fail(UQC_E_ARG, "uqc_fock_build: bad fp64_bound");
+    uqc_ctx* ctx = B->ctx;
+    UQC_HIP(hipSetDevice(ctx->device));
+    const bool dev = is_device_ptr(D);
+    for (const void* p : {(const void*)J, (const void*)K, (const void*)G})
+        if (p && is_device_ptr(p) != dev)
+            return uqc_fail(UQC_E_ARG, "uqc_fock_build: mix of host and device pointers");
+    uqc_status st = UQC_OK;
+    Plan* plan = get_plan(B, o.schwarz_tau, o.precision, o.fp64_bound, &st);
+    if (!plan) return st;
+    const size_t N = B->nbf, NN = N * N;
+    hipStream_t s = ctx->stream;
+    const double* Dd = D;
+    double *Jd = J, *Kd = K, *Gd = G;
+    if (!dev) {
+        double* io = B->d_io;
+        UQC_HIP(hipMemcpyAsync(io, D, NN * sizeof(double), hipMemcpyHostToDevice, s));
+        Dd = io;
+        Jd = J ? io + NN : nullptr;
+        Kd = K ? io + 2 * NN : nullptr;
+        Gd = G ? io + 3 * NN : nullptr;
+    }
+    unsigned long long* maxbits = (unsigned long long*)(B->d_scal + 1);
+    UQC_HIP(launch_zero(B->d_scal, 8, s));
+    UQC_HIP(launch_prepare(Dd, B->d_f, B->d_Dp, (int)N, maxbits, s));
+    unsigned long long hb[2] = {0, 0};
+    UQC_HIP(hipMemcpyAsync(hb, maxbits, sizeof(hb), hipMemcpyDeviceToHost, s));
+    UQC_HIP(hipStreamSynchronize(s));
+    double md, ma;
+    std::memcpy(&md, &hb[0], 8);
+    std::memcpy(&ma, &hb[1], 8);
+    if (!(md <= 1e-12 * ma)) return uqc_fail(UQC_E_NOT_SYMMETRIC, "uqc_fock_build: density is not symmetric (or not finite)");
+    UQC_HIP(launch_zero(B->d_J, 2 * NN, s));
+    const bool timing = o.timing != 0;
+    size_t ev = 0;
+    for (auto& g : plan->groups) {
+        if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, ev++), s));
+        UQC_HIP(launch_digest(g.cls, g.mixed, g.d_tasks, g.d_begin, g.ntask, g.nitems, ctx->boys64, ctx->boys32, s));
+        if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, ev++), s));
+    }
+    UQC_HIP(launch_finalize(Dd, B->d_J, B->d_K, B->d_f, Jd, Kd, Gd, B->d_scal, (int)N, s));
+    double E2 = 0.0;
+    UQC_HIP(hipMemcpyAsync(&E2, B->d_scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (!dev) {
+        if (J) UQC_HIP(hipMemcpyAsync(J, Jd, NN * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (K) UQC_HIP(hipMemcpyAsync(K, Kd, NN * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (G) UQC_HIP(hipMemcpyAsync(G, Gd, NN * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    UQC_HIP(hipStreamSynchronize(s));
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->E2 = E2;
+        stats->quartets = plan->quartets;
+        stats->quartets_screened = plan->screened;
+        stats->prim_quartets = plan->prim_quartets;
+        stats->fp64_quartets = plan->fp64_quartets;
+        stats->flops = plan->flops;
+        if (timing) {
+            size_t e = 0;
+            int nc = 0;
+            for (auto& g : plan->groups) {
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, ctx->events[e], ctx->events[e + 1]);
+                e += 2;
+                stats->eri_ms += ms;
+                if (nc < UQC_MAX_CLASS_STATS) {
+                    int la, lb, lc, ld;
+                    class_ls(g.cls, &la, &lb, &lc, &ld);
+                    stats->class_id[nc] = la * 1000 + lb * 100 + lc * 10 + ld + (g.mixed ? 10000 : 0);
+                    stats->class_ms[nc] = ms;
+                    stats->class_flops[nc] = g.flops;
+                    stats->class_quartets[nc] = g.quartets;
+                    ++nc;
+                }
+            }
+            stats->nclass = nc;
+        }
+        stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return UQC_OK;
+}
+
+// ---------------------------------------------------------------------------------------------- Boys check
+uqc_status uqc_boys(uqc_ctx* ctx, int precision, int mmax, int n, const double* T, double* out) {
+    if (!ctx || (n > 0 && (!T || !out))) return uqc_fail(UQC_E_ARG, "uqc_boys: NULL argument");
+    if (mmax < 0 || mmax > 8 || n < 0) return uqc_fail(UQC_E_ARG, "uqc_boys: mmax must be 0..8, n >= 0");
+    if (precision != UQC_FP64 && precision != UQC_MIXED) return uqc_fail(UQC_E_ARG, "uqc_boys: bad precision");
+    for (int i = 0; i < n; ++i)
+        if (!(T[i] >= 0) || !std::isfinite(T[i])) return uqc_fail(UQC_E_ARG, "uqc_boys: T must be finite and >= 0");
+    if (n == 0) return UQC_OK;
+    UQC_HIP(hipSetDevice(ctx->device));
+    double* d = nullptr;
+    const size_t m = (size_t)mmax + 1;
+    if (hipMalloc(&d, (size_t)n * (1 + m) * sizeof(double)) != hipSuccess)
+        return uqc_fail(UQC_E_NOMEM, "uqc_boys: allocation failed");
+    uqc_status st = UQC_OK;
+    if (hipMemcpyAsync(d, T, n * sizeof(double), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        launch_boys(precision, mmax, n, d, d + n, ctx->boys64, ctx->boys32, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(out, d + n, (size_t)n * m * sizeof(double), hipMemcpyDeviceToHost, ctx->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        st = uqc_fail(UQC_E_DEVICE, "uqc_boys: kernel or copy failed");
+    (void)hipFree(d);
+    return st;
+}

@@ -1,0 +1,92 @@
+// Host-side objects behind the opaque handles of include/uqc.h.
+#pragma once
+#include "../../include/uqc.h"
+#include "uqc_internal.h"
+
+#include <list>
+#include <string>
+#include <utility>
+#include <vector>
+
+uqc_status uqc_fail(uqc_status s, const std::string& msg);
+
+#define UQC_HIP(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            return uqc_fail(UQC_E_DEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct uqc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    double* boys64 = nullptr;
+    float* boys32 = nullptr;
+    std::vector<hipEvent_t> events;
+};
+
+hipEvent_t ctx_event(uqc_ctx* c, size_t i);
+
+namespace uqc {
+
+struct ShellH {
+    int l = 0, K = 0, off = 0;
+    double A[3] = {0, 0, 0};
+    std::vector<double> alpha, c;  // exponents; coefficients with radial and contracted normalisation folded in
+};
+
+struct Bin {
+    int la = 0, lb = 0, Ka = 0, Kb = 0, K = 0, np = 0;
+    std::vector<double> prim, AB, sdeg, Q;
+    std::vector<int> off_a, off_b, sa, sb;
+    void* d_mem = nullptr;
+    BinDev dev{};
+};
+
+struct LaunchGroup {
+    int cls = 0;
+    int mixed = 0;
+    int ntask = 0;
+    long long nitems = 0, quartets = 0, prim_quartets = 0;
+    double flops = 0;
+    const TaskDev* d_tasks = nullptr;
+    const long long* d_begin = nullptr;
+    std::vector<TaskDev> host_tasks;   // copies (device pointers inside), used to batch several bases
+    std::vector<long long> host_begin;
+};
+
+struct PlanKey {
+    double tau;
+    int prec;
+    double bound;
+};
+
+struct Plan {
+    std::vector<LaunchGroup> groups;
+    long long quartets = 0, screened = 0, prim_quartets = 0, fp64_quartets = 0;
+    double flops = 0;
+    void* d_mem = nullptr;
+};
+
+void free_plan(Plan& p);
+
+}  // namespace uqc
+
+struct uqc_basis {
+    uqc_ctx* ctx = nullptr;
+    int nshell = 0, nbf = 0;
+    std::vector<uqc::ShellH> shells;
+    std::vector<double> fcomp;
+    std::vector<uqc::Bin> bins;
+    std::vector<int> pair_bin, pair_pos, pair_first;  // [a * nshell + b]
+    std::vector<double> Qfull;
+    double qmax = 0;
+    std::list<std::pair<uqc::PlanKey, uqc::Plan>> plans;  // list: plan pointers stay valid
+    void* d_work = nullptr;
+    size_t work_bytes = 0;
+    double *d_f = nullptr, *d_Dp = nullptr, *d_J = nullptr, *d_K = nullptr, *d_scal = nullptr, *d_io = nullptr;
+    ~uqc_basis();
+};
+
+uqc::Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st);

@@ -1,0 +1,85 @@
+// Device building blocks shared by the libuqc kernels: Boys function, wavefront reductions, Cartesian component
+// scale factors.
+#pragma once
+#include "uqc_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <cmath>
+
+namespace uqc {
+
+// Cartesian component scale relative to the axis component: 1/sqrt((2lx-1)!!(2ly-1)!!(2lz-1)!!).  Only d shells
+// have two values: xx, yy, zz (components 0, 3, 5) carry 1/sqrt(3).
+__host__ __device__ constexpr double comp_factor(int l, int c) {
+    return (l == 2 && (c == 0 || c == 3 || c == 5)) ? 0.57735026918962576451 : 1.0;
+}
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ------------------------------------------------------------------------------------------------ Boys function
+// F_m(T) = int_0^1 t^{2m} exp(-T t^2) dt.  For T < 40: Taylor series of order 7 around the nearest grid point
+// T_g = g/10 (|T - T_g| <= 0.05, truncation error < 1e-15 relative), using dF_m/dT = -F_{m+1}, for the highest order
+// needed, then the downward recursion F_m = (2T F_{m+1} + exp(-T)) / (2m+1).  For T >= 40: F_0 = sqrt(pi/T)/2
+// (erf(sqrt(T)) = 1 to double precision) and the upward recursion F_{m+1} = ((2m+1) F_m - exp(-T)) / (2T).
+template <int L>
+__device__ __forceinline__ void boys64(double T, const double* __restrict__ tab, double* F) {
+    if (T < (double)kBoysTmax) {
+        const int g = (int)(T * (double)kBoysGridPerUnit + 0.5);
+        const double d = (double)g * 0.1 - T;
+        const double* r = tab + g * kBoysNm + L;
+        double p = r[7];
+        p = fma(p, d * (1.0 / 7.0), r[6]);
+        p = fma(p, d * (1.0 / 6.0), r[5]);
+        p = fma(p, d * (1.0 / 5.0), r[4]);
+        p = fma(p, d * (1.0 / 4.0), r[3]);
+        p = fma(p, d * (1.0 / 3.0), r[2]);
+        p = fma(p, d * (1.0 / 2.0), r[1]);
+        p = fma(p, d, r[0]);
+        F[L] = p;
+        if constexpr (L > 0) {
+            const double e = exp(-T);
+            const double t2 = T + T;
+#pragma unroll
+            for (int m = L - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (2 * m + 1));
+        }
+    } else {
+        const double it = 1.0 / T;
+        F[0] = 0.5 * sqrt(kPi * it);
+        if constexpr (L > 0) {
+            const double e = exp(-T);
+            const double h = 0.5 * it;
+#pragma unroll
+            for (int m = 0; m < L; ++m) F[m + 1] = fma((double)(2 * m + 1), F[m], -e) * h;
+        }
+    }
+}
+
+// FP32 variant (mixed mode, T <= 30 only): Taylor order 4 around the same grid (truncation < 3e-9 relative).
+template <int L>
+__device__ __forceinline__ void boys32(float T, const float* __restrict__ tab, float* F) {
+    const int g = (int)(T * (float)kBoysGridPerUnit + 0.5f);
+    const float d = (float)g * 0.1f - T;
+    const float* r = tab + g * kBoysNm + L;
+    float p = r[4];
+    p = fmaf(p, d * 0.25f, r[3]);
+    p = fmaf(p, d * (1.0f / 3.0f), r[2]);
+    p = fmaf(p, d * 0.5f, r[1]);
+    p = fmaf(p, d, r[0]);
+    F[L] = p;
+    if constexpr (L > 0) {
+        const float e = expf(-T);
+        const float t2 = T + T;
+#pragma unroll
+        for (int m = L - 1; m >= 0; --m) F[m] = fmaf(t2, F[m + 1], e) * (1.0f / (2 * m + 1));
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+
+__device__ __forceinline__ void atomic_add(double* p, double v) { (void)unsafeAtomicAdd(p, v); }
+
+}  // namespace uqc

@@ -1,0 +1,47 @@
+// One angular-momentum class of the quartet kernels: compiled once per class with
+// -DUQC_CLASS_ID=n -DUQC_LA=.. -DUQC_LB=.. -DUQC_LC=.. -DUQC_LD=.. so that the classes build in parallel.
+#include "uqc_eri_impl.h"
+
+#if !defined(UQC_CLASS_ID) || !defined(UQC_LA) || !defined(UQC_LB) || !defined(UQC_LC) || !defined(UQC_LD)
+#error "uqc_eri_class.hip needs UQC_CLASS_ID and UQC_LA..UQC_LD"
+#endif
+
+#define UQC_CAT2(a, b) a##b
+#define UQC_CAT(a, b) UQC_CAT2(a, b)
+
+namespace uqc {
+
+static hipError_t launch_digest_cls(bool mixed, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
+                                    long long nitems, const double* b64, const float* b32, hipStream_t s) {
+    const long long waves_per_block = kBlock / kWave;
+    const long long nblocks = (nitems + waves_per_block - 1) / waves_per_block;
+    if (nblocks <= 0) return hipSuccess;
+    if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (mixed)
+        hipLaunchKernelGGL((k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, true>), dim3((unsigned)nblocks), dim3(kBlock), 0,
+                           s, d_tasks, d_task_begin, ntask, nitems, b64, b32);
+    else
+        hipLaunchKernelGGL((k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, false>), dim3((unsigned)nblocks), dim3(kBlock),
+                           0, s, d_tasks, d_task_begin, ntask, nitems, b64, b32);
+    return hipGetLastError();
+}
+
+static hipError_t launch_list_cls(bool mixed, int mode, const ListDev& L, const double* b64, const float* b32,
+                                  hipStream_t s) {
+    if (L.n <= 0) return hipSuccess;
+    const unsigned nblocks = (unsigned)((L.n + kBlock - 1) / kBlock);
+    if (mode == MODE_SCHWARZ)
+        hipLaunchKernelGGL((k_list<UQC_LA, UQC_LB, UQC_LC, UQC_LD, false, MODE_SCHWARZ>), dim3(nblocks),
+                           dim3(kBlock), 0, s, L, b64, b32);
+    else if (mixed)
+        hipLaunchKernelGGL((k_list<UQC_LA, UQC_LB, UQC_LC, UQC_LD, true, MODE_STORE>), dim3(nblocks), dim3(kBlock), 0,
+                           s, L, b64, b32);
+    else
+        hipLaunchKernelGGL((k_list<UQC_LA, UQC_LB, UQC_LC, UQC_LD, false, MODE_STORE>), dim3(nblocks), dim3(kBlock),
+                           0, s, L, b64, b32);
+    return hipGetLastError();
+}
+
+ClassLaunchers UQC_CAT(class_launchers_, UQC_CLASS_ID)() { return ClassLaunchers{&launch_digest_cls, &launch_list_cls}; }
+
+}  // namespace uqc

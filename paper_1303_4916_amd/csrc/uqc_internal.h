@@ -1,0 +1,89 @@
+// Internal data layout shared by the host plan and the device kernels of libuqc.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace uqc {
+
+constexpr int kWave = 64;              // CDNA wavefront width
+constexpr int kBlock = 256;            // threads per block of the quartet kernels (4 wavefronts)
+constexpr int kMaxK = 16;              // maximum contraction depth
+constexpr int kBoysGridPerUnit = 10;   // Boys Taylor grid: T_g = g / 10
+constexpr int kBoysTmax = 40;          // grid covers [0, 40); asymptotic form beyond
+constexpr int kBoysNg = kBoysTmax * kBoysGridPerUnit + 1;
+constexpr int kBoysNm = 16;            // F_0 .. F_15 stored per grid point (m <= 8 plus Taylor order 7)
+constexpr int kBoysTmax32 = 30;        // FP32 evaluation limit in mixed mode
+constexpr int kNumClasses = 21;
+
+// Primitive-pair fields, stored field-major: prim[field][k][np] (consecutive pairs contiguous)
+enum PrimField { F_Z = 0, F_PX, F_PY, F_PZ, F_PAX, F_PAY, F_PAZ, F_PREF, F_O2Z, kNumFields };
+
+// One bin of shell pairs with the same (l_a, l_b, K_a, K_b), sorted by Schwarz bound (descending).
+struct BinDev {
+    const double* prim;   // [kNumFields][K][np]
+    const double* AB;     // [3][np]  A - B
+    const int* off_a;     // [np] first basis function of shell a (the higher-l shell)
+    const int* off_b;     // [np]
+    const double* sdeg;   // [np] 0.5 if a == b else 1
+    int np;
+    int K;                // primitive pairs per shell pair (K_a * K_b)
+};
+
+// One (bra bin, ket bin) block of the quartet work list of a Fock build.
+struct TaskDev {
+    BinDev bra, ket;
+    const int* lo;             // [nbra] first ket index (in the ket bin)
+    const int* hi;             // [nbra] one past the last ket index
+    const long long* item_off; // [nbra + 1] exclusive prefix of ceil((hi - lo) / 64)
+    long long item_begin;      // first work item of this task within its launch
+    long long nitems;
+    int nbra;
+    int same;                  // bra bin == ket bin: the diagonal quartet (bra == ket) gets an extra 1/2
+    const double* D;           // scaled density D' = f D f (nbf x nbf)
+    double* J;                 // J accumulator (nbf x nbf), symmetrised in the finalize step
+    double* K;                 // K accumulator
+    int nbf;
+};
+
+// An explicit list of quartets (bra index, ket index) for block output or Schwarz bounds.
+struct ListDev {
+    BinDev bra, ket;
+    const int* bra_idx;
+    const int* ket_idx;
+    int n;
+    double* out;               // STORE: [n][NA*NB*NC*ND]; SCHWARZ: [n]
+};
+
+enum Mode { MODE_STORE = 0, MODE_SCHWARZ = 1 };
+
+// Host launchers of one angular-momentum class (defined in uqc_eri_class.hip, one object per class).
+struct ClassLaunchers {
+    hipError_t (*digest)(bool mixed, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
+                         long long nitems, const double* boys64, const float* boys32, hipStream_t s);
+    hipError_t (*list)(bool mixed, int mode, const ListDev& list, const double* boys64, const float* boys32,
+                       hipStream_t s);
+};
+
+// Host-side launchers (defined in uqc_kernels.hip).
+int class_index(int la, int lb, int lc, int ld);           // -1 if not canonical
+void class_ls(int idx, int* la, int* lb, int* lc, int* ld);
+hipError_t launch_digest(int cls, bool mixed, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
+                         long long nitems, const double* boys64, const float* boys32, hipStream_t s);
+hipError_t launch_list(int cls, bool mixed, int mode, const ListDev& list, const double* boys64,
+                       const float* boys32, hipStream_t s);
+hipError_t launch_prepare(const double* D, const double* f, double* Dp, int nbf, unsigned long long* maxbits,
+                          hipStream_t s);
+hipError_t launch_zero(double* p, size_t n, hipStream_t s);
+hipError_t launch_finalize(const double* D, const double* Jacc, const double* Kacc, const double* f, double* J,
+                           double* K, double* G, double* E2, int nbf, hipStream_t s);
+hipError_t launch_boys(int prec, int mmax, int n, const double* T, double* out, const double* boys64,
+                       const float* boys32, hipStream_t s);
+hipError_t launch_perturb(double* D, const double* R, int nbf, int ncol, double eps, double trace0, double* work,
+                          hipStream_t s);
+hipError_t launch_normal(double* R, long long n, unsigned long long seed, unsigned long long stream,
+                         hipStream_t s);
+hipError_t launch_trace(const double* D, int nbf, double* out, hipStream_t s);
+double class_flops_prim(int cls);
+double class_flops_contr(int cls);
+
+}  // namespace uqc

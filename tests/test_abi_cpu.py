@@ -1,0 +1,85 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every declared entry point, and its
+host-only logic (defaults, argument checks that precede any device call) behaves as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1303_4916_amd import uqc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "uqc.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = set(re.findall(r"\b(uqc_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = uqc.load()
+    declared = _declared()
+    assert len(declared) >= 17
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(uqc.EXPORTED) == declared
+
+
+def test_library_has_gfx950_code_object():
+    data = open(uqc.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_default_options():
+    o = uqc.default_opts()
+    assert o.schwarz_tau == 1e-12 and o.precision == uqc.FP64 and o.fp64_bound == 1e-3 and o.timing == 0
+
+
+def test_null_arguments_rejected_before_device_use():
+    L = uqc.load()
+    assert L.uqc_init(0, None, None) == uqc.UQC_E_ARG
+    assert b"NULL" in L.uqc_last_error()
+    assert L.uqc_basis_create(None, 1, None, None, None, None, None, None) == uqc.UQC_E_ARG
+    assert L.uqc_fock_build(None, None, None, None, None, None, None) == uqc.UQC_E_ARG
+    assert L.uqc_eri_block(None, 0, 0, 0, 0, 0, None) == uqc.UQC_E_ARG
+    assert L.uqc_poll(None, 1, None) == uqc.UQC_E_ARG
+    assert L.uqc_server_destroy(None) == uqc.UQC_E_ARG
+
+
+def test_init_without_device_reports_device_error():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is visible")
+    except Exception:
+        pass
+    L = uqc.load()
+    h = ctypes.c_void_p()
+    assert L.uqc_init(0, None, ctypes.byref(h)) == uqc.UQC_E_DEVICE
+    assert L.uqc_last_error() != b""
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the public structs have the C compiler's sizes and field offsets."""
+    import subprocess
+    fields = {"uqc_fock_opts": (uqc.FockOpts, ["schwarz_tau", "precision", "fp64_bound", "timing"]),
+              "uqc_stats": (uqc.Stats, [f for f, _ in uqc.Stats._fields_]),
+              "uqc_request": (uqc.Request, [f for f, _ in uqc.Request._fields_]),
+              "uqc_result": (uqc.Result, [f for f, _ in uqc.Result._fields_])}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "uqc.h"', "int main(void) {"]
+    for st, (_, fl) in fields.items():
+        src.append('printf("%%s %%zu\\n", "%s", sizeof(%s));' % (st, st))
+        for f in fl:
+            src.append('printf("%%s.%%s %%zu\\n", "%s", "%s", offsetof(%s, %s));' % (st, f, st, f))
+    src.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)])
+    out = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)]).decode().split("\n") if line)
+    for st, (cls, fl) in fields.items():
+        assert int(out[st]) == ctypes.sizeof(cls), st
+        for f in fl:
+            assert int(out[st + "." + f]) == getattr(cls, f).offset, (st, f)
