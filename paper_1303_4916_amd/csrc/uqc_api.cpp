@@ -32,7 +32,7 @@ void uqc_fock_opts_default(uqc_fock_opts* o) {
 }
 
 // ---------------------------------------------------------------------------------------------- Boys table
-// F_n(T_g), n = 0..15, T_g = g/10 for g = 0..400, from Gauss-Legendre quadrature (long double, 96 nodes) of the
+// F_n(T_g), n = 0..16, T_g = g/8 for g = 0..320, from Gauss-Legendre quadrature (long double, 96 nodes) of the
 // defining integral F_n(T) = int_0^1 t^{2n} exp(-T t^2) dt; the integrand is entire, so the rule converges to the
 // working precision for T <= 40.
 static void legendre_nodes(int n, std::vector<long double>& x, std::vector<long double>& w) {
@@ -71,7 +71,7 @@ static void build_boys_table(std::vector<double>& tab) {
     legendre_nodes(96, x, w);
     tab.assign((size_t)kBoysNg * kBoysNm, 0.0);
     for (int g = 0; g < kBoysNg; ++g) {
-        const long double T = (long double)((double)g * 0.1);
+        const long double T = (long double)g / kBoysGridPerUnit;
         for (int n = 0; n < kBoysNm; ++n) {
             long double s = 0;
             for (size_t i = 0; i < x.size(); ++i) {
@@ -165,10 +165,11 @@ void uqc::free_plan(Plan& p) {
     p.d_mem = nullptr;
 }
 
-// Device arrays of a bin in one allocation: prim [kNumFields*K*np], AB [3*np], sdeg [np], off_a [np], off_b [np].
+// Device arrays of a bin in one allocation: prim [kNumFields*K*np], AB [3*np], sdeg [np], Q [np], off_a [np],
+// off_b [np].
 static uqc_status upload_bin(Bin& b) {
     const size_t np = b.np, K = b.K;
-    const size_t nd = kNumFields * K * np + 3 * np + np;
+    const size_t nd = kNumFields * K * np + 3 * np + 2 * np;
     const size_t bytes = nd * sizeof(double) + 2 * np * sizeof(int);
     if (!b.d_mem) {
         if (hipMalloc(&b.d_mem, bytes) != hipSuccess) return uqc_fail(UQC_E_NOMEM, "basis: bin allocation failed");
@@ -178,6 +179,7 @@ static uqc_status upload_bin(Bin& b) {
     std::memcpy(hd, b.prim.data(), kNumFields * K * np * sizeof(double));
     std::memcpy(hd + kNumFields * K * np, b.AB.data(), 3 * np * sizeof(double));
     std::memcpy(hd + kNumFields * K * np + 3 * np, b.sdeg.data(), np * sizeof(double));
+    std::memcpy(hd + kNumFields * K * np + 4 * np, b.Q.data(), np * sizeof(double));
     int* hi = (int*)(hd + nd);
     std::memcpy(hi, b.off_a.data(), np * sizeof(int));
     std::memcpy(hi + np, b.off_b.data(), np * sizeof(int));
@@ -187,11 +189,26 @@ static uqc_status upload_bin(Bin& b) {
     b.dev.prim = dd;
     b.dev.AB = dd + kNumFields * K * np;
     b.dev.sdeg = dd + kNumFields * K * np + 3 * np;
+    b.dev.Q = dd + kNumFields * K * np + 4 * np;
     b.dev.off_a = di;
     b.dev.off_b = di + np;
     b.dev.np = (int)np;
     b.dev.K = (int)K;
     return UQC_OK;
+}
+
+static int decade(double q) { return q > 0 ? (int)std::floor(std::log10(q)) : -400; }
+
+int Bin::first_below(int dec) const {
+    for (const auto& x : bstart)
+        if (x.first < dec) return x.second;
+    return np;
+}
+
+int Bin::first_at_or_below(int dec) const {
+    for (const auto& x : bstart)
+        if (x.first <= dec) return x.second;
+    return np;
 }
 
 // Reorders the host arrays of a bin by the permutation `perm` (new position i takes old perm[i]).
@@ -414,8 +431,20 @@ uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* n
         Bin& bn = B->bins[bi];
         std::vector<int> perm(bn.np);
         std::iota(perm.begin(), perm.end(), 0);
-        std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return bn.Q[x] > bn.Q[y]; });
+        // decade of the bound (descending), then first shell, then bound (descending)
+        std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) {
+            const int dx = decade(bn.Q[x]), dy = decade(bn.Q[y]);
+            if (dx != dy) return dx > dy;
+            if (bn.off_a[x] != bn.off_a[y]) return bn.off_a[x] < bn.off_a[y];
+            return bn.Q[x] > bn.Q[y];
+        });
         permute_bin(bn, perm);
+        bn.bucket.resize(bn.np);
+        bn.bstart.clear();
+        for (int i = 0; i < bn.np; ++i) {
+            bn.bucket[i] = decade(bn.Q[i]);
+            if (i == 0 || bn.bucket[i] != bn.bucket[i - 1]) bn.bstart.push_back({bn.bucket[i], i});
+        }
         uqc_status st = upload_bin(bn);
         if (st != UQC_OK) { delete B; return st; }
         for (int i = 0; i < bn.np; ++i) {
@@ -427,7 +456,7 @@ uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* n
             }
             B->Qfull[(size_t)a * nshell + b] = B->Qfull[(size_t)b * nshell + a] = bn.Q[i];
         }
-        B->qmax = std::max(B->qmax, bn.np ? bn.Q[0] : 0.0);
+        for (int i = 0; i < bn.np; ++i) B->qmax = std::max(B->qmax, bn.Q[i]);
     }
     // workspace: f[nbf], D', J, K accumulators, E2 + symmetry scalars, host-pointer staging for D, J, K, G
     {
@@ -476,9 +505,31 @@ uqc_status uqc_schwarz(const uqc_basis* b, double* Q) {
 }
 
 // ---------------------------------------------------------------------------------------------- screened plan
-// For every bin pair (X >= Y) the canonical quartets are, per bra pair i of X, the kets j of Y with
-// Q_i Q_j >= tau (a prefix, Y being sorted by bound) and, if X == Y, j <= i.  In mixed precision the prefix with
-// Q_i Q_j > bound forms the FP64 task, the rest the FP32-recursion task.
+// For every bin pair (X >= Y) the canonical quartets are, per bra pair i of X, the kets j of Y with Q_i Q_j >= tau
+// and, if X == Y, j <= i.  Ket bins are ordered by decade of Q (descending), so the kets that can pass form a prefix
+// ending one decade below the decade of tau / Q_i; the kernels apply the exact test per lane.  In mixed precision
+// the FP64 task takes the kets with Q_i Q_j > bound and the FP32-recursion task those with Q_i Q_j <= bound; the
+// decades around the split are scanned by both tasks with complementary per-lane tests.
+void uqc::plan_account(Plan& p) {
+    p.quartets = p.prim_quartets = p.fp64_quartets = 0;
+    p.flops = 0;
+    for (auto& g : p.groups) {
+        g.quartets = g.prim_quartets = 0;
+        g.flops = 0;
+        for (int t = 0; t < g.ntask; ++t) {
+            const long long q = (long long)p.h_count[g.task0 + t];
+            g.quartets += q;
+            g.prim_quartets += q * g.task_K[t];
+            g.flops += (double)q * ((double)g.task_K[t] * class_flops_prim(g.cls) + class_flops_contr(g.cls));
+        }
+        p.quartets += g.quartets;
+        p.prim_quartets += g.prim_quartets;
+        if (!g.mixed) p.fp64_quartets += g.quartets;
+        p.flops += g.flops;
+    }
+    p.screened = p.canonical - p.quartets;
+}
+
 Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st) {
     for (auto& kv : B->plans)
         if (kv.first.tau == tau && kv.first.prec == prec && (prec == UQC_FP64 || kv.first.bound == bound))
@@ -487,87 +538,95 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
     Plan plan;
     struct HostTask {
         int cls, mixed, X, Y, same;
+        double lo_excl, hi_incl;
         std::vector<int> lo, hi;
         std::vector<long long> off;
-        long long nitems, quartets, prim;
+        long long nitems;
     };
     std::vector<HostTask> tasks;
     const int nb = (int)B->bins.size();
-    long long total_canonical = 0;
     {
         const long long npair = (long long)B->nshell * (B->nshell + 1) / 2;
-        total_canonical = npair * (npair + 1) / 2;
+        plan.canonical = npair * (npair + 1) / 2;
     }
-    long long kept = 0;
+    const bool mixed = prec == UQC_MIXED;
     for (int X = 0; X < nb; ++X)
         for (int Y = 0; Y <= X; ++Y) {
             const Bin &bx = B->bins[X], &by = B->bins[Y];
             const int cls = class_index(bx.la, bx.lb, by.la, by.lb);
-            HostTask t64{cls, 0, X, Y, X == Y, {}, {}, {}, 0, 0, 0};
-            HostTask t32{cls, 1, X, Y, X == Y, {}, {}, {}, 0, 0, 0};
+            HostTask t64{cls, 0, X, Y, X == Y, mixed ? bound : -1.0, INFINITY, {}, {}, {}, 0};
+            HostTask t32{cls, 1, X, Y, X == Y, -1.0, bound, {}, {}, {}, 0};
             for (int i = 0; i < bx.np; ++i) {
                 const double qi = bx.Q[i];
-                auto count_if_prefix = [&](auto pred) {
-                    int lo = 0, hi = by.np;  // first j where pred fails
-                    while (lo < hi) {
-                        const int mid = (lo + hi) / 2;
-                        if (pred(by.Q[mid])) lo = mid + 1; else hi = mid;
-                    }
-                    return lo;
-                };
-                int h = tau > 0 ? count_if_prefix([&](double qj) { return qi * qj >= tau; }) : by.np;
+                int h = by.np;
+                if (tau > 0) h = qi > 0 ? by.first_below(decade(tau / qi) - 1) : 0;
                 if (X == Y) h = std::min(h, i + 1);
-                int n64 = h;
-                if (prec == UQC_MIXED) n64 = std::min(h, count_if_prefix([&](double qj) { return qi * qj > bound; }));
+                int h64 = h, l32 = h;
+                if (mixed) {
+                    if (qi > 0) {
+                        const int dsplit = decade(bound / qi);
+                        h64 = std::min(h, by.first_below(dsplit - 1));
+                        l32 = std::min(h, by.first_at_or_below(dsplit + 1));
+                    } else {
+                        h64 = 0;
+                        l32 = 0;
+                    }
+                }
                 t64.lo.push_back(0);
-                t64.hi.push_back(n64);
-                t32.lo.push_back(n64);
+                t64.hi.push_back(h64);
+                t32.lo.push_back(l32);
                 t32.hi.push_back(h);
-                kept += h;
             }
             for (HostTask* t : {&t64, &t32}) {
-                if (t->mixed && prec != UQC_MIXED) continue;
+                if (t->mixed && !mixed) continue;
                 t->off.resize(bx.np + 1);
-                long long acc = 0, q = 0;
+                long long acc = 0;
                 for (int i = 0; i < bx.np; ++i) {
                     t->off[i] = acc;
-                    const int n = t->hi[i] - t->lo[i];
-                    acc += (n + kWave - 1) / kWave;
-                    q += n;
+                    acc += (std::max(t->hi[i] - t->lo[i], 0) + kWave - 1) / kWave;
                 }
                 t->off[bx.np] = acc;
                 t->nitems = acc;
-                t->quartets = q;
-                t->prim = q * (long long)bx.K * by.K;
-                if (q > 0) tasks.push_back(std::move(*t));
+                if (acc > 0) tasks.push_back(std::move(*t));
             }
         }
-    plan.quartets = kept;
-    plan.screened = total_canonical - kept;
-    // group tasks into one launch per (class, precision)
+    // group tasks into one launch per (class, precision); task order = group order, so the counters of a group
+    // are contiguous
     std::vector<std::pair<int, int>> gkeys;
     for (auto& t : tasks) {
         std::pair<int, int> k{t.cls, t.mixed};
         if (std::find(gkeys.begin(), gkeys.end(), k) == gkeys.end()) gkeys.push_back(k);
     }
-    std::sort(gkeys.begin(), gkeys.end());
-    // device memory: per task lo/hi/off; per group TaskDev array + task_begin
+    std::sort(gkeys.begin(), gkeys.end(), [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+        return a.first != b.first ? a.first > b.first : a.second < b.second;  // heavy classes first
+    });
+    std::vector<int> order;
+    for (auto& gk : gkeys)
+        for (size_t ti = 0; ti < tasks.size(); ++ti)
+            if (tasks[ti].cls == gk.first && tasks[ti].mixed == gk.second) order.push_back((int)ti);
+    plan.ntasks = (int)tasks.size();
+    // device memory: counters, per task lo/hi/off, per group TaskDev array + task_begin
     size_t bytes = 0;
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    bytes += align(tasks.size() * sizeof(unsigned long long));
     for (auto& t : tasks) {
         const size_t n = B->bins[t.X].np;
         bytes += align(n * sizeof(int)) * 2 + align((n + 1) * sizeof(long long));
     }
     for (size_t g = 0; g < gkeys.size(); ++g) bytes += align(tasks.size() * sizeof(TaskDev)) + align(tasks.size() * 8);
-    std::vector<char> host(bytes);
+    std::vector<char> host(bytes, 0);
     if (hipMalloc(&plan.d_mem, std::max(bytes, (size_t)256)) != hipSuccess) {
         *st = uqc_fail(UQC_E_NOMEM, "plan: allocation failed");
         return nullptr;
     }
     char* dbase = (char*)plan.d_mem;
     size_t pos = 0;
+    plan.d_count = (unsigned long long*)dbase;
+    plan.h_count.assign(tasks.size(), 0);
+    pos += align(tasks.size() * sizeof(unsigned long long));
     std::vector<TaskDev> tdev(tasks.size());
-    for (size_t ti = 0; ti < tasks.size(); ++ti) {
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+        const int ti = order[oi];
         auto& t = tasks[ti];
         const size_t n = B->bins[t.X].np;
         std::memcpy(host.data() + pos, t.lo.data(), n * sizeof(int));
@@ -579,7 +638,7 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
         std::memcpy(host.data() + pos, t.off.data(), (n + 1) * sizeof(long long));
         const long long* doff = (const long long*)(dbase + pos);
         pos += align((n + 1) * sizeof(long long));
-        TaskDev& d = tdev[ti];
+        TaskDev& d = tdev[oi];
         d.bra = B->bins[t.X].dev;
         d.ket = B->bins[t.Y].dev;
         d.lo = dlo;
@@ -587,6 +646,10 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
         d.item_off = doff;
         d.item_begin = 0;
         d.nitems = t.nitems;
+        d.tau = tau;
+        d.lo_excl = t.lo_excl;
+        d.hi_incl = t.hi_incl;
+        d.count = plan.d_count + oi;
         d.nbra = (int)n;
         d.same = t.same;
         d.D = B->d_Dp;
@@ -594,22 +657,23 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
         d.K = B->d_K;
         d.nbf = B->nbf;
     }
+    size_t oi = 0;
     for (auto& gk : gkeys) {
         LaunchGroup G;
         G.cls = gk.first;
         G.mixed = gk.second;
+        G.task0 = (int)oi;
         std::vector<TaskDev> gt;
         std::vector<long long> begin;
         long long items = 0;
-        for (size_t ti = 0; ti < tasks.size(); ++ti) {
-            if (tasks[ti].cls != gk.first || tasks[ti].mixed != gk.second) continue;
-            TaskDev d = tdev[ti];
+        while (oi < order.size() && tasks[order[oi]].cls == gk.first && tasks[order[oi]].mixed == gk.second) {
+            TaskDev d = tdev[oi];
             d.item_begin = items;
             begin.push_back(items);
             items += d.nitems;
             gt.push_back(d);
-            G.quartets += tasks[ti].quartets;
-            G.prim_quartets += tasks[ti].prim;
+            G.task_K.push_back(B->bins[tasks[order[oi]].X].K * B->bins[tasks[order[oi]].Y].K);
+            ++oi;
         }
         G.ntask = (int)gt.size();
         G.nitems = items;
@@ -619,12 +683,8 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
         std::memcpy(host.data() + pos, begin.data(), begin.size() * sizeof(long long));
         G.d_begin = (const long long*)(dbase + pos);
         pos += align(tasks.size() * 8);
-        G.flops = (double)G.prim_quartets * class_flops_prim(G.cls) + (double)G.quartets * class_flops_contr(G.cls);
         G.host_tasks = gt;
         G.host_begin = begin;
-        plan.prim_quartets += G.prim_quartets;
-        if (!G.mixed) plan.fp64_quartets += G.quartets;
-        plan.flops += G.flops;
         plan.groups.push_back(G);
     }
     if (bytes && hipMemcpy(plan.d_mem, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
@@ -828,6 +888,7 @@ uqc_status uqc_fock_build(uqc_basis* B, const double* D, double* J, double* K, d
     std::memcpy(&ma, &hb[1], 8);
     if (!(md <= 1e-12 * ma)) return uqc_fail(UQC_E_NOT_SYMMETRIC, "uqc_fock_build: density is not symmetric (or not finite)");
     UQC_HIP(launch_zero(B->d_J, 2 * NN, s));
+    if (plan->ntasks) UQC_HIP(launch_zero((double*)plan->d_count, (size_t)plan->ntasks, s));
     const bool timing = o.timing != 0;
     size_t ev = 0;
     for (auto& g : plan->groups) {
@@ -838,12 +899,16 @@ uqc_status uqc_fock_build(uqc_basis* B, const double* D, double* J, double* K, d
     UQC_HIP(launch_finalize(Dd, B->d_J, B->d_K, B->d_f, Jd, Kd, Gd, B->d_scal, (int)N, s));
     double E2 = 0.0;
     UQC_HIP(hipMemcpyAsync(&E2, B->d_scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (plan->ntasks)
+        UQC_HIP(hipMemcpyAsync(plan->h_count.data(), plan->d_count, plan->ntasks * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, s));
     if (!dev) {
         if (J) UQC_HIP(hipMemcpyAsync(J, Jd, NN * sizeof(double), hipMemcpyDeviceToHost, s));
         if (K) UQC_HIP(hipMemcpyAsync(K, Kd, NN * sizeof(double), hipMemcpyDeviceToHost, s));
         if (G) UQC_HIP(hipMemcpyAsync(G, Gd, NN * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     UQC_HIP(hipStreamSynchronize(s));
+    plan_account(*plan);
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->E2 = E2;

@@ -1,6 +1,6 @@
 // Host-side objects behind the opaque handles of include/uqc.h.
 #pragma once
-#include "../../include/uqc.h"
+#include "uqc.h"
 #include "uqc_internal.h"
 
 #include <list>
@@ -40,6 +40,10 @@ struct Bin {
     int la = 0, lb = 0, Ka = 0, Kb = 0, K = 0, np = 0;
     std::vector<double> prim, AB, sdeg, Q;
     std::vector<int> off_a, off_b, sa, sb;
+    std::vector<int> bucket;                   // [np] decade of Q (floor(log10 Q)), non-increasing along the bin
+    std::vector<std::pair<int, int>> bstart;   // (decade, first index) for every decade present, in bin order
+    int first_below(int dec) const;            // first index whose decade is < dec (np if none)
+    int first_at_or_below(int dec) const;      // first index whose decade is <= dec (np if none)
     void* d_mem = nullptr;
     BinDev dev{};
 };
@@ -48,8 +52,10 @@ struct LaunchGroup {
     int cls = 0;
     int mixed = 0;
     int ntask = 0;
-    long long nitems = 0, quartets = 0, prim_quartets = 0;
+    int task0 = 0;                     // index of the group's first task counter in the plan's counter array
+    long long nitems = 0, quartets = 0, prim_quartets = 0;  // counts of the last build
     double flops = 0;
+    std::vector<int> task_K;           // primitive quartets per shell quartet of every task (K_bra * K_ket)
     const TaskDev* d_tasks = nullptr;
     const long long* d_begin = nullptr;
     std::vector<TaskDev> host_tasks;   // copies (device pointers inside), used to batch several bases
@@ -64,10 +70,17 @@ struct PlanKey {
 
 struct Plan {
     std::vector<LaunchGroup> groups;
-    long long quartets = 0, screened = 0, prim_quartets = 0, fp64_quartets = 0;
+    long long canonical = 0;                       // canonical shell quartets of the basis
+    long long quartets = 0, screened = 0, prim_quartets = 0, fp64_quartets = 0;  // counts of the last build
     double flops = 0;
+    int ntasks = 0;
+    unsigned long long* d_count = nullptr;         // [ntasks] per-task quartet counters (device)
+    std::vector<unsigned long long> h_count;
     void* d_mem = nullptr;
 };
+
+// Counts of the last build, from the per-task counters (h_count must hold the device values).
+void plan_account(Plan& p);
 
 void free_plan(Plan& p);
 

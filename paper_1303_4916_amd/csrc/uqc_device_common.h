@@ -17,17 +17,18 @@ __host__ __device__ constexpr double comp_factor(int l, int c) {
 constexpr double kPi = 3.14159265358979323846;
 
 // ------------------------------------------------------------------------------------------------ Boys function
-// F_m(T) = int_0^1 t^{2m} exp(-T t^2) dt.  For T < 40: Taylor series of order 7 around the nearest grid point
-// T_g = g/10 (|T - T_g| <= 0.05, truncation error < 1e-15 relative), using dF_m/dT = -F_{m+1}, for the highest order
+// F_m(T) = int_0^1 t^{2m} exp(-T t^2) dt.  For T < 40: Taylor series of order 8 around the nearest grid point
+// T_g = g/8 (|T - T_g| <= 1/16, truncation error < 1e-16 relative), using dF_m/dT = -F_{m+1}, for the highest order
 // needed, then the downward recursion F_m = (2T F_{m+1} + exp(-T)) / (2m+1).  For T >= 40: F_0 = sqrt(pi/T)/2
 // (erf(sqrt(T)) = 1 to double precision) and the upward recursion F_{m+1} = ((2m+1) F_m - exp(-T)) / (2T).
 template <int L>
 __device__ __forceinline__ void boys64(double T, const double* __restrict__ tab, double* F) {
     if (T < (double)kBoysTmax) {
         const int g = (int)(T * (double)kBoysGridPerUnit + 0.5);
-        const double d = (double)g * 0.1 - T;
+        const double d = (double)g * (1.0 / kBoysGridPerUnit) - T;  // exact grid point
         const double* r = tab + g * kBoysNm + L;
-        double p = r[7];
+        double p = r[8];
+        p = fma(p, d * (1.0 / 8.0), r[7]);
         p = fma(p, d * (1.0 / 7.0), r[6]);
         p = fma(p, d * (1.0 / 6.0), r[5]);
         p = fma(p, d * (1.0 / 5.0), r[4]);
@@ -54,13 +55,15 @@ __device__ __forceinline__ void boys64(double T, const double* __restrict__ tab,
     }
 }
 
-// FP32 variant (mixed mode, T <= 30 only): Taylor order 4 around the same grid (truncation < 3e-9 relative).
+// FP32 variant (mixed mode, T <= 30 only): Taylor order 5 around the same grid points (truncation < 1e-10
+// relative); the grid offset d is exact in FP32 because the grid spacing is a power of two.
 template <int L>
 __device__ __forceinline__ void boys32(float T, const float* __restrict__ tab, float* F) {
     const int g = (int)(T * (float)kBoysGridPerUnit + 0.5f);
-    const float d = (float)g * 0.1f - T;
+    const float d = (float)g * (1.0f / kBoysGridPerUnit) - T;
     const float* r = tab + g * kBoysNm + L;
-    float p = r[4];
+    float p = r[5];
+    p = fmaf(p, d * 0.2f, r[4]);
     p = fmaf(p, d * 0.25f, r[3]);
     p = fmaf(p, d * (1.0f / 3.0f), r[2]);
     p = fmaf(p, d * 0.5f, r[1]);

@@ -94,10 +94,23 @@ __device__ __forceinline__ void accumulate(const BinDev& B, int bra, const BinDe
     }
 }
 
+// Segmented inclusive sum across the wavefront: lanes with equal keys form contiguous runs; inseg[s] tells whether
+// lane - 2^s belongs to the same run.  After the scan the last lane of every run holds the run's total.
+__device__ __forceinline__ double seg_scan(double x, const bool* inseg) {
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const double y = __shfl_up(x, 1 << st, kWave);
+        if (inseg[st]) x += y;
+    }
+    return x;
+}
+
 // J/K digest of one contracted quartet block v = (ab|cd) (raw components), weight w (degeneracy factors; 0 for
 // idle lanes):  J_ab += 2w v.D_cd, J_cd += 2w v.D_ab, K_ac += w v.D_bd, K_ad += w v.D_bc, K_bc += w v.D_ad,
 // K_bd += w v.D_ac.  The accumulators are symmetrised (J + J^T, K + K^T) in the finalize step.  The bra pair (a, b)
-// is the same for every lane of the wavefront.
+// is the same for every lane of the wavefront, so J_ab is summed over the wavefront before one atomic add; ket
+// pairs sharing their first shell c sit in adjacent lanes, so K_ac and K_bc are summed over each such run before
+// one atomic add per run; J_cd, K_ad and K_bd are added per lane.
 template <int NA, int NB, int NC, int ND>
 __device__ __forceinline__ void digest(const double* __restrict__ v, double w, bool act, int lane, int oa, int ob,
                                        int oc, int od, const double* __restrict__ D, double* __restrict__ J,
@@ -163,38 +176,65 @@ __device__ __forceinline__ void digest(const double* __restrict__ v, double w, b
             const double s = wave_sum(w2 * jab[i * NB + j]);
             if (lane == 0) atomic_add(J + (size_t)(oa + i) * N + ob + j, s);
         }
+    // runs of adjacent lanes with equal first ket shell; the same shell may recur in a later, separate run (the
+    // wavefront can span two decades of the ket order), so runs are told apart by their index, not by the shell
+    const int kprev = __shfl_up(oc, 1, kWave);
+    const bool head = lane == 0 || kprev != oc;
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long upto = lane == kWave - 1 ? ~0ULL : ((1ULL << (lane + 1)) - 1ULL);
+    const int run = __popcll(heads & upto);
+    bool inseg[6];
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int ro = __shfl_up(run, 1 << st, kWave);
+        inseg[st] = lane >= (1 << st) && ro == run;
+    }
+    const bool run_last = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ULL);
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const double s = seg_scan(w * kac[i * NC + k], inseg);
+            if (run_last && s != 0.0) atomic_add(K + (size_t)(oa + i) * N + oc + k, s);
+        }
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const double s = seg_scan(w * kbc[j * NC + k], inseg);
+            if (run_last && s != 0.0) atomic_add(K + (size_t)(ob + j) * N + oc + k, s);
+        }
     if (act) {
 #pragma unroll
         for (int k = 0; k < NC; ++k)
 #pragma unroll
             for (int l = 0; l < ND; ++l) atomic_add(J + (size_t)(oc + k) * N + od + l, w2 * jcd[k * ND + l]);
 #pragma unroll
-        for (int i = 0; i < NA; ++i) {
-#pragma unroll
-            for (int k = 0; k < NC; ++k) atomic_add(K + (size_t)(oa + i) * N + oc + k, w * kac[i * NC + k]);
+        for (int i = 0; i < NA; ++i)
 #pragma unroll
             for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(oa + i) * N + od + l, w * kad[i * ND + l]);
-        }
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-#pragma unroll
-            for (int k = 0; k < NC; ++k) atomic_add(K + (size_t)(ob + j) * N + oc + k, w * kbc[j * NC + k]);
+        for (int j = 0; j < NB; ++j)
 #pragma unroll
             for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(ob + j) * N + od + l, w * kbd[j * ND + l]);
-        }
     }
 }
 
 template <int LA, int LB, int LC, int LD, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_digest(const TaskDev* __restrict__ tasks,
                                                    const long long* __restrict__ task_begin, int ntask,
-                                                   long long nitems, const double* __restrict__ boys64tab,
+                                                   long long nitems, unsigned long long perm,
+                                                   const double* __restrict__ boys64tab,
                                                    const float* __restrict__ boys32tab) {
     using C = EriClass<LA, LB, LC, LD>;
     const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const int lane = (int)(threadIdx.x % kWave);
-    const long long item = (long long)blockIdx.x * (kBlock / kWave) + wid;
-    if (item >= nitems) return;
+    const long long slot = (long long)blockIdx.x * (kBlock / kWave) + wid;
+    if (slot >= nitems) return;
+    // Items of one bra pair are consecutive in the work list; a bijective scatter (slot * perm mod nitems, perm
+    // coprime to nitems) makes the wavefronts in flight work on different bra pairs, so their atomic updates of
+    // J_ab and of the K rows of shells a and b do not pile onto the same addresses.
+    const long long item = (long long)(((unsigned long long)slot * perm) % (unsigned long long)nitems);
     int t = 0;
     {
         int lo = 0, hi = ntask - 1;
@@ -217,8 +257,16 @@ __global__ __launch_bounds__(kBlock) void k_digest(const TaskDev* __restrict__ t
     }
     const int kend = tk.hi[bra];
     int ket = tk.lo[bra] + (int)(li - tk.item_off[bra]) * kWave + lane;
-    const bool act = ket < kend;
+    bool act = ket < kend;
     if (!act) ket = kend - 1;  // idle lanes recompute a valid quartet with weight 0 (keeps the wave converged)
+    {
+        // exact screening and precision routing per lane (the work range is only decade-accurate)
+        const double q = tk.bra.Q[bra] * tk.ket.Q[ket];
+        act = act && q >= tk.tau && q > tk.lo_excl && q <= tk.hi_incl;
+    }
+    const unsigned long long live = __ballot(act);
+    if (live == 0ULL) return;  // uniform: nothing of this item survives screening
+    if (lane == 0) atomicAdd(tk.count, (unsigned long long)__popcll(live));
 
     double acc[C::NACC];
 #pragma unroll

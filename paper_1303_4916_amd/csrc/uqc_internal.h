@@ -8,23 +8,26 @@ namespace uqc {
 constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kBlock = 256;            // threads per block of the quartet kernels (4 wavefronts)
 constexpr int kMaxK = 16;              // maximum contraction depth
-constexpr int kBoysGridPerUnit = 10;   // Boys Taylor grid: T_g = g / 10
+constexpr int kBoysGridPerUnit = 8;    // Boys Taylor grid: T_g = g / 8 (exact in binary, same points in FP32/FP64)
 constexpr int kBoysTmax = 40;          // grid covers [0, 40); asymptotic form beyond
 constexpr int kBoysNg = kBoysTmax * kBoysGridPerUnit + 1;
-constexpr int kBoysNm = 16;            // F_0 .. F_15 stored per grid point (m <= 8 plus Taylor order 7)
+constexpr int kBoysNm = 17;            // F_0 .. F_16 stored per grid point (m <= 8 plus Taylor order 8)
 constexpr int kBoysTmax32 = 30;        // FP32 evaluation limit in mixed mode
 constexpr int kNumClasses = 21;
 
 // Primitive-pair fields, stored field-major: prim[field][k][np] (consecutive pairs contiguous)
 enum PrimField { F_Z = 0, F_PX, F_PY, F_PZ, F_PAX, F_PAY, F_PAZ, F_PREF, F_O2Z, kNumFields };
 
-// One bin of shell pairs with the same (l_a, l_b, K_a, K_b), sorted by Schwarz bound (descending).
+// One bin of shell pairs with the same (l_a, l_b, K_a, K_b).  Pairs are ordered by decade of their Schwarz bound
+// (descending), then by their first shell, so that the ket range of any bra pair is a prefix at decade granularity
+// and kets sharing their first shell are adjacent inside a wavefront.
 struct BinDev {
     const double* prim;   // [kNumFields][K][np]
     const double* AB;     // [3][np]  A - B
     const int* off_a;     // [np] first basis function of shell a (the higher-l shell)
     const int* off_b;     // [np]
     const double* sdeg;   // [np] 0.5 if a == b else 1
+    const double* Q;      // [np] Schwarz bound of the pair
     int np;
     int K;                // primitive pairs per shell pair (K_a * K_b)
 };
@@ -37,6 +40,9 @@ struct TaskDev {
     const long long* item_off; // [nbra + 1] exclusive prefix of ceil((hi - lo) / 64)
     long long item_begin;      // first work item of this task within its launch
     long long nitems;
+    double tau;                // a quartet in the range is computed iff Q_ab Q_cd >= tau
+    double lo_excl, hi_incl;   //   and lo_excl < Q_ab Q_cd <= hi_incl (precision routing)
+    unsigned long long* count; // quartets computed by this task (one atomic per wavefront)
     int nbra;
     int same;                  // bra bin == ket bin: the diagonal quartet (bra == ket) gets an extra 1/2
     const double* D;           // scaled density D' = f D f (nbf x nbf)
@@ -59,7 +65,8 @@ enum Mode { MODE_STORE = 0, MODE_SCHWARZ = 1 };
 // Host launchers of one angular-momentum class (defined in uqc_eri_class.hip, one object per class).
 struct ClassLaunchers {
     hipError_t (*digest)(bool mixed, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
-                         long long nitems, const double* boys64, const float* boys32, hipStream_t s);
+                         long long nitems, unsigned long long perm, const double* boys64, const float* boys32,
+                         hipStream_t s);
     hipError_t (*list)(bool mixed, int mode, const ListDev& list, const double* boys64, const float* boys32,
                        hipStream_t s);
 };

@@ -154,7 +154,8 @@ bool uqc_server::step() {
     for (Req* r : act) {
         uqc_basis* B = r->basis;
         const size_t NN = (size_t)B->nbf * B->nbf;
-        if (launch_zero(B->d_scal, 8, s) != hipSuccess ||
+        if ((r->plan->ntasks && launch_zero((double*)r->plan->d_count, (size_t)r->plan->ntasks, s) != hipSuccess) ||
+            launch_zero(B->d_scal, 8, s) != hipSuccess ||
             launch_prepare(r->d_D, B->d_f, B->d_Dp, B->nbf, (unsigned long long*)(B->d_scal + 1), s) != hipSuccess ||
             launch_zero(B->d_J, 2 * NN, s) != hipSuccess)
             return fail_all("server: preparation launch failed");
@@ -220,7 +221,10 @@ bool uqc_server::step() {
         const size_t NN = (size_t)B->nbf * B->nbf;
         if (launch_finalize(act[i]->d_D, B->d_J, B->d_K, B->d_f, B->d_io + NN, B->d_io + 2 * NN, B->d_io + 3 * NN,
                             B->d_scal, B->nbf, s) != hipSuccess ||
-            hipMemcpyAsync(&e2[i], B->d_scal, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+            hipMemcpyAsync(&e2[i], B->d_scal, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            (act[i]->plan->ntasks &&
+             hipMemcpyAsync(act[i]->plan->h_count.data(), act[i]->plan->d_count,
+                            act[i]->plan->ntasks * sizeof(unsigned long long), hipMemcpyDeviceToHost, s) != hipSuccess))
             return fail_all("server: finalize failed");
     }
     if (hipStreamSynchronize(s) != hipSuccess) return fail_all("server: step failed on the device");
@@ -228,6 +232,7 @@ bool uqc_server::step() {
     for (size_t i = 0; i < act.size(); ++i) {
         Req* r = act[i];
         r->E2[r->iter] = e2[i];
+        plan_account(*r->plan);
         r->quartets += r->plan->quartets;
         ++r->iter;
         uqc_basis* B = r->basis;
