@@ -155,6 +155,23 @@ def gen_vrr(c):
     return v, es, fs, acc_lines
 
 
+def interleave(v, acc_lines):
+    """VRR statements with every accumulation placed right after the statement that defines its target, so a
+    target's register can be released as soon as its last use as an intermediate is past."""
+    where = {}
+    for line in acc_lines:
+        nm = line.split("(double)")[1].rstrip(";")
+        where.setdefault(nm, []).append(line)
+    out = []
+    for line in v.lines:
+        out.append(line)
+        nm = line.split()[2]
+        out.extend(where.pop(nm, []))
+    for rest in where.values():  # targets that are Boys values themselves (class (ss|ss))
+        out.extend(rest)
+    return out
+
+
 class Hrr:
     """Horizontal recursion programme on one side (bra or ket), as a list of (target, src1, src2, dir)."""
 
@@ -309,9 +326,7 @@ def main(outdir):
                 hdr.append("    const T oe%d = T(%d) * g.o2e, oer%d = oe%d * g.roe;" % (k, k, k, k))
             else:
                 hdr.append("    const T oze%d = T(%d) * g.o2ze;" % (k, k))
-        for line in v.lines:
-            hdr.append("    " + line)
-        for line in acc_lines:
+        for line in interleave(v, acc_lines):
             hdr.append("    " + line)
         hdr.append("    (void)PAx; (void)PAy; (void)PAz; (void)WPx; (void)WPy; (void)WPz;")
         hdr.append("    (void)QCx; (void)QCy; (void)QCz; (void)WQx; (void)WQy; (void)WQz;")

@@ -1,0 +1,152 @@
+"""GPU tests of the continuous-batching server (uqc_server_create / uqc_submit / uqc_poll).
+
+* every result of a request run in the mix equals the same request run alone (one slot), to atomic-order rounding;
+* the server's densities follow D_{t+1} = (1-eps) D_t + eps R_t R_t^T rescaled to tr(D_0), with R_t from the
+  counter-based generator defined in include/uqc.h, re-implemented here from its published definition
+  (SplitMix64 finaliser, Box-Muller) in numpy;
+* every per-iteration E2 equals a direct uqc_fock_build of the host-recomputed density;
+* a tight HBM budget defers requests (they all finish), a request larger than the budget is refused, unknown
+  tickets are reported.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1303_4916_amd import uqc
+from paper_1303_4916_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+M64 = (1 << 64) - 1
+
+
+def splitmix64(x: np.ndarray) -> np.ndarray:
+    with np.errstate(over="ignore"):
+        z = (x + np.uint64(0x9E3779B97F4A7C15)) & np.uint64(M64)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def normals(n: int, seed: int, t: int) -> np.ndarray:
+    i = np.arange(n, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        x = (np.uint64(seed) * np.uint64(0x9E3779B97F4A7C15) + np.uint64(t) * np.uint64(0xD1B54A32D192ED03) +
+             np.uint64(2) * i)
+        a = splitmix64(x)
+        b = splitmix64(x + np.uint64(1))
+    u1 = ((a >> np.uint64(11)) + np.uint64(1)).astype(np.float64) * 2.0 ** -53
+    u2 = (b >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def density_sequence(D0, n_iter, ncol, eps, seed):
+    N = D0.shape[0]
+    tr0 = np.trace(D0)
+    Ds = [D0]
+    for t in range(n_iter - 1):
+        R = normals(N * ncol, seed, t).reshape(N, ncol)
+        D = (1 - eps) * Ds[-1] + eps * (R @ R.T)
+        Ds.append(D * (tr0 / np.trace(D)))
+    return Ds
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = uqc.Context(0)
+    yield c
+    c.close()
+
+
+def _requests():
+    out = []
+    for i, (n, prec) in enumerate([(3, uqc.FP64), (6, uqc.MIXED), (4, uqc.FP64), (9, uqc.FP64), (5, uqc.MIXED),
+                                   (7, uqc.FP64)]):
+        sh = wl.lattice_shells(n, 500 + i)
+        D0 = wl.random_density(np.random.default_rng(600 + i), sh.nbf, 3, float(n))
+        out.append(dict(shells=sh, D0=D0, n_iter=4, ncol=3, eps=0.05, seed=7000 + i,
+                        opts=uqc.default_opts(tau=1e-12, precision=prec, fp64_bound=1e-5)))
+    return out
+
+
+def _run(ctx, reqs, slots, budget=8 << 30, stagger_s=0.0):
+    srv = uqc.Server(ctx, budget, slots)
+    tickets = []
+    for r in reqs:
+        tickets.append(srv.submit(**r))
+        if stagger_s:
+            time.sleep(stagger_s)
+    res = {}
+    t0 = time.time()
+    while len(res) < len(tickets):
+        for t in tickets:
+            if t not in res:
+                out = srv.poll(t)
+                if out is not None:
+                    res[t] = out
+        assert time.time() - t0 < 120, "server did not finish"
+        time.sleep(0.005)
+    srv.close()
+    return [res[t] for t in tickets]
+
+
+def test_server_mix_equals_alone_and_direct(ctx):
+    reqs = _requests()
+    mix = _run(ctx, reqs, slots=4, stagger_s=0.002)
+    alone = _run(ctx, reqs, slots=1)
+    for r, m, a in zip(reqs, mix, alone):
+        assert m["n_iter"] == r["n_iter"] and a["n_iter"] == r["n_iter"]
+        e_m, e_a = np.array(m["E2"]), np.array(a["E2"])
+        assert np.max(np.abs(e_m - e_a)) <= 1e-12 * np.max(np.abs(e_a))
+        assert np.max(np.abs(m["G"] - a["G"])) <= 1e-12 * np.max(np.abs(a["G"]))
+        # densities follow the published recurrence
+        Ds = density_sequence(r["D0"], r["n_iter"], r["ncol"], r["eps"], r["seed"])
+        assert np.max(np.abs(m["D"] - Ds[-1])) <= 1e-12 * np.max(np.abs(Ds[-1]))
+        # every iteration equals a direct build of that density
+        B = uqc.Basis(ctx, r["shells"])
+        for t, D in enumerate(Ds):
+            J, K, G, st = B.fock_build(D, r["opts"])
+            assert abs(st.E2 - e_m[t]) <= 1e-12 * abs(st.E2), (t, st.E2, e_m[t])
+        assert np.max(np.abs(G - m["G"])) <= 1e-12 * np.max(np.abs(G))
+        B.close()
+        assert m["admit_ms"] >= m["submit_ms"] and m["finish_ms"] >= m["admit_ms"]
+
+
+def test_server_budget_defers_and_refuses(ctx):
+    reqs = _requests()[:4]
+    # budget that holds about one request: all must still complete, one after another
+    small = 3 * 1024 * 1024
+    srv = uqc.Server(ctx, small, 4)
+    big = wl.lattice_shells(40, 9)
+    with pytest.raises(uqc.UqcError) as e:
+        srv.submit(big, wl.random_density(np.random.default_rng(1), big.nbf, 3, 40.0), n_iter=1)
+    assert e.value.status == uqc.UQC_E_NOMEM
+    with pytest.raises(uqc.UqcError) as e:
+        srv.poll(123456)
+    assert e.value.status == uqc.UQC_E_NOT_FOUND
+    srv.close()
+    done = _run(ctx, reqs, slots=4, budget=small)
+    ref = _run(ctx, reqs, slots=1)
+    for d, r in zip(done, ref):
+        assert d["n_iter"] == r["n_iter"]
+        assert np.max(np.abs(np.array(d["E2"]) - np.array(r["E2"]))) <= 1e-12 * np.max(np.abs(r["E2"]))
+
+
+def test_server_rejects_bad_requests(ctx):
+    srv = uqc.Server(ctx, 1 << 30, 2)
+    sh = wl.lattice_shells(3, 3)
+    D = wl.random_density(np.random.default_rng(2), sh.nbf, 3, 3.0)
+    Dn = D.copy()
+    Dn[0, 1] += 0.1
+    with pytest.raises(uqc.UqcError) as e:
+        srv.submit(sh, Dn, n_iter=2)
+    assert e.value.status == uqc.UQC_E_NOT_SYMMETRIC
+    with pytest.raises(uqc.UqcError) as e:
+        srv.submit(sh, D, n_iter=0)
+    assert e.value.status == uqc.UQC_E_ARG
+    t = srv.submit(sh, D, n_iter=2)
+    srv.drain()
+    out = srv.poll(t)
+    assert out is not None and out["n_iter"] == 2
+    srv.close()
