@@ -81,11 +81,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--workload", default="medium", choices=["medium", "mixed150", "large400", "serve"],
+                    help="medium (default, the benchmark line); mixed150 / large400: mixed vs FP64 accuracy and "
+                         "speed; serve: Poisson request stream through the continuous-batching server")
+    ap.add_argument("--nreq", type=int, default=32, help="serve: requests taken from the 512-request stream")
+    ap.add_argument("--oracle-quartets", type=int, default=4000, help="mixed150/large400: oracle sample size")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the Fock build would shard by "
               "bra-pair work lists with one all-reduce of J and K; not built).", file=sys.stderr)
         sys.exit(2)
+
+    if a.workload == "serve":
+        return bench_serve(a)
+    if a.workload in ("mixed150", "large400"):
+        return bench_mixed(a)
 
     import torch
     from paper_1303_4916_amd import uqc
@@ -186,6 +196,149 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(out), flush=True)
     B.close()
+    ctx.close()
+
+
+def _sample_quartets(nshell: int, n: int, seed: int) -> np.ndarray:
+    """Uniform sample of canonical shell quartets (a>=b, c>=d, ab>=cd)."""
+    rng = np.random.default_rng(seed)
+    npair = nshell * (nshell + 1) // 2
+    out = []
+    while len(out) < n:
+        p = rng.integers(0, npair, size=(4 * n, 2))
+        p.sort(axis=1)
+        for cd, ab in p:
+            a = int((np.sqrt(8 * ab + 1) - 1) // 2)
+            b = int(ab - a * (a + 1) // 2)
+            c = int((np.sqrt(8 * cd + 1) - 1) // 2)
+            d = int(cd - c * (c + 1) // 2)
+            out.append((a, b, c, d))
+            if len(out) == n:
+                break
+    return np.array(out, dtype=np.int32)
+
+
+def bench_mixed(a):
+    """Mixed precision (FP32 recursions, FP64 accumulation) vs the FP64 path on one system: full-build G and E2
+    errors, ERI-block errors of both precisions vs the oracle on a uniform sample of canonical quartets."""
+    import torch
+    from paper_1303_4916_amd import uqc
+    from paper_1303_4916_amd import workloads as wl
+    import oracle
+
+    w = wl.mixed150(ndens=1) if a.workload == "mixed150" else wl.large400(ndens=1)
+    ctx = uqc.Context(0)
+    t = time.perf_counter()
+    B = uqc.Basis(ctx, w.shells)
+    plan_ms = (time.perf_counter() - t) * 1e3
+    N = B.nbf
+    D = torch.from_numpy(w.densities[0]).cuda()
+    J = torch.empty((N, N), dtype=torch.float64, device="cuda")
+    K = torch.empty_like(J)
+    G = torch.empty_like(J)
+    res = {}
+    print("%s: N=%d, plan %.0f ms" % (w.name, N, plan_ms), file=sys.stderr, flush=True)
+    for name, opts in [("fp64", uqc.default_opts(tau=w.tau, timing=True)),
+                       ("mixed", uqc.default_opts(tau=w.tau, precision=uqc.MIXED, timing=True))]:
+        times = []
+        for rep in range(max(1, a.steps)):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = B.fock_build_ptr(D.data_ptr(), J.data_ptr(), K.data_ptr(), G.data_ptr(), opts)
+            times.append(time.perf_counter() - t)
+            print("  %s build %d: %.1f ms" % (name, rep, times[-1] * 1e3), file=sys.stderr, flush=True)
+        res[name] = {"ms": 1e3 * min(times), "E2": st.E2, "G": G.cpu().numpy().copy(), "quartets": st.quartets,
+                     "fp64_quartets": st.fp64_quartets, "flops": st.flops}
+    G64, Gm = res["fp64"]["G"], res["mixed"]["G"]
+    q = _sample_quartets(B.nshell, a.oracle_quartets, 31)
+    O = oracle.Basis(w.shells)
+    oracle.set_threads(min(os.cpu_count() or 1, 16))
+    e64 = em = ref_max = 0.0
+    b64 = B.eri_blocks(q, uqc.FP64)
+    bm = B.eri_blocks(q, uqc.MIXED)
+    for (qa, qb, qc, qd), x64, xm in zip(q, b64, bm):
+        r = O.eri(int(qa), int(qb), int(qc), int(qd))
+        e64 = max(e64, float(np.max(np.abs(x64 - r))))
+        em = max(em, float(np.max(np.abs(xm - r))))
+        ref_max = max(ref_max, float(np.max(np.abs(r))))
+    out = {
+        "metric": METRIC,
+        "value": res["mixed"]["quartets"] / (res["mixed"]["ms"] * 1e-3),
+        "unit": "shell quartets/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": 0,
+        "ms_per_step": res["mixed"]["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 recursions + f64 accumulation", "data": "synthetic",
+        "config": {"workload": w.name + (": 150 atoms, N=1650, first s K=6, tau=1e-12" if a.workload == "mixed150"
+                                         else ": 400 atoms, N=4400, K=3 on every shell, tau=1e-11"),
+                   "nbf": N, "tau": w.tau, "fp64_bound": 1e-5},
+        "plan_ms": plan_ms,
+        "fp64_build_ms": res["fp64"]["ms"], "mixed_build_ms": res["mixed"]["ms"],
+        "mixed_speedup_vs_fp64": res["fp64"]["ms"] / res["mixed"]["ms"],
+        "quartets_per_build": res["fp64"]["quartets"],
+        "mixed_fp64_routed_quartets": res["mixed"]["fp64_quartets"],
+        "E2_fp64": res["fp64"]["E2"], "abs_E2_error_mixed_vs_fp64_Eh": abs(res["mixed"]["E2"] - res["fp64"]["E2"]),
+        "G_frobenius_rel_error_mixed_vs_fp64": float(np.linalg.norm(Gm - G64) / np.linalg.norm(G64)),
+        "G_max_abs_error_mixed_vs_fp64": float(np.max(np.abs(Gm - G64))),
+        "oracle_sample": {"quartets": int(len(q)), "max_abs_eri_error_fp64": e64, "max_abs_eri_error_mixed": em,
+                          "max_abs_eri": ref_max, "sample": "uniform over canonical shell quartets, seed 31"},
+        "fp64_tflops_algorithmic": res["fp64"]["flops"] / (res["fp64"]["ms"] * 1e-3) / 1e12,
+    }
+    print(json.dumps(out), flush=True)
+    B.close()
+    ctx.close()
+
+
+def bench_serve(a):
+    """Poisson stream of Fock-build requests (mean 200 req/s, 4-120 atoms log-uniform, 8 iterations each) through
+    the continuous-batching server, FP64 and mixed side by side; per-request latency = finish - submit."""
+    from paper_1303_4916_amd import uqc
+    from paper_1303_4916_amd import workloads as wl
+
+    stream = wl.stream(512)[:a.nreq]
+    ctx = uqc.Context(0)
+    out = {"metric": METRIC, "unit": "requests/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic",
+           "config": {"workload": "poisson200_4to120atoms_8iter: first %d of 512 requests" % len(stream),
+                      "budget_GiB": 64, "slots": 16}}
+    for prec_name, prec in [("fp64", uqc.FP64), ("mixed", uqc.MIXED)]:
+        srv = uqc.Server(ctx, 64 << 30, 16)
+        t0 = time.perf_counter()
+        tickets = []
+        for r in stream:
+            now = time.perf_counter() - t0
+            if r.arrival_s > now:
+                time.sleep(r.arrival_s - now)
+            tickets.append(srv.submit(r.shells, r.D0, n_iter=8, ncol=max(1, r.natoms // 2), eps=0.05,
+                                      seed=4000 + r.rid, opts=uqc.default_opts(tau=1e-12, precision=prec)))
+        done = {}
+        last = time.perf_counter()
+        while len(done) < len(tickets):
+            for tk in tickets:
+                if tk not in done:
+                    res = srv.poll(tk, want_matrices=False)
+                    if res is not None:
+                        done[tk] = res
+            if time.perf_counter() - last > 10:
+                print("serve %s: %d of %d requests done after %.0f s" % (prec_name, len(done), len(tickets),
+                                                                       time.perf_counter() - t0),
+                      file=sys.stderr, flush=True)
+                last = time.perf_counter()
+            time.sleep(0.002)
+        wall = time.perf_counter() - t0
+        lat, q, iters = [], 0, 0
+        for tk in tickets:
+            res = done[tk]
+            lat.append(res["finish_ms"] - res["submit_ms"])
+            q += res["quartets"]
+            iters += res["n_iter"]
+        srv.close()
+        out[prec_name] = {"wall_s": wall, "requests_per_s": len(stream) / wall, "fock_builds_per_s": iters / wall,
+                          "quartets_per_s": q / wall, "p50_latency_ms": float(np.percentile(lat, 50)),
+                          "p99_latency_ms": float(np.percentile(lat, 99))}
+    out["value"] = out["fp64"]["quartets_per_s"]
+    out["unit"] = "shell quartets/s"
+    out["mixed_speedup_vs_fp64"] = out["fp64"]["wall_s"] / out["mixed"]["wall_s"]
+    print(json.dumps(out), flush=True)
     ctx.close()
 
 

@@ -27,7 +27,7 @@ void uqc_fock_opts_default(uqc_fock_opts* o) {
     if (!o) return;
     o->schwarz_tau = 1e-12;
     o->precision = UQC_FP64;
-    o->fp64_bound = 1e-3;
+    o->fp64_bound = 1e-5;
     o->timing = 0;
 }
 
@@ -197,7 +197,10 @@ static uqc_status upload_bin(Bin& b) {
     return UQC_OK;
 }
 
-static int decade(double q) { return q > 0 ? (int)std::floor(std::log10(q)) : -400; }
+// Decade of a pair bound, rounded up near powers of ten, and decade of a threshold, rounded down: every pair with
+// Q >= t then has decade(Q) >= decade_floor(t), whatever the rounding of log10.
+static int decade(double q) { return q > 0 ? (int)std::floor(std::log10(q) + 1e-9) : -400; }
+static int decade_floor(double t) { return t > 0 ? (int)std::floor(std::log10(t) - 1e-9) : -400; }
 
 int Bin::first_below(int dec) const {
     for (const auto& x : bstart)
@@ -509,7 +512,7 @@ uqc_status uqc_schwarz(const uqc_basis* b, double* Q) {
 // and, if X == Y, j <= i.  Ket bins are ordered by decade of Q (descending), so the kets that can pass form a prefix
 // ending one decade below the decade of tau / Q_i; the kernels apply the exact test per lane.  In mixed precision
 // the FP64 task takes the kets with Q_i Q_j > bound and the FP32-recursion task those with Q_i Q_j <= bound; the
-// decades around the split are scanned by both tasks with complementary per-lane tests.
+// decade holding the split is scanned by both tasks with complementary per-lane tests.
 void uqc::plan_account(Plan& p) {
     p.quartets = p.prim_quartets = p.fp64_quartets = 0;
     p.flops = 0;
@@ -559,14 +562,14 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
             for (int i = 0; i < bx.np; ++i) {
                 const double qi = bx.Q[i];
                 int h = by.np;
-                if (tau > 0) h = qi > 0 ? by.first_below(decade(tau / qi) - 1) : 0;
+                if (tau > 0) h = qi > 0 ? by.first_below(decade_floor(tau / qi)) : 0;
                 if (X == Y) h = std::min(h, i + 1);
                 int h64 = h, l32 = h;
                 if (mixed) {
                     if (qi > 0) {
-                        const int dsplit = decade(bound / qi);
-                        h64 = std::min(h, by.first_below(dsplit - 1));
-                        l32 = std::min(h, by.first_at_or_below(dsplit + 1));
+                        // FP64 needs Q_j > bound / qi, FP32 needs Q_j <= bound / qi
+                        h64 = std::min(h, by.first_below(decade_floor(bound / qi)));
+                        l32 = std::min(h, by.first_at_or_below(decade(bound / qi)));
                     } else {
                         h64 = 0;
                         l32 = 0;
