@@ -27,6 +27,68 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "shell quartets/s and Fock builds/s at ≤1e-6 Eh vs FP64; p50/p99 build latency"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_medium60_fp64.json")
+
+
+def kernel_sources_sha256() -> str:
+    """Hash of every source the device kernels are built from (traffic counters are only valid for these)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1303_4916_amd", "csrc")
+    for d in (csrc, os.path.join(csrc, "generated")):
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".h", ".hip", ".cpp", ".py")):
+                h.update(f.encode())
+                h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_write_csv: str, out: str, cmd: str):
+    """Per-kernel HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch), each scaled
+    by the counter's reading for a plain 1 GiB device-to-device copy (bytes known)."""
+    import csv
+
+    def per_kernel(path, counter):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            k = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("uqc::", "")
+            v = acc.setdefault(k, [0.0, set()])
+            v[0] += float(r["Counter_Value"])
+            v[1].add(r["Dispatch_Id"])
+        return {k: (v[0], len(v[1])) for k, v in acc.items()}
+
+    cf, cw = per_kernel(copy_fetch_csv, "FETCH_SIZE"), per_kernel(copy_write_csv, "WRITE_SIZE")
+    ck = max(cf, key=lambda k: cf[k][0])
+    gib_kib = float(1 << 20)
+    f_scale = gib_kib / (cf[ck][0] / cf[ck][1])
+    w_scale = gib_kib / (cw[ck][0] / cw[ck][1]) if ck in cw else 1.0
+    kf, kw = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    kernels = {}
+    for k in kf:
+        fb = kf[k][0] / kf[k][1] * f_scale * 1024
+        wb = (kw[k][0] / kw[k][1] * w_scale * 1024) if k in kw else 0.0
+        kernels[k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "launches": kf[k][1]}
+    doc = {"command": cmd, "copy_kernel": ck, "fetch_scale": f_scale, "write_scale": w_scale,
+           "kernel_sources_sha256": kernel_sources_sha256(), "kernels": kernels}
+    with open(out, "w") as f:
+        json.dump(doc, f, indent=1, sort_keys=True)
+    return doc
+
+
+def traffic_for(kernel_key: str):
+    """HBM bytes per launch of a kernel from the committed counter summary, or None if the kernels changed since."""
+    try:
+        doc = json.load(open(TRAFFIC_FILE))
+    except Exception:
+        return None
+    if doc.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    k = doc["kernels"].get(kernel_key)
+    if not k:
+        return None
+    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 2.4 GHz x 128 FP64 FLOP/clk/CU
 CLASS_NAME = "spd"
 
@@ -37,6 +99,13 @@ def class_name(cid: int) -> str:
     digits = [c // 1000, (c // 100) % 10, (c // 10) % 10, c % 10]
     return "(" + "".join(CLASS_NAME[d] for d in digits[:2]) + "|" + "".join(CLASS_NAME[d] for d in digits[2:]) + \
            ")" + ("-mixed" if mixed else "")
+
+
+def dom_kernel_key(cid: int) -> str:
+    """rocprofv3 short name of the FP64/mixed class kernel with this class id."""
+    c = cid % 10000
+    ls = [c // 1000, (c // 100) % 10, (c // 10) % 10, c % 10]
+    return "k_digest<%d, %d, %d, %d, %s>" % (ls[0], ls[1], ls[2], ls[3], "true" if cid >= 10000 else "false")
 
 
 def cpu_baseline(w, target_s: float = 15.0):
@@ -81,12 +150,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--workload", default="medium", choices=["medium", "mixed150", "large400", "serve"],
+    ap.add_argument("--workload", default="medium", choices=["medium", "mixed150", "large400", "serve", "copy"],
                     help="medium (default, the benchmark line); mixed150 / large400: mixed vs FP64 accuracy and "
                          "speed; serve: Poisson request stream through the continuous-batching server")
     ap.add_argument("--nreq", type=int, default=32, help="serve: requests taken from the 512-request stream")
     ap.add_argument("--oracle-quartets", type=int, default=4000, help="mixed150/large400: oracle sample size")
+    ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                         "COPY_WRITE_CSV", "CMD"),
+                    help="write the per-kernel traffic summary from rocprofv3 counter CSVs and exit")
     a = ap.parse_args()
+    if a.summarize_pmc:
+        summarize_pmc(*a.summarize_pmc[:4], TRAFFIC_FILE, a.summarize_pmc[4])
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the Fock build would shard by "
               "bra-pair work lists with one all-reduce of J and K; not built).", file=sys.stderr)
@@ -94,6 +169,8 @@ def main():
 
     if a.workload == "serve":
         return bench_serve(a)
+    if a.workload == "copy":
+        return bench_copy(a)
     if a.workload in ("mixed150", "large400"):
         return bench_mixed(a)
 
@@ -172,7 +249,7 @@ def main():
         "eri_kernel_ms_per_build": eri_ms,
         "E2_first": E2s[0],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic_for(dom_kernel_key(dom)),
                      "kernel": "k_digest " + class_name(dom), "kernel_avg_ms": dom_avg_ms,
                      "kernel_flops_per_launch": cls_flops[dom]},
         "classes": {class_name(k): {"ms": cls_ms[k] / a.steps, "quartets": cls_q[k],
@@ -286,6 +363,22 @@ def bench_mixed(a):
     print(json.dumps(out), flush=True)
     B.close()
     ctx.close()
+
+
+def bench_copy(a):
+    """Reference for hardware traffic counters: a plain device-to-device copy of exactly 1 GiB, three times."""
+    import torch
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / 3
+    print(json.dumps({"workload": "copy 1 GiB", "bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                      "GBps_read_plus_write": 2 * (1 << 30) / dt / 1e9}), flush=True)
 
 
 def bench_serve(a):

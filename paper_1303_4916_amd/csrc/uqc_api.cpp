@@ -32,9 +32,10 @@ void uqc_fock_opts_default(uqc_fock_opts* o) {
 }
 
 // ---------------------------------------------------------------------------------------------- Boys table
-// F_n(T_g), n = 0..16, T_g = g/8 for g = 0..320, from Gauss-Legendre quadrature (long double, 96 nodes) of the
-// defining integral F_n(T) = int_0^1 t^{2n} exp(-T t^2) dt; the integrand is entire, so the rule converges to the
-// working precision for T <= 40.
+// F_n(T_g), n = 0..16, and exp(-T_g), T_g = g/8 for g = 0..320; F_n from Gauss-Legendre quadrature (long double,
+// 96 nodes) of the
+// defining integral F_n(T) = int_0^1 t^{2n} exp(-T t^2) dt; the integrand is entire, so the rule converges to
+// the working precision for T <= 40.
 static void legendre_nodes(int n, std::vector<long double>& x, std::vector<long double>& w) {
     x.resize(n);
     w.resize(n);
@@ -72,7 +73,8 @@ static void build_boys_table(std::vector<double>& tab) {
     tab.assign((size_t)kBoysNg * kBoysNm, 0.0);
     for (int g = 0; g < kBoysNg; ++g) {
         const long double T = (long double)g / kBoysGridPerUnit;
-        for (int n = 0; n < kBoysNm; ++n) {
+        tab[(size_t)g * kBoysNm + kBoysExpCol] = (double)std::exp(-T);
+        for (int n = 0; n < kBoysExpCol; ++n) {
             long double s = 0;
             for (size_t i = 0; i < x.size(); ++i) {
                 const long double t = 0.5L * (x[i] + 1);  // map [-1, 1] -> [0, 1]
@@ -105,10 +107,18 @@ uqc_status uqc_init(int device, void* hip_stream, uqc_ctx** out) {
         }
         c->own_stream = true;
     }
-    std::vector<double> tab;
-    build_boys_table(tab);
-    std::vector<float> tab32(tab.size());
-    for (size_t i = 0; i < tab.size(); ++i) tab32[i] = (float)tab[i];
+    std::vector<double> full;
+    build_boys_table(full);
+    std::vector<float> tab32(full.size());
+    for (size_t i = 0; i < full.size(); ++i) tab32[i] = (float)full[i];
+    // per-order slices for the FP64 evaluation
+    std::vector<double> tab((size_t)(kBoysLmax + 1) * kBoysNg * kBoysRow);
+    for (int L = 0; L <= kBoysLmax; ++L)
+        for (int g = 0; g < kBoysNg; ++g) {
+            double* row = tab.data() + ((size_t)L * kBoysNg + g) * kBoysRow;
+            for (int k = 0; k < 9; ++k) row[k] = full[(size_t)g * kBoysNm + L + k];
+            row[9] = full[(size_t)g * kBoysNm + kBoysExpCol];
+        }
     if (hipMalloc(&c->boys64, tab.size() * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->boys32, tab32.size() * sizeof(float)) != hipSuccess) {
         uqc_finalize(c);

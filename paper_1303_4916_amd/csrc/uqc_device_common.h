@@ -17,28 +17,41 @@ __host__ __device__ constexpr double comp_factor(int l, int c) {
 constexpr double kPi = 3.14159265358979323846;
 
 // ------------------------------------------------------------------------------------------------ Boys function
-// F_m(T) = int_0^1 t^{2m} exp(-T t^2) dt.  For T < 40: Taylor series of order 8 around the nearest grid point
-// T_g = g/8 (|T - T_g| <= 1/16, truncation error < 1e-16 relative), using dF_m/dT = -F_{m+1}, for the highest order
-// needed, then the downward recursion F_m = (2T F_{m+1} + exp(-T)) / (2m+1).  For T >= 40: F_0 = sqrt(pi/T)/2
-// (erf(sqrt(T)) = 1 to double precision) and the upward recursion F_{m+1} = ((2m+1) F_m - exp(-T)) / (2T).
+// F_m(T) = int_0^1 t^{2m} exp(-T t^2) dt, returned multiplied by `pref` (`tab`: the per-order FP64 slices).
+// For T < 40: Taylor series of order 8
+// around the nearest grid point T_g = g/8 (|d| = |T_g - T| <= 1/16, truncation error < 1e-16 relative), using
+// dF_m/dT = -F_{m+1}, for the highest order needed; exp(-T) = exp(-T_g) exp(d) with exp(-T_g) tabulated and exp(d)
+// from its Taylor series to order 9 (truncation < 3e-19); then the downward recursion
+// F_m = (2T F_{m+1} + exp(-T)) / (2m+1).  For T >= 40: F_0 = sqrt(pi/T)/2 (erf(sqrt(T)) = 1 to double precision)
+// and the upward recursion F_{m+1} = ((2m+1) F_m - exp(-T)) / (2T).
 template <int L>
-__device__ __forceinline__ void boys64(double T, const double* __restrict__ tab, double* F) {
+__device__ __forceinline__ void boys64(double T, double pref, const double* __restrict__ tab, double* F) {
     if (T < (double)kBoysTmax) {
         const int g = (int)(T * (double)kBoysGridPerUnit + 0.5);
         const double d = (double)g * (1.0 / kBoysGridPerUnit) - T;  // exact grid point
-        const double* r = tab + g * kBoysNm + L;
-        double p = r[8];
-        p = fma(p, d * (1.0 / 8.0), r[7]);
-        p = fma(p, d * (1.0 / 7.0), r[6]);
-        p = fma(p, d * (1.0 / 6.0), r[5]);
-        p = fma(p, d * (1.0 / 5.0), r[4]);
-        p = fma(p, d * (1.0 / 4.0), r[3]);
-        p = fma(p, d * (1.0 / 3.0), r[2]);
-        p = fma(p, d * (1.0 / 2.0), r[1]);
-        p = fma(p, d, r[0]);
-        F[L] = p;
+        const double2* row = reinterpret_cast<const double2*>(tab + ((size_t)L * kBoysNg + g) * kBoysRow);
+        const double2 r01 = row[0], r23 = row[1], r45 = row[2], r67 = row[3], r8e = row[4];
+        double p = r8e.x;
+        p = fma(p, d * (1.0 / 8.0), r67.y);
+        p = fma(p, d * (1.0 / 7.0), r67.x);
+        p = fma(p, d * (1.0 / 6.0), r45.y);
+        p = fma(p, d * (1.0 / 5.0), r45.x);
+        p = fma(p, d * (1.0 / 4.0), r23.y);
+        p = fma(p, d * (1.0 / 3.0), r23.x);
+        p = fma(p, d * (1.0 / 2.0), r01.y);
+        p = fma(p, d, r01.x);
+        F[L] = p * pref;
         if constexpr (L > 0) {
-            const double e = exp(-T);
+            double x = fma(d, 1.0 / 9.0, 1.0);
+            x = fma(x, d * (1.0 / 8.0), 1.0);
+            x = fma(x, d * (1.0 / 7.0), 1.0);
+            x = fma(x, d * (1.0 / 6.0), 1.0);
+            x = fma(x, d * (1.0 / 5.0), 1.0);
+            x = fma(x, d * (1.0 / 4.0), 1.0);
+            x = fma(x, d * (1.0 / 3.0), 1.0);
+            x = fma(x, d * (1.0 / 2.0), 1.0);
+            x = fma(x, d, 1.0);
+            const double e = r8e.y * x * pref;
             const double t2 = T + T;
 #pragma unroll
             for (int m = L - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (2 * m + 1));
@@ -52,7 +65,28 @@ __device__ __forceinline__ void boys64(double T, const double* __restrict__ tab,
 #pragma unroll
             for (int m = 0; m < L; ++m) F[m + 1] = fma((double)(2 * m + 1), F[m], -e) * h;
         }
+#pragma unroll
+        for (int m = 0; m <= L; ++m) F[m] *= pref;
     }
+}
+
+// 1/x and 1/sqrt(x) for positive normal x: hardware approximations refined by Newton steps (two for the
+// reciprocal, two for the square root) to full double precision.
+__device__ __forceinline__ double rcp64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsqrt64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    double t = fma(-h * y, y, 0.5);
+    y = fma(y, t, y);
+    t = fma(-h * y, y, 0.5);
+    return fma(y, t, y);
 }
 
 // FP32 variant (mixed mode, T <= 30 only): Taylor order 5 around the same grid points (truncation < 1e-10

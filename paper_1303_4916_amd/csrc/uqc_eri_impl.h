@@ -50,12 +50,12 @@ __device__ __forceinline__ void accumulate(const BinDev& B, int bra, const BinDe
             const double o2z = bp[F_O2Z * fsb];
 
             const double ze = zeta + eta;
-            const double inv = 1.0 / ze;
+            const double inv = rcp64(ze);
             const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;
             const double rho = zeta * eta * inv;
             const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
             const double roz = eta * inv, roe = zeta * inv;
-            const double pref = prefb * prefk * sqrt(inv);
+            const double pref = prefb * prefk * rsqrt64(ze);
             if constexpr (!MIXED) {
                 PrimGeom<double> g;
                 g.PA[0] = PAx; g.PA[1] = PAy; g.PA[2] = PAz;
@@ -64,9 +64,7 @@ __device__ __forceinline__ void accumulate(const BinDev& B, int bra, const BinDe
                 g.WQ[0] = roe * PQx; g.WQ[1] = roe * PQy; g.WQ[2] = roe * PQz;
                 g.o2z = o2z; g.roz = roz; g.o2e = o2e; g.roe = roe; g.o2ze = 0.5 * inv;
                 double F[C::L + 1];
-                boys64<C::L>(T, boys64tab, F);
-#pragma unroll
-                for (int m = 0; m <= C::L; ++m) F[m] *= pref;
+                boys64<C::L>(T, pref, boys64tab, F);
                 C::template vrr<double>(F, g, acc);
             } else {
                 PrimGeom<float> g;
@@ -84,9 +82,9 @@ __device__ __forceinline__ void accumulate(const BinDev& B, int bra, const BinDe
                     for (int m = 0; m <= C::L; ++m) F[m] *= pf;
                 } else {
                     double Fd[C::L + 1];
-                    boys64<C::L>(T, boys64tab, Fd);
+                    boys64<C::L>(T, pref, boys64tab, Fd);
 #pragma unroll
-                    for (int m = 0; m <= C::L; ++m) F[m] = (float)(Fd[m] * pref);
+                    for (int m = 0; m <= C::L; ++m) F[m] = (float)Fd[m];
                 }
                 C::template vrr<float>(F, g, acc);
             }

@@ -11,7 +11,12 @@ constexpr int kMaxK = 16;              // maximum contraction depth
 constexpr int kBoysGridPerUnit = 8;    // Boys Taylor grid: T_g = g / 8 (exact in binary, same points in FP32/FP64)
 constexpr int kBoysTmax = 40;          // grid covers [0, 40); asymptotic form beyond
 constexpr int kBoysNg = kBoysTmax * kBoysGridPerUnit + 1;
-constexpr int kBoysNm = 17;            // F_0 .. F_16 stored per grid point (m <= 8 plus Taylor order 8)
+constexpr int kBoysNm = 18;            // per grid point: F_0 .. F_16 (m <= 8 plus Taylor order 8), then exp(-T_g)
+constexpr int kBoysExpCol = 17;
+// Device layout of the FP64 table: one slice per highest order L = 0..8, each row holding F_L .. F_{L+8} and
+// exp(-T_g) (10 doubles, 80 bytes, 16-byte aligned), so a Boys evaluation reads one row with five 16-byte loads.
+constexpr int kBoysRow = 10;
+constexpr int kBoysLmax = 8;
 constexpr int kBoysTmax32 = 30;        // FP32 evaluation limit in mixed mode
 constexpr int kNumClasses = 21;
 

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_boys(int prec, int n, const double* 
     const double t = T[x];
     if (prec == 0 || t > (double)kBoysTmax32) {
         double F[L + 1];
-        boys64<L>(t, b64, F);
+        boys64<L>(t, 1.0, b64, F);
         for (int m = 0; m <= L; ++m) out[(size_t)x * (L + 1) + m] = F[m];
     } else {
         float F[L + 1];
