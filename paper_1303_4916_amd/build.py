@@ -40,16 +40,26 @@ def classes():
     return out
 
 
+def _team_classes():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("gen_eri", os.path.join(CSRC, "gen_eri.py"))
+    g = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(g)
+    return set(g.TEAM_CLASSES)
+
+
 def _units():
     headers = [os.path.join(CSRC, h) for h in ("uqc_internal.h", "uqc_device_common.h", "uqc_eri_impl.h",
                                                "uqc_api_internal.h")]
     headers += [os.path.join(GEN, "eri_classes.h"), os.path.join(GEN, "eri_flops.h"),
                 os.path.join(ROOT, "include", "uqc.h")]
     units = []
+    team = _team_classes()
+    headers = headers + [os.path.join(CSRC, "uqc_eri_team.h"), os.path.join(GEN, "eri_team.h")]
     for i, (la, lb, lc, ld) in enumerate(classes()):
         units.append((os.path.join(CSRC, "uqc_eri_class.hip"), os.path.join(OBJ, "eri_class_%02d.o" % i),
                       ["-DUQC_CLASS_ID=%d" % i, "-DUQC_LA=%d" % la, "-DUQC_LB=%d" % lb, "-DUQC_LC=%d" % lc,
-                       "-DUQC_LD=%d" % ld], headers))
+                       "-DUQC_LD=%d" % ld, "-DUQC_TEAM=%d" % (1 if (la, lb, lc, ld) in team else 0)], headers))
     for src in ("uqc_kernels.hip", "uqc_api.cpp", "uqc_serve.cpp"):
         units.append((os.path.join(CSRC, src), os.path.join(OBJ, os.path.splitext(src)[0] + ".o"), [], headers))
     # heaviest classes first so they start early

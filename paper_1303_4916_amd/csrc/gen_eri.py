@@ -25,6 +25,7 @@ Usage: gen_eri.py OUTDIR   (writes eri_classes.h and eri_flops.json)
 """
 from __future__ import annotations
 
+import itertools
 import json
 import os
 import sys
@@ -269,6 +270,175 @@ def gen_hrr(c, es, fs):
     return lines, flops
 
 
+
+# ------------------------------------------------------------------------------------------------------------------
+# Team evaluation of the largest classes.  The six permutations of the Cartesian axes map the set of [e0|f0]
+# targets (and of (ab|cd) outputs) onto itself.  A team of six lanes evaluates one contracted quartet: lane p runs
+# the recursion for one representative of every orbit with its geometry vectors relabelled by p, which yields the
+# true integrals of the permuted components.  Every lane runs identical straight-line code, each holds about a
+# sixth of the accumulators, and the horizontal recursion reads the values it needs from the other lanes.
+#   relabel:  P(t, p)_i = t[p[i]]           (geometry seen by lane p: V_lane = P(V, p))
+#   inverse:  Q(t, p)[p[i]] = t[i]          (lane p's representative r stands for the true component Q(r, p))
+#   Q(Q(t, pi), p) = Q(t, p o pi) with (p o pi)[i] = p[pi[i]]
+# ------------------------------------------------------------------------------------------------------------------
+PERMS = list(itertools.permutations(range(3)))
+TEAM_CLASSES = [(2, 0, 2, 0), (2, 1, 2, 1), (2, 2, 1, 1), (2, 2, 2, 0), (2, 2, 2, 1), (2, 2, 2, 2)]
+TEAM_SIZE = 6
+
+
+def perm_q(t, p):
+    u = [0, 0, 0]
+    for i in range(3):
+        u[p[i]] = t[i]
+    return tuple(u)
+
+
+def perm_compose(p, q):
+    return tuple(p[q[i]] for i in range(3))
+
+
+def binom(n, k):
+    return [[1], [1, 1], [1, 2, 1]][n][k]
+
+
+def orbit_rep(x, act):
+    """x: tuple of component triples; returns (representative, perm index pi with act(rep, pi) == x)."""
+    orb = [(tuple(act(t, p) for t in x), ip) for ip, p in enumerate(PERMS)]
+    rep = min(o for o, _ in orb)
+    # find pi with Q(rep, pi) == x
+    for ip, p in enumerate(PERMS):
+        if tuple(act(t, p) for t in rep) == x:
+            return rep, ip
+    raise AssertionError
+
+
+def gen_team(c):
+    la, lb, lc, ld = c
+    v = Vrr(la, lb, lc, ld)
+    es, fs = v.targets()
+    targets = [(e, f) for e in es for f in fs]
+    reps = sorted({orbit_rep(t, perm_q)[0] for t in targets})
+    rep_idx = {r: i for i, r in enumerate(reps)}
+    acc_lines = []
+    for i, (e, f) in enumerate(reps):
+        nm = v.get(e, f, 0)
+        acc_lines.append("acc[%d] += (double)%s;" % (i, nm))
+    vrr_lines = interleave(v, acc_lines)
+    # outputs and their orbits
+    ca, cb, cc, cd = comps(la), comps(lb), comps(lc), comps(ld)
+    outs = [(a, b, cx, d) for a in ca for b in cb for cx in cc for d in cd]
+    out_reps = sorted({orbit_rep(o, perm_q)[0] for o in outs})
+    hl = []       # horizontal recursion + digest lines
+    leaf = {}     # (rep index, perm index) -> name
+
+    def get_leaf(e, f):
+        r, ip = orbit_rep((e, f), perm_q)
+        if r == (e, f):
+            ip = 0  # identity: the lane's own accumulator
+        key = (rep_idx[r], ip)
+        if key not in leaf:
+            nm = "lf%d_%d" % key
+            if ip == 0:
+                hl.append("const double %s = acc[%d];" % (nm, key[0]))
+            else:
+                hl.append("const double %s = fetch(acc[%d], src[%d]);" % (nm, key[0], ip))
+            leaf[key] = nm
+        return leaf[key]
+
+    mono = {}
+
+    def get_mono(kind, m):
+        if sum(m) == 0:
+            return None
+        key = (kind, m)
+        if key not in mono:
+            nm = "%s%d%d%d" % ((kind,) + m)
+            fac = []
+            for i, ax in enumerate("xyz"):
+                fac += ["%s%s" % (kind, ax)] * m[i]
+            hl.append("const double %s = %s;" % (nm, " * ".join(fac)))
+            mono[key] = nm
+        return mono[key]
+
+    half = {}
+    flops = [0]
+
+    def get_half(e, cx, d):
+        key = (e, cx, d)
+        if key in half:
+            return half[key]
+        terms = []
+        for kx in range(d[0] + 1):
+            for ky in range(d[1] + 1):
+                for kz in range(d[2] + 1):
+                    k = (kx, ky, kz)
+                    f = tuple(cx[i] + k[i] for i in range(3))
+                    coef = binom(d[0], kx) * binom(d[1], ky) * binom(d[2], kz)
+                    mnm = get_mono("CD", tuple(d[i] - k[i] for i in range(3)))
+                    terms.append((coef, mnm, get_leaf(e, f)))
+        nm = "h%d" % len(half)
+        expr = None
+        for coef, mnm, lf in terms:
+            t = lf if mnm is None else "%s * %s" % (mnm, lf)
+            if coef != 1:
+                t = "%d.0 * %s" % (coef, t) if mnm is None else "(%d.0 * %s) * %s" % (coef, mnm, lf)
+            expr = t if expr is None else "%s + %s" % (expr, t)
+            flops[0] += 2
+        hl.append("const double %s = %s;" % (nm, expr))
+        half[key] = nm
+        return nm
+
+    na, nb, nc, nd = ncart(la), ncart(lb), ncart(lc), ncart(ld)
+    ia, ib, ic, idd = ({t: i for i, t in enumerate(x)} for x in (ca, cb, cc, cd))
+    masks = []
+    for o in out_reps:
+        a, b, cx, d = o
+        terms = []
+        for kx in range(b[0] + 1):
+            for ky in range(b[1] + 1):
+                for kz in range(b[2] + 1):
+                    k = (kx, ky, kz)
+                    e = tuple(a[i] + k[i] for i in range(3))
+                    coef = binom(b[0], kx) * binom(b[1], ky) * binom(b[2], kz)
+                    mnm = get_mono("AB", tuple(b[i] - k[i] for i in range(3)))
+                    terms.append((coef, mnm, get_half(e, cx, d)))
+        expr = None
+        for coef, mnm, hn in terms:
+            t = hn if mnm is None else "%s * %s" % (mnm, hn)
+            if coef != 1:
+                t = "%d.0 * %s" % (coef, t)
+            expr = t if expr is None else "%s + %s" % (expr, t)
+            flops[0] += 2
+        # owners: one lane per coset of the stabiliser
+        stab = [ip for ip, p in enumerate(PERMS) if tuple(perm_q(t, p) for t in o) == o]
+        mask = 0
+        for ip, p in enumerate(PERMS):
+            coset = [PERMS.index(perm_compose(p, PERMS[s])) for s in stab]
+            if ip == min(coset):
+                mask |= 1 << ip
+        masks.append(mask)
+        i, j, k, l = ia[a], ib[b], ic[cx], idd[d]
+        wexpr = "w" if mask == (1 << TEAM_SIZE) - 1 else "(((%d >> pidx) & 1) ? w : 0.0)" % mask
+        hl.append("{ const double x = (%s) * %s;" % (expr, wexpr))
+        hl.append("  jab[%d] = fma(x, dcd[%d], jab[%d]); jcd[%d] = fma(x, dab[%d], jcd[%d]);"
+                  % (i * nb + j, k * nd + l, i * nb + j, k * nd + l, i * nb + j, k * nd + l))
+        hl.append("  kac[%d] = fma(x, dbd[%d], kac[%d]); kad[%d] = fma(x, dbc[%d], kad[%d]);"
+                  % (i * nc + k, j * nd + l, i * nc + k, i * nd + l, j * nc + k, i * nd + l))
+        hl.append("  kbc[%d] = fma(x, dad[%d], kbc[%d]); kbd[%d] = fma(x, dac[%d], kbd[%d]); }"
+                  % (j * nc + k, i * nd + l, j * nc + k, j * nd + l, i * nc + k, j * nd + l))
+    return {"vrr": vrr_lines, "nrep": len(reps), "reps": reps, "out_reps": out_reps, "hrr_digest": hl,
+            "masks": masks, "v": v, "hrr_flops": flops[0]}
+
+
+def perm_comp_table():
+    """kPermComp[l][p][k]: index in the shell of true component Q(comps(l)[k], p)."""
+    rows = []
+    for l in range(3):
+        cl = comps(l)
+        idx = {t: i for i, t in enumerate(cl)}
+        rows.append([[idx[perm_q(t, p)] for t in cl] + [0] * (6 - len(cl)) for p in PERMS])
+    return rows
+
 def setup_flops(L):
     """Per-primitive-quartet set-up outside the recursion: zeta+eta, 1/(zeta+eta) (counted as 1), rho, PQ, T,
     WP, WQ, recursion constants, prefactor with sqrt (counted as 1), Boys (Taylor of order 7 at F_L: 7 mul +
@@ -359,12 +529,72 @@ def main(outdir):
     _write(os.path.join(outdir, "eri_classes.h"), "\n".join(hdr) + "\n")
     # frozen FLOP model, also as a C table (class order = generation order)
     lines = ["// Generated by gen_eri.py: algorithmic FLOPs per primitive quartet and per contracted quartet.",
-             "#pragma once", "static const double kClassFlopsPrim[%d] = {" % len(table)]
+             "#pragma once", "static constexpr double kClassFlopsPrim[%d] = {" % len(table)]
     lines.append(", ".join("%d" % table[cname(c)]["f_prim"] for c in classes()) + "};")
-    lines.append("static const double kClassFlopsContr[%d] = {" % len(table))
+    lines.append("static constexpr double kClassFlopsContr[%d] = {" % len(table))
     lines.append(", ".join("%d" % table[cname(c)]["f_contr"] for c in classes()) + "};")
+    lines.append("// 1 where the Fock-build kernel of the class is the six-lane team kernel (10 ket pairs per wavefront)")
+    lines.append("static constexpr int kClassTeam[%d] = {%s};" % (len(table), ", ".join(
+        "1" if c in TEAM_CLASSES else "0" for c in classes())))
     _write(os.path.join(outdir, "eri_flops.h"), "\n".join(lines) + "\n")
     _write(os.path.join(outdir, "eri_flops.json"), json.dumps(table, indent=1, sort_keys=True) + "\n")
+    # team classes
+    th = ["// Generated by gen_eri.py: six-lane team evaluation of the largest classes.  Do not edit.", "#pragma once",
+          ""]
+    pc = perm_comp_table()
+    th.append("static constexpr int kPermAxes[6][3] = {%s};" % ", ".join(
+        "{%d, %d, %d}" % p for p in PERMS))
+    th.append("static constexpr int kPermCompose[6][6] = {%s};" % ", ".join(
+        "{%s}" % ", ".join(str(PERMS.index(perm_compose(p, q))) for q in PERMS) for p in PERMS))
+    th.append("static constexpr int kPermComp[3][6][6] = {%s};" % ", ".join(
+        "{%s}" % ", ".join("{%s}" % ", ".join(str(x) for x in row) for row in pc[l]) for l in range(3)))
+    th.append("")
+    for c in TEAM_CLASSES:
+        t = gen_team(c)
+        v = t["v"]
+        L = sum(c)
+        th.append("// class (%s%s|%s%s): %d orbit representatives of %d targets, %d representative outputs"
+                  % (LET[c[0]], LET[c[1]], LET[c[2]], LET[c[3]], t["nrep"], len(v.targets()[0]) * len(v.targets()[1]),
+                     len(t["out_reps"])))
+        th.append("template <> struct TeamClass<%d, %d, %d, %d> {" % c)
+        th.append("  static constexpr int L = %d;" % L)
+        th.append("  static constexpr int NREP = %d;" % t["nrep"])
+        th.append("  static constexpr int NA = %d, NB = %d, NC = %d, ND = %d;" % tuple(ncart(x) for x in c))
+        th.append("  template <typename T>")
+        th.append("  __device__ static __forceinline__ void vrr(const T* __restrict__ F, const PrimGeom<T>& g, "
+                  "double* __restrict__ acc) {")
+        th.append("    const T PAx = g.PA[0], PAy = g.PA[1], PAz = g.PA[2];")
+        th.append("    const T WPx = g.WP[0], WPy = g.WP[1], WPz = g.WP[2];")
+        th.append("    const T QCx = g.QC[0], QCy = g.QC[1], QCz = g.QC[2];")
+        th.append("    const T WQx = g.WQ[0], WQy = g.WQ[1], WQz = g.WQ[2];")
+        for m in range(L + 1):
+            th.append("    const T F%d = F[%d];" % (m, m))
+        for (kind, k) in sorted(v.used_consts):
+            if kind == "oz":
+                th.append("    const T oz%d = T(%d) * g.o2z, ozr%d = oz%d * g.roz;" % (k, k, k, k))
+            elif kind == "oe":
+                th.append("    const T oe%d = T(%d) * g.o2e, oer%d = oe%d * g.roe;" % (k, k, k, k))
+            else:
+                th.append("    const T oze%d = T(%d) * g.o2ze;" % (k, k))
+        for line in t["vrr"]:
+            th.append("    " + line)
+        th.append("    (void)PAx; (void)PAy; (void)PAz; (void)WPx; (void)WPy; (void)WPz;")
+        th.append("    (void)QCx; (void)QCy; (void)QCz; (void)WQx; (void)WQy; (void)WQz;")
+        th.append("  }")
+        th.append("  __device__ static __forceinline__ void hrr_digest(const double* __restrict__ acc, "
+                  "const int* __restrict__ src, int pidx, double w, double ABx, double ABy, double ABz, "
+                  "double CDx, double CDy, double CDz, const double* __restrict__ dab, "
+                  "const double* __restrict__ dcd, const double* __restrict__ dbd, const double* __restrict__ dbc, "
+                  "const double* __restrict__ dad, const double* __restrict__ dac, double* __restrict__ jab, "
+                  "double* __restrict__ jcd, double* __restrict__ kac, double* __restrict__ kad, "
+                  "double* __restrict__ kbc, double* __restrict__ kbd) {")
+        for line in t["hrr_digest"]:
+            th.append("    " + line)
+        th.append("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz; (void)src; (void)pidx;")
+        th.append("  }")
+        th.append("};")
+        th.append("")
+    _write(os.path.join(outdir, "eri_team.h"), "\n".join(th) + "\n")
 
 
 if __name__ == "__main__":

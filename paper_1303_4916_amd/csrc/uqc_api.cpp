@@ -593,10 +593,11 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
             for (HostTask* t : {&t64, &t32}) {
                 if (t->mixed && !mixed) continue;
                 t->off.resize(bx.np + 1);
+                const int per_item = class_team(cls) ? kTeamKets : kWave;
                 long long acc = 0;
                 for (int i = 0; i < bx.np; ++i) {
                     t->off[i] = acc;
-                    acc += (std::max(t->hi[i] - t->lo[i], 0) + kWave - 1) / kWave;
+                    acc += (std::max(t->hi[i] - t->lo[i], 0) + per_item - 1) / per_item;
                 }
                 t->off[bx.np] = acc;
                 t->nitems = acc;

@@ -119,4 +119,8 @@ __device__ __forceinline__ double wave_sum(double x) {
 
 __device__ __forceinline__ void atomic_add(double* p, double v) { (void)unsafeAtomicAdd(p, v); }
 
+__device__ __forceinline__ void atomic_add_lds(double* p, double v) {
+    (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 }  // namespace uqc

@@ -1,6 +1,10 @@
 // One angular-momentum class of the quartet kernels: compiled once per class with
-// -DUQC_CLASS_ID=n -DUQC_LA=.. -DUQC_LB=.. -DUQC_LC=.. -DUQC_LD=.. so that the classes build in parallel.
+// -DUQC_CLASS_ID=n -DUQC_LA=.. -DUQC_LB=.. -DUQC_LC=.. -DUQC_LD=.. -DUQC_TEAM=0|1 so that the classes build in
+// parallel; UQC_TEAM selects the six-lane team kernel for the Fock build.
 #include "uqc_eri_impl.h"
+#if UQC_TEAM
+#include "uqc_eri_team.h"
+#endif
 
 #if !defined(UQC_CLASS_ID) || !defined(UQC_LA) || !defined(UQC_LB) || !defined(UQC_LC) || !defined(UQC_LD)
 #error "uqc_eri_class.hip needs UQC_CLASS_ID and UQC_LA..UQC_LD"
@@ -18,12 +22,21 @@ static hipError_t launch_digest_cls(bool mixed, const TaskDev* d_tasks, const lo
     const long long nblocks = (nitems + waves_per_block - 1) / waves_per_block;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+#if UQC_TEAM
+    if (mixed)
+        hipLaunchKernelGGL((k_digest_team<UQC_LA, UQC_LB, UQC_LC, UQC_LD, true>), dim3((unsigned)nblocks),
+                           dim3(kBlock), 0, s, d_tasks, d_task_begin, ntask, nitems, perm, b64, b32);
+    else
+        hipLaunchKernelGGL((k_digest_team<UQC_LA, UQC_LB, UQC_LC, UQC_LD, false>), dim3((unsigned)nblocks),
+                           dim3(kBlock), 0, s, d_tasks, d_task_begin, ntask, nitems, perm, b64, b32);
+#else
     if (mixed)
         hipLaunchKernelGGL((k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, true>), dim3((unsigned)nblocks), dim3(kBlock), 0,
                            s, d_tasks, d_task_begin, ntask, nitems, perm, b64, b32);
     else
         hipLaunchKernelGGL((k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, false>), dim3((unsigned)nblocks), dim3(kBlock),
                            0, s, d_tasks, d_task_begin, ntask, nitems, perm, b64, b32);
+#endif
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ constexpr int kBoysRow = 10;
 constexpr int kBoysLmax = 8;
 constexpr int kBoysTmax32 = 30;        // FP32 evaluation limit in mixed mode
 constexpr int kNumClasses = 21;
+constexpr int kTeamKets = 10;          // ket pairs per wavefront in the six-lane team kernels
 
 // Primitive-pair fields, stored field-major: prim[field][k][np] (consecutive pairs contiguous)
 enum PrimField { F_Z = 0, F_PX, F_PY, F_PZ, F_PAX, F_PAY, F_PAZ, F_PREF, F_O2Z, kNumFields };
@@ -42,7 +43,8 @@ struct TaskDev {
     BinDev bra, ket;
     const int* lo;             // [nbra] first ket index (in the ket bin)
     const int* hi;             // [nbra] one past the last ket index
-    const long long* item_off; // [nbra + 1] exclusive prefix of ceil((hi - lo) / 64)
+    const long long* item_off; // [nbra + 1] exclusive prefix of ceil((hi - lo) / kets per item: 64, or 10 for
+                               // the team kernels)
     long long item_begin;      // first work item of this task within its launch
     long long nitems;
     double tau;                // a quartet in the range is computed iff Q_ab Q_cd >= tau
@@ -96,6 +98,7 @@ hipError_t launch_normal(double* R, long long n, unsigned long long seed, unsign
                          hipStream_t s);
 hipError_t launch_trace(const double* D, int nbf, double* out, hipStream_t s);
 double class_flops_prim(int cls);
+int class_team(int cls);               // 1 if the class's Fock-build kernel is the six-lane team kernel
 double class_flops_contr(int cls);
 
 }  // namespace uqc

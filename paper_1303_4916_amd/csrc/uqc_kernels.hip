@@ -41,6 +41,7 @@ void class_ls(int idx, int* la, int* lb, int* lc, int* ld) {
 }
 
 double class_flops_prim(int cls) { return kClassFlopsPrim[cls]; }
+int class_team(int cls) { return kClassTeam[cls]; }
 double class_flops_contr(int cls) { return kClassFlopsContr[cls]; }
 
 hipError_t launch_digest(int cls, bool mixed, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,

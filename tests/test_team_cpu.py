@@ -1,0 +1,158 @@
+"""CPU emulation of the six-lane team evaluation generated for the largest classes (no GPU).
+
+Each emulated lane p runs the generated representative recursion with its geometry vectors relabelled by the axis
+permutation p, reads the values it needs from the other lanes as the device code does (source lane p o pi), and
+digests its representative outputs in its own frame with densities gathered at permuted component indices.  The
+test checks that (1) the owned outputs of the six lanes cover the true block exactly once and equal the oracle
+(after removing the oracle's primitive normalisation), and (2) the per-lane digests, added at their true indices,
+equal the digest of the oracle block."""
+import importlib.util
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1303_4916_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+_spec = importlib.util.spec_from_file_location("gen_eri", os.path.join(ROOT, "paper_1303_4916_amd", "csrc",
+                                                                       "gen_eri.py"))
+gen = importlib.util.module_from_spec(_spec)
+_spec.loader.exec_module(gen)
+
+
+def _fma(a, b, c):
+    return a * b + c
+
+
+def _norm(a, comp):
+    lx, ly, lz = comp
+    l = lx + ly + lz
+    df = lambda n: float(np.prod(np.arange(n, 0, -2))) if n > 0 else 1.0
+    return (2 * a / math.pi) ** 0.75 * (4 * a) ** (l / 2) / math.sqrt(df(2 * lx - 1) * df(2 * ly - 1) * df(2 * lz - 1))
+
+
+def _geometry(A, B, C, D, al, be, ga, de):
+    z, e = al + be, ga + de
+    P = (al * A + be * B) / z
+    Q = (ga * C + de * D) / e
+    ze = z + e
+    PQ = P - Q
+    T = z * e / ze * float(PQ @ PQ)
+    pref = (2 * math.pi ** 2.5 / (z * e * math.sqrt(ze)) * math.exp(-al * be / z * float((A - B) @ (A - B))) *
+            math.exp(-ga * de / e * float((C - D) @ (C - D))))
+    return dict(PA=P - A, WP=-(e / ze) * PQ, QC=Q - C, WQ=(z / ze) * PQ, AB=A - B, CD=C - D, T=T, pref=pref,
+                o2z=0.5 / z, o2e=0.5 / e, o2ze=0.5 / ze, roz=e / ze, roe=z / ze)
+
+
+def _lane_env(geo, p, L):
+    env = {"fma": _fma}
+    F = oracle.boys(L, geo["T"]) * geo["pref"]
+    for m in range(L + 1):
+        env["F%d" % m] = F[m]
+    for name in ("PA", "WP", "QC", "WQ", "AB", "CD"):
+        V = geo[name]
+        for i, ax in enumerate("xyz"):
+            env[name + ax] = V[p[i]]  # geometry relabelled for lane p
+    for k in range(1, 9):
+        env["oz%d" % k] = k * geo["o2z"]
+        env["ozr%d" % k] = k * geo["o2z"] * geo["roz"]
+        env["oe%d" % k] = k * geo["o2e"]
+        env["oer%d" % k] = k * geo["o2e"] * geo["roe"]
+        env["oze%d" % k] = k * geo["o2ze"]
+    return env
+
+
+@pytest.mark.parametrize("c", gen.TEAM_CLASSES, ids=gen.cname)
+def test_team_emulation_matches_oracle(c):
+    la, lb, lc, ld = c
+    t = gen.gen_team(c)
+    rng = np.random.default_rng(sum(x * 3 ** i for i, x in enumerate(c)) + 99)
+    cen = rng.uniform(-1.5, 1.5, size=(4, 3))
+    ex = np.exp(rng.uniform(math.log(0.3), math.log(5.0), size=4))
+    sh = wl.Shells(np.array(c, np.int32), np.ones(4, np.int32), cen, ex, np.ones(4), np.arange(4, dtype=np.int32))
+    ref = oracle.Basis(sh).eri(0, 1, 2, 3)
+    comps = [gen.comps(l) for l in c]
+    scale = np.einsum("i,j,k,l->ijkl", *[np.array([_norm(ex[s], cp) for cp in comps[s]]) for s in range(4)])
+    raw_ref = ref / scale
+    geo = _geometry(*cen, *ex)
+    L = la + lb + lc + ld
+    # phase 1: every lane's representative accumulators
+    vrr_code = "\n".join(re.sub(r"^const (T|double) ", "", x).rstrip(";").replace("(double)", "") for x in t["vrr"])
+    accs = []
+    for p in gen.PERMS:
+        env = _lane_env(geo, p, L)
+        env["acc"] = np.zeros(t["nrep"])
+        exec(vrr_code, env)
+        accs.append(env["acc"])
+    # phase 2: per lane, the horizontal recursion on its representative outputs, with cross-lane reads
+    comp_tab = [[gen.PERMS.index(gen.perm_compose(p, q)) for q in gen.PERMS] for p in gen.PERMS]
+    na, nb, nc, nd = (len(x) for x in comps)
+    covered = np.zeros((na, nb, nc, nd), dtype=int)
+    got = np.zeros((na, nb, nc, nd))
+    rngD = np.random.default_rng(5)
+    N = na + nb + nc + nd
+    Dm = rngD.standard_normal((N, N))
+    Dm = Dm + Dm.T
+    off = [0, na, na + nb, na + nb + nc]
+    true_dig = {k: np.zeros(n) for k, n in [("jab", na * nb), ("jcd", nc * nd), ("kac", na * nc), ("kad", na * nd),
+                                             ("kbc", nb * nc), ("kbd", nb * nd)]}
+    pc_tab = gen.perm_comp_table()
+    for ip, p in enumerate(gen.PERMS):
+        env = _lane_env(geo, p, L)
+        env["acc"] = accs[ip]
+        env["src"] = comp_tab[ip]
+        env["pidx"] = ip
+        env["w"] = 1.0
+        env["fetch"] = None
+        rec = []
+        code = []
+        for line in t["hrr_digest"]:
+            m = re.match(r"\{ const double x = (.*);$", line)
+            if m:
+                code.append("_rec.append(%s)" % m.group(1))
+            elif line.startswith("  "):
+                continue
+            else:
+                line = re.sub(r"^const double ", "", line).rstrip(";")
+                line = re.sub(r"fetch\(acc\[(\d+)\], src\[(\d+)\]\)", r"_acc[src[\2]][\1]", line)
+                code.append(line)
+        env["_rec"] = rec
+        env["_acc"] = accs
+        code = "\n".join(code).replace("? w : 0.0", "and w or 0.0").replace("(((", "((").replace(") & 1) and", ") & 1 and")
+        code = re.sub(r"\(\(\((\d+) >> pidx\) & 1\) \? w : 0\.0\)", r"(w if ((\1 >> pidx) & 1) else 0.0)", code)
+        exec(code, env)
+        assert len(rec) == len(t["out_reps"])
+        # map representative outputs to true components; owned ones only
+        pcs = [pc_tab[l][ip] for l in c]
+        for n, (o, mask) in enumerate(zip(t["out_reps"], t["masks"])):
+            if not (mask >> ip) & 1:
+                continue
+            idx = tuple(gen.comps(c[s]).index(gen.perm_q(o[s], p)) for s in range(4))
+            covered[idx] += 1
+            got[idx] = rec[n]
+            # digest in the lane's frame, added at true indices (mirrors the device reduction)
+            i, j, k, l = (gen.comps(c[s]).index(o[s]) for s in range(4))
+            I, Jx, K, Lx = (pcs[s][x] for s, x in zip(range(4), (i, j, k, l)))
+            x = rec[n]
+            true_dig["jab"][I * nb + Jx] += x * Dm[off[2] + K, off[3] + Lx]
+            true_dig["jcd"][K * nd + Lx] += x * Dm[off[0] + I, off[1] + Jx]
+            true_dig["kac"][I * nc + K] += x * Dm[off[1] + Jx, off[3] + Lx]
+            true_dig["kad"][I * nd + Lx] += x * Dm[off[1] + Jx, off[2] + K]
+            true_dig["kbc"][Jx * nc + K] += x * Dm[off[0] + I, off[3] + Lx]
+            true_dig["kbd"][Jx * nd + Lx] += x * Dm[off[0] + I, off[2] + K]
+    assert np.all(covered == 1)
+    assert np.max(np.abs(got - raw_ref)) <= 1e-12 * np.max(np.abs(raw_ref))
+    # reference digest of the full true block
+    v = raw_ref
+    Dab, Dcd = Dm[off[0]:off[0] + na, off[1]:off[1] + nb], Dm[off[2]:off[2] + nc, off[3]:off[3] + nd]
+    Dbd, Dbc = Dm[off[1]:off[1] + nb, off[3]:off[3] + nd], Dm[off[1]:off[1] + nb, off[2]:off[2] + nc]
+    Dad, Dac = Dm[off[0]:off[0] + na, off[3]:off[3] + nd], Dm[off[0]:off[0] + na, off[2]:off[2] + nc]
+    refd = {"jab": np.einsum("ijkl,kl->ij", v, Dcd).ravel(), "jcd": np.einsum("ijkl,ij->kl", v, Dab).ravel(),
+            "kac": np.einsum("ijkl,jl->ik", v, Dbd).ravel(), "kad": np.einsum("ijkl,jk->il", v, Dbc).ravel(),
+            "kbc": np.einsum("ijkl,il->jk", v, Dad).ravel(), "kbd": np.einsum("ijkl,ik->jl", v, Dac).ravel()}
+    for k in refd:
+        assert np.max(np.abs(true_dig[k] - refd[k])) <= 1e-12 * max(np.max(np.abs(refd[k])), 1e-300), k
