@@ -77,6 +77,23 @@ def summarize_pmc(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_writ
     return doc
 
 
+def summarize_stats(stats_csv: str, out: str, cmd: str, title: str):
+    """Markdown table of a rocprofv3 --kernel-trace --stats kernel summary (average launch durations)."""
+    import csv
+    rows = []
+    for r in csv.DictReader(open(stats_csv)):
+        k = r["Name"].split("(")[0].replace("void ", "").replace("uqc::", "")
+        rows.append((k, int(r["Calls"]), float(r["AverageNs"]) * 1e-6, float(r["TotalDurationNs"]) * 1e-6,
+                     float(r["Percentage"])))
+    rows.sort(key=lambda r: -r[3])
+    lines = ["# %s -- rocprofv3 kernel stats" % title, "", "Command (from the repository root):", "", "```", cmd,
+             "```", "", "kernel_sources_sha256: %s" % kernel_sources_sha256(), "",
+             "| kernel | calls | avg ms | total ms | % |", "|---|---|---|---|---|"]
+    lines += ["| %s | %d | %.3f | %.2f | %.1f |" % r for r in rows]
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def traffic_for(kernel_key: str):
     """HBM bytes per launch of a kernel from the committed counter summary, or None if the kernels changed since."""
     try:
@@ -85,7 +102,8 @@ def traffic_for(kernel_key: str):
         return None
     if doc.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
-    k = doc["kernels"].get(kernel_key)
+    # the largest classes run as the team kernel (k_digest_team), the others as k_digest
+    k = doc["kernels"].get(kernel_key) or doc["kernels"].get(kernel_key.replace("k_digest<", "k_digest_team<"))
     if not k:
         return None
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
@@ -158,7 +176,12 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                                                          "COPY_WRITE_CSV", "CMD"),
                     help="write the per-kernel traffic summary from rocprofv3 counter CSVs and exit")
+    ap.add_argument("--summarize-stats", nargs=4, metavar=("STATS_CSV", "OUT_MD", "CMD", "TITLE"),
+                    help="write a markdown summary of a rocprofv3 kernel stats CSV and exit")
     a = ap.parse_args()
+    if a.summarize_stats:
+        summarize_stats(*a.summarize_stats)
+        return
     if a.summarize_pmc:
         summarize_pmc(*a.summarize_pmc[:4], TRAFFIC_FILE, a.summarize_pmc[4])
         return

@@ -282,7 +282,7 @@ def gen_hrr(c, es, fs):
 #   Q(Q(t, pi), p) = Q(t, p o pi) with (p o pi)[i] = p[pi[i]]
 # ------------------------------------------------------------------------------------------------------------------
 PERMS = list(itertools.permutations(range(3)))
-TEAM_CLASSES = [(2, 0, 2, 0), (2, 1, 2, 1), (2, 2, 1, 1), (2, 2, 2, 0), (2, 2, 2, 1), (2, 2, 2, 2)]
+TEAM_CLASSES = [(2, 1, 2, 1), (2, 2, 1, 1), (2, 2, 2, 0), (2, 2, 2, 1), (2, 2, 2, 2)]
 TEAM_SIZE = 6
 
 

@@ -116,7 +116,11 @@ uqc_status uqc_init(int device, void* hip_stream, uqc_ctx** out) {
     for (int L = 0; L <= kBoysLmax; ++L)
         for (int g = 0; g < kBoysNg; ++g) {
             double* row = tab.data() + ((size_t)L * kBoysNg + g) * kBoysRow;
-            for (int k = 0; k < 9; ++k) row[k] = full[(size_t)g * kBoysNm + L + k];
+            double inv_fact = 1.0;  // Taylor coefficients F_{L+k}(T_g) / k!
+            for (int k = 0; k < 9; ++k) {
+                if (k > 0) inv_fact /= k;
+                row[k] = full[(size_t)g * kBoysNm + L + k] * inv_fact;
+            }
             row[9] = full[(size_t)g * kBoysNm + kBoysExpCol];
         }
     if (hipMalloc(&c->boys64, tab.size() * sizeof(double)) != hipSuccess ||
@@ -175,21 +179,37 @@ void uqc::free_plan(Plan& p) {
     p.d_mem = nullptr;
 }
 
-// Device arrays of a bin in one allocation: prim [kNumFields*K*np], AB [3*np], sdeg [np], Q [np], off_a [np],
-// off_b [np].
+// Device arrays of a bin in one allocation: prim [kNumFields*K*np], AB [3*np], sdeg [np], Q [np], rec
+// [np*K*kRec], hdr [np*kHdr], off_a [np], off_b [np].
 static uqc_status upload_bin(Bin& b) {
     const size_t np = b.np, K = b.K;
-    const size_t nd = kNumFields * K * np + 3 * np + 2 * np;
+    const size_t n_prim = kNumFields * K * np, n_rec = np * K * kRec, n_hdr = np * kHdr;
+    const size_t nd = n_prim + 3 * np + 2 * np + n_rec + n_hdr;
     const size_t bytes = nd * sizeof(double) + 2 * np * sizeof(int);
     if (!b.d_mem) {
         if (hipMalloc(&b.d_mem, bytes) != hipSuccess) return uqc_fail(UQC_E_NOMEM, "basis: bin allocation failed");
     }
-    std::vector<char> host(bytes);
+    std::vector<char> host(bytes, 0);
     double* hd = (double*)host.data();
-    std::memcpy(hd, b.prim.data(), kNumFields * K * np * sizeof(double));
-    std::memcpy(hd + kNumFields * K * np, b.AB.data(), 3 * np * sizeof(double));
-    std::memcpy(hd + kNumFields * K * np + 3 * np, b.sdeg.data(), np * sizeof(double));
-    std::memcpy(hd + kNumFields * K * np + 4 * np, b.Q.data(), np * sizeof(double));
+    std::memcpy(hd, b.prim.data(), n_prim * sizeof(double));
+    std::memcpy(hd + n_prim, b.AB.data(), 3 * np * sizeof(double));
+    std::memcpy(hd + n_prim + 3 * np, b.sdeg.data(), np * sizeof(double));
+    std::memcpy(hd + n_prim + 4 * np, b.Q.data(), np * sizeof(double));
+    double* rec = hd + n_prim + 5 * np;
+    double* hdr = rec + n_rec;
+    for (size_t i = 0; i < np; ++i) {
+        for (size_t k = 0; k < K; ++k)
+            for (size_t f = 0; f < (size_t)kNumFields; ++f) rec[(i * K + k) * kRec + f] = b.prim[(f * K + k) * np + i];
+        double* h = hdr + i * kHdr;
+        h[0] = b.AB[i];
+        h[1] = b.AB[np + i];
+        h[2] = b.AB[2 * np + i];
+        h[3] = b.sdeg[i];
+        h[4] = b.Q[i];
+        int* o = (int*)(h + 5);
+        o[0] = b.off_a[i];
+        o[1] = b.off_b[i];
+    }
     int* hi = (int*)(hd + nd);
     std::memcpy(hi, b.off_a.data(), np * sizeof(int));
     std::memcpy(hi + np, b.off_b.data(), np * sizeof(int));
@@ -197,9 +217,11 @@ static uqc_status upload_bin(Bin& b) {
     double* dd = (double*)b.d_mem;
     int* di = (int*)(dd + nd);
     b.dev.prim = dd;
-    b.dev.AB = dd + kNumFields * K * np;
-    b.dev.sdeg = dd + kNumFields * K * np + 3 * np;
-    b.dev.Q = dd + kNumFields * K * np + 4 * np;
+    b.dev.AB = dd + n_prim;
+    b.dev.sdeg = dd + n_prim + 3 * np;
+    b.dev.Q = dd + n_prim + 4 * np;
+    b.dev.rec = dd + n_prim + 5 * np;
+    b.dev.hdr = b.dev.rec + n_rec;
     b.dev.off_a = di;
     b.dev.off_b = di + np;
     b.dev.np = (int)np;
@@ -522,7 +544,8 @@ uqc_status uqc_schwarz(const uqc_basis* b, double* Q) {
 // and, if X == Y, j <= i.  Ket bins are ordered by decade of Q (descending), so the kets that can pass form a prefix
 // ending one decade below the decade of tau / Q_i; the kernels apply the exact test per lane.  In mixed precision
 // the FP64 task takes the kets with Q_i Q_j > bound and the FP32-recursion task those with Q_i Q_j <= bound; the
-// decade holding the split is scanned by both tasks with complementary per-lane tests.
+// decade holding the split is scanned by both tasks with complementary per-lane tests.  The work items of a task
+// are (ket chunk, group of bra pairs) pairs, listed chunk by chunk (TaskDev).
 void uqc::plan_account(Plan& p) {
     p.quartets = p.prim_quartets = p.fp64_quartets = 0;
     p.flops = 0;
@@ -553,7 +576,8 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
         int cls, mixed, X, Y, same;
         double lo_excl, hi_incl;
         std::vector<int> lo, hi;
-        std::vector<long long> off;
+        std::vector<int> blist;   // bra indices, chunk by chunk, ordered by first shell inside a chunk
+        std::vector<int> items;   // pairs {first blist entry, chunk}, then the sentinel {blist size, 0}
         long long nitems;
     };
     std::vector<HostTask> tasks;
@@ -567,8 +591,8 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
         for (int Y = 0; Y <= X; ++Y) {
             const Bin &bx = B->bins[X], &by = B->bins[Y];
             const int cls = class_index(bx.la, bx.lb, by.la, by.lb);
-            HostTask t64{cls, 0, X, Y, X == Y, mixed ? bound : -1.0, INFINITY, {}, {}, {}, 0};
-            HostTask t32{cls, 1, X, Y, X == Y, -1.0, bound, {}, {}, {}, 0};
+            HostTask t64{cls, 0, X, Y, X == Y, mixed ? bound : -1.0, INFINITY, {}, {}, {}, {}, 0};
+            HostTask t32{cls, 1, X, Y, X == Y, -1.0, bound, {}, {}, {}, {}, 0};
             for (int i = 0; i < bx.np; ++i) {
                 const double qi = bx.Q[i];
                 int h = by.np;
@@ -590,18 +614,40 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
                 t32.lo.push_back(l32);
                 t32.hi.push_back(h);
             }
+            // bra pairs by first shell (then bin position): a wavefront keeps its K_ad / K_ac sums across a run
+            std::vector<int> by_a(bx.np);
+            std::iota(by_a.begin(), by_a.end(), 0);
+            std::stable_sort(by_a.begin(), by_a.end(), [&](int x, int y) { return bx.off_a[x] < bx.off_a[y]; });
+            const int S = class_team(cls) ? kTeamKets : kWave;
+            const int GB = class_team(cls) ? kTeamGroupBras : kGroupBras;
             for (HostTask* t : {&t64, &t32}) {
                 if (t->mixed && !mixed) continue;
-                t->off.resize(bx.np + 1);
-                const int per_item = class_team(cls) ? kTeamKets : kWave;
-                long long acc = 0;
-                for (int i = 0; i < bx.np; ++i) {
-                    t->off[i] = acc;
-                    acc += (std::max(t->hi[i] - t->lo[i], 0) + per_item - 1) / per_item;
+                int nch = 0;
+                for (int i = 0; i < bx.np; ++i)
+                    if (t->hi[i] > t->lo[i]) nch = std::max(nch, (t->hi[i] + S - 1) / S);
+                std::vector<long long> start(nch + 1, 0);
+                for (int i = 0; i < bx.np; ++i)
+                    if (t->hi[i] > t->lo[i])
+                        for (int c = t->lo[i] / S; c <= (t->hi[i] - 1) / S; ++c) ++start[c + 1];
+                for (int c = 0; c < nch; ++c) start[c + 1] += start[c];
+                if (start[nch] > 0x7fffffffLL) {
+                    *st = uqc_fail(UQC_E_NOMEM, "plan: work list exceeds 2^31 entries");
+                    return nullptr;
                 }
-                t->off[bx.np] = acc;
-                t->nitems = acc;
-                if (acc > 0) tasks.push_back(std::move(*t));
+                t->blist.resize(start[nch]);
+                std::vector<long long> fill(start.begin(), start.end() - 1);
+                for (int i : by_a)
+                    if (t->hi[i] > t->lo[i])
+                        for (int c = t->lo[i] / S; c <= (t->hi[i] - 1) / S; ++c) t->blist[fill[c]++] = i;
+                for (int c = 0; c < nch; ++c)
+                    for (long long e = start[c]; e < start[c + 1]; e += GB) {
+                        t->items.push_back((int)e);
+                        t->items.push_back(c);
+                    }
+                t->nitems = (long long)t->items.size() / 2;
+                t->items.push_back((int)start[nch]);
+                t->items.push_back(0);
+                if (t->nitems > 0) tasks.push_back(std::move(*t));
             }
         }
     // group tasks into one launch per (class, precision); task order = group order, so the counters of a group
@@ -625,7 +671,7 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
     bytes += align(tasks.size() * sizeof(unsigned long long));
     for (auto& t : tasks) {
         const size_t n = B->bins[t.X].np;
-        bytes += align(n * sizeof(int)) * 2 + align((n + 1) * sizeof(long long));
+        bytes += align(n * sizeof(int)) * 2 + align(t.blist.size() * sizeof(int)) + align(t.items.size() * sizeof(int));
     }
     for (size_t g = 0; g < gkeys.size(); ++g) bytes += align(tasks.size() * sizeof(TaskDev)) + align(tasks.size() * 8);
     std::vector<char> host(bytes, 0);
@@ -649,15 +695,19 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
         std::memcpy(host.data() + pos, t.hi.data(), n * sizeof(int));
         const int* dhi = (const int*)(dbase + pos);
         pos += align(n * sizeof(int));
-        std::memcpy(host.data() + pos, t.off.data(), (n + 1) * sizeof(long long));
-        const long long* doff = (const long long*)(dbase + pos);
-        pos += align((n + 1) * sizeof(long long));
+        std::memcpy(host.data() + pos, t.blist.data(), t.blist.size() * sizeof(int));
+        const int* dblist = (const int*)(dbase + pos);
+        pos += align(t.blist.size() * sizeof(int));
+        std::memcpy(host.data() + pos, t.items.data(), t.items.size() * sizeof(int));
+        const int2* ditems = (const int2*)(dbase + pos);
+        pos += align(t.items.size() * sizeof(int));
         TaskDev& d = tdev[oi];
         d.bra = B->bins[t.X].dev;
         d.ket = B->bins[t.Y].dev;
         d.lo = dlo;
         d.hi = dhi;
-        d.item_off = doff;
+        d.blist = dblist;
+        d.items = ditems;
         d.item_begin = 0;
         d.nitems = t.nitems;
         d.tau = tau;

@@ -16,59 +16,13 @@ __host__ __device__ constexpr double comp_factor(int l, int c) {
 
 constexpr double kPi = 3.14159265358979323846;
 
-// ------------------------------------------------------------------------------------------------ Boys function
-// F_m(T) = int_0^1 t^{2m} exp(-T t^2) dt, returned multiplied by `pref` (`tab`: the per-order FP64 slices).
-// For T < 40: Taylor series of order 8
-// around the nearest grid point T_g = g/8 (|d| = |T_g - T| <= 1/16, truncation error < 1e-16 relative), using
-// dF_m/dT = -F_{m+1}, for the highest order needed; exp(-T) = exp(-T_g) exp(d) with exp(-T_g) tabulated and exp(d)
-// from its Taylor series to order 9 (truncation < 3e-19); then the downward recursion
-// F_m = (2T F_{m+1} + exp(-T)) / (2m+1).  For T >= 40: F_0 = sqrt(pi/T)/2 (erf(sqrt(T)) = 1 to double precision)
-// and the upward recursion F_{m+1} = ((2m+1) F_m - exp(-T)) / (2T).
-template <int L>
-__device__ __forceinline__ void boys64(double T, double pref, const double* __restrict__ tab, double* F) {
-    if (T < (double)kBoysTmax) {
-        const int g = (int)(T * (double)kBoysGridPerUnit + 0.5);
-        const double d = (double)g * (1.0 / kBoysGridPerUnit) - T;  // exact grid point
-        const double2* row = reinterpret_cast<const double2*>(tab + ((size_t)L * kBoysNg + g) * kBoysRow);
-        const double2 r01 = row[0], r23 = row[1], r45 = row[2], r67 = row[3], r8e = row[4];
-        double p = r8e.x;
-        p = fma(p, d * (1.0 / 8.0), r67.y);
-        p = fma(p, d * (1.0 / 7.0), r67.x);
-        p = fma(p, d * (1.0 / 6.0), r45.y);
-        p = fma(p, d * (1.0 / 5.0), r45.x);
-        p = fma(p, d * (1.0 / 4.0), r23.y);
-        p = fma(p, d * (1.0 / 3.0), r23.x);
-        p = fma(p, d * (1.0 / 2.0), r01.y);
-        p = fma(p, d, r01.x);
-        F[L] = p * pref;
-        if constexpr (L > 0) {
-            double x = fma(d, 1.0 / 9.0, 1.0);
-            x = fma(x, d * (1.0 / 8.0), 1.0);
-            x = fma(x, d * (1.0 / 7.0), 1.0);
-            x = fma(x, d * (1.0 / 6.0), 1.0);
-            x = fma(x, d * (1.0 / 5.0), 1.0);
-            x = fma(x, d * (1.0 / 4.0), 1.0);
-            x = fma(x, d * (1.0 / 3.0), 1.0);
-            x = fma(x, d * (1.0 / 2.0), 1.0);
-            x = fma(x, d, 1.0);
-            const double e = r8e.y * x * pref;
-            const double t2 = T + T;
-#pragma unroll
-            for (int m = L - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (2 * m + 1));
-        }
-    } else {
-        const double it = 1.0 / T;
-        F[0] = 0.5 * sqrt(kPi * it);
-        if constexpr (L > 0) {
-            const double e = exp(-T);
-            const double h = 0.5 * it;
-#pragma unroll
-            for (int m = 0; m < L; ++m) F[m + 1] = fma((double)(2 * m + 1), F[m], -e) * h;
-        }
-#pragma unroll
-        for (int m = 0; m <= L; ++m) F[m] *= pref;
-    }
-}
+// Read-only data that is the same for the whole wavefront (bra-pair records and headers, work lists, the density
+// block of the bra pair) is read through the constant address space, so uniform addresses become scalar loads.
+// None of it is written while a kernel runs.
+typedef const __attribute__((address_space(4))) double* cdptr;
+typedef const __attribute__((address_space(4))) int* ciptr;
+__device__ __forceinline__ cdptr as_const(const double* p) { return (cdptr)p; }
+__device__ __forceinline__ ciptr as_const(const int* p) { return (ciptr)p; }
 
 // 1/x and 1/sqrt(x) for positive normal x: hardware approximations refined by Newton steps (two for the
 // reciprocal, two for the square root) to full double precision.
@@ -87,6 +41,59 @@ __device__ __forceinline__ double rsqrt64(double x) {
     y = fma(y, t, y);
     t = fma(-h * y, y, 0.5);
     return fma(y, t, y);
+}
+
+// ------------------------------------------------------------------------------------------------ Boys function
+// F_m(T) = int_0^1 t^{2m} exp(-T t^2) dt, returned multiplied by `pref` (`tab`: the per-order FP64 slices).
+// For T < 60: Taylor series of order 8 around the nearest grid point T_g = g/8 (|d| = |T_g - T| <= 1/16,
+// truncation error < 1e-16 relative), using dF_m/dT = -F_{m+1}, for the highest order needed (the table holds
+// the coefficients F_{L+k}(T_g)/k!); exp(-T) = exp(-T_g) exp(d) with exp(-T_g) tabulated and exp(d) from its
+// Taylor series to order 9 (truncation < 3e-19); then the downward recursion F_m = (2T F_{m+1} + exp(-T)) / (2m+1).
+// For T >= 60: F_0 = sqrt(pi/T)/2 (erf(sqrt(T)) = 1 to double precision) and the upward recursion
+// F_{m+1} = (2m+1) F_m / (2T); the exp(-T) term the exact recursion subtracts is below 1e-26 and changes no F_m,
+// m <= 8, by more than 2e-17 of its value.
+template <int L>
+__device__ __forceinline__ void boys64(double T, double pref, const double* __restrict__ tab, double* F) {
+    if (T < (double)kBoysTmax) {
+        const int g = (int)(T * (double)kBoysGridPerUnit + 0.5);
+        const double d = (double)g * (1.0 / kBoysGridPerUnit) - T;  // exact grid point
+        const double2* row = reinterpret_cast<const double2*>(tab + ((size_t)L * kBoysNg + g) * kBoysRow);
+        const double2 r01 = row[0], r23 = row[1], r45 = row[2], r67 = row[3], r8e = row[4];
+        double p = r8e.x;
+        p = fma(p, d, r67.y);
+        p = fma(p, d, r67.x);
+        p = fma(p, d, r45.y);
+        p = fma(p, d, r45.x);
+        p = fma(p, d, r23.y);
+        p = fma(p, d, r23.x);
+        p = fma(p, d, r01.y);
+        p = fma(p, d, r01.x);
+        F[L] = p * pref;
+        if constexpr (L > 0) {
+            double x = 1.0 / 362880.0;
+            x = fma(x, d, 1.0 / 40320.0);
+            x = fma(x, d, 1.0 / 5040.0);
+            x = fma(x, d, 1.0 / 720.0);
+            x = fma(x, d, 1.0 / 120.0);
+            x = fma(x, d, 1.0 / 24.0);
+            x = fma(x, d, 1.0 / 6.0);
+            x = fma(x, d, 0.5);
+            x = fma(x, d, 1.0);
+            x = fma(x, d, 1.0);
+            const double e = r8e.y * x * pref;
+            const double t2 = T + T;
+#pragma unroll
+            for (int m = L - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (2 * m + 1));
+        }
+    } else {
+        const double r = rsqrt64(T);
+        F[0] = (0.88622692545275801365 * pref) * r;  // sqrt(pi)/2
+        if constexpr (L > 0) {
+            const double h = 0.5 * r * r;
+#pragma unroll
+            for (int m = 0; m < L; ++m) F[m + 1] = ((double)(2 * m + 1) * h) * F[m];
+        }
+    }
 }
 
 // FP32 variant (mixed mode, T <= 30 only): Taylor order 5 around the same grid points (truncation < 1e-10

@@ -1,14 +1,14 @@
 // Shell-quartet electron-repulsion-integral kernels (templates), instantiated once per angular-momentum class in
 // uqc_eri_class.hip.
 //
-// Quartet kernels.  One work item = one bra shell pair x up to 64 ket shell pairs of one (bra bin, ket bin) block.
-// A wavefront takes one item: every lane evaluates one contracted shell quartet (ab|cd) of the integrals of
-// Eq. (5); the bra pair is the same for the whole wavefront, so its primitive-pair data are wave-uniform (scalar
-// registers) while each lane streams its own ket pair's data (coalesced, pairs stored field-major).  Per primitive
-// quartet: Boys function (tabulated Taylor grid + downward recursion), Obara-Saika vertical recursion,
-// accumulation into FP64 contracted integrals; per contracted quartet: horizontal recursion, then the J/K digest
-// of Eq. (12) using the 8-fold permutational symmetry.  J_ab (same for the whole wavefront) is reduced across the
-// wavefront before one atomic add; the five per-lane blocks J_cd, K_ac, K_ad, K_bc, K_bd use FP64 atomics in L2.
+// Quartet kernels.  One work item = one chunk of 64 ket shell pairs x a group of bra shell pairs of one (bra bin,
+// ket bin) block.  A wavefront takes one item; every lane evaluates, for each bra pair of the group in turn, one
+// contracted shell quartet (ab|cd) of the integrals of Eq. (5).  The bra pair is the same for the whole wavefront
+// (wave-uniform, scalar loads) while each lane streams its own ket pair's data (coalesced, pairs stored
+// field-major), which stays in cache across the group.  Per primitive quartet: Boys function (tabulated Taylor
+// grid + downward recursion), Obara-Saika vertical recursion, accumulation into FP64 contracted integrals; per
+// contracted quartet: horizontal recursion, then the J/K digest of Eq. (12) using the 8-fold permutational
+// symmetry.
 #pragma once
 #include "uqc_device_common.h"
 
@@ -32,8 +32,9 @@ template <class C, bool MIXED>
 __device__ __forceinline__ void accumulate(const BinDev& B, int bra, const BinDev& Kt, int ket,
                                            const double* __restrict__ boys64tab, const float* __restrict__ boys32tab,
                                            double* __restrict__ acc) {
-    const size_t npb = (size_t)B.np, npk = (size_t)Kt.np;
-    const size_t fsb = (size_t)B.K * npb, fsk = (size_t)Kt.K * npk;
+    const size_t npk = (size_t)Kt.np;
+    const size_t fsk = (size_t)Kt.K * npk;
+    const cdptr brec = as_const(B.rec) + (size_t)bra * B.K * kRec;  // wavefront-uniform: scalar loads
     for (int kk = 0; kk < Kt.K; ++kk) {
         const double* kp = Kt.prim + (size_t)kk * npk + ket;
         const double eta = kp[F_Z * fsk];
@@ -42,20 +43,21 @@ __device__ __forceinline__ void accumulate(const BinDev& B, int bra, const BinDe
         const double prefk = kp[F_PREF * fsk];
         const double o2e = kp[F_O2Z * fsk];
         for (int kb = 0; kb < B.K; ++kb) {
-            const double* bp = B.prim + (size_t)kb * npb + bra;
-            const double zeta = bp[F_Z * fsb];
-            const double Px = bp[F_PX * fsb], Py = bp[F_PY * fsb], Pz = bp[F_PZ * fsb];
-            const double PAx = bp[F_PAX * fsb], PAy = bp[F_PAY * fsb], PAz = bp[F_PAZ * fsb];
-            const double prefb = bp[F_PREF * fsb];
-            const double o2z = bp[F_O2Z * fsb];
+            const cdptr bp = brec + kb * kRec;
+            const double zeta = bp[F_Z];
+            const double Px = bp[F_PX], Py = bp[F_PY], Pz = bp[F_PZ];
+            const double PAx = bp[F_PAX], PAy = bp[F_PAY], PAz = bp[F_PAZ];
+            const double prefb = bp[F_PREF];
+            const double o2z = bp[F_O2Z];
 
             const double ze = zeta + eta;
-            const double inv = rcp64(ze);
+            const double rz = rsqrt64(ze);
+            const double inv = rz * rz;
             const double PQx = Px - Qx, PQy = Py - Qy, PQz = Pz - Qz;
             const double rho = zeta * eta * inv;
             const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
             const double roz = eta * inv, roe = zeta * inv;
-            const double pref = prefb * prefk * rsqrt64(ze);
+            const double pref = prefb * prefk * rz;
             if constexpr (!MIXED) {
                 PrimGeom<double> g;
                 g.PA[0] = PAx; g.PA[1] = PAy; g.PA[2] = PAz;
@@ -103,45 +105,18 @@ __device__ __forceinline__ double seg_scan(double x, const bool* inseg) {
     return x;
 }
 
-// J/K digest of one contracted quartet block v = (ab|cd) (raw components), weight w (degeneracy factors; 0 for
-// idle lanes):  J_ab += 2w v.D_cd, J_cd += 2w v.D_ab, K_ac += w v.D_bd, K_ad += w v.D_bc, K_bc += w v.D_ad,
-// K_bd += w v.D_ac.  The accumulators are symmetrised (J + J^T, K + K^T) in the finalize step.  The bra pair (a, b)
-// is the same for every lane of the wavefront, so J_ab is summed over the wavefront before one atomic add; ket
-// pairs sharing their first shell c sit in adjacent lanes, so K_ac and K_bc are summed over each such run before
-// one atomic add per run; J_cd, K_ad and K_bd are added per lane.
+// Partial J/K sums of one contracted quartet block v = (ab|cd) (raw components) against the scaled density:
+// jab = v.D_cd, jcd = v.D_ab, kac = v.D_bd, kad = v.D_bc, kbc = v.D_ad, kbd = v.D_ac (Eq. 12 with the 8-fold
+// permutational symmetry; the accumulators are symmetrised, J + J^T and K + K^T, in the finalize step).
 template <int NA, int NB, int NC, int ND>
-__device__ __forceinline__ void digest(const double* __restrict__ v, double w, bool act, int lane, int oa, int ob,
-                                       int oc, int od, const double* __restrict__ D, double* __restrict__ J,
-                                       double* __restrict__ K, int N) {
-    constexpr int NAB = NA * NB, NCD = NC * ND;
-    double dab[NAB], dcd[NCD], dbd[NB * ND], dbc[NB * NC], dad[NA * ND], dac[NA * NC];
+__device__ __forceinline__ void partials(const double* __restrict__ v, const double* dab, const double* dcd,
+                                         const double* dbd, const double* dbc, const double* dad, const double* dac,
+                                         double* jab, double* jcd, double* kac, double* kad, double* kbc,
+                                         double* kbd) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i)
+    for (int x = 0; x < NA * NB; ++x) jab[x] = 0.0;
 #pragma unroll
-        for (int j = 0; j < NB; ++j) dab[i * NB + j] = D[(size_t)(oa + i) * N + ob + j];
-#pragma unroll
-    for (int k = 0; k < NC; ++k)
-#pragma unroll
-        for (int l = 0; l < ND; ++l) dcd[k * ND + l] = D[(size_t)(oc + k) * N + od + l];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-#pragma unroll
-        for (int l = 0; l < ND; ++l) dbd[j * ND + l] = D[(size_t)(ob + j) * N + od + l];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) dbc[j * NC + k] = D[(size_t)(ob + j) * N + oc + k];
-    }
-#pragma unroll
-    for (int i = 0; i < NA; ++i) {
-#pragma unroll
-        for (int l = 0; l < ND; ++l) dad[i * ND + l] = D[(size_t)(oa + i) * N + od + l];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) dac[i * NC + k] = D[(size_t)(oa + i) * N + oc + k];
-    }
-    double jab[NAB], jcd[NCD], kac[NA * NC], kad[NA * ND], kbc[NB * NC], kbd[NB * ND];
-#pragma unroll
-    for (int x = 0; x < NAB; ++x) jab[x] = 0.0;
-#pragma unroll
-    for (int x = 0; x < NCD; ++x) jcd[x] = 0.0;
+    for (int x = 0; x < NC * ND; ++x) jcd[x] = 0.0;
 #pragma unroll
     for (int x = 0; x < NA * NC; ++x) kac[x] = 0.0;
 #pragma unroll
@@ -166,120 +141,236 @@ __device__ __forceinline__ void digest(const double* __restrict__ v, double w, b
                     kbc[j * NC + k] = fma(x, dad[i * ND + l], kbc[j * NC + k]);
                     kbd[j * ND + l] = fma(x, dac[i * NC + k], kbd[j * ND + l]);
                 }
-    const double w2 = 2.0 * w;
-#pragma unroll
-    for (int i = 0; i < NA; ++i)
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const double s = wave_sum(w2 * jab[i * NB + j]);
-            if (lane == 0) atomic_add(J + (size_t)(oa + i) * N + ob + j, s);
-        }
-    // runs of adjacent lanes with equal first ket shell; the same shell may recur in a later, separate run (the
-    // wavefront can span two decades of the ket order), so runs are told apart by their index, not by the shell
-    const int kprev = __shfl_up(oc, 1, kWave);
-    const bool head = lane == 0 || kprev != oc;
-    const unsigned long long heads = __ballot(head);
-    const unsigned long long upto = lane == kWave - 1 ? ~0ULL : ((1ULL << (lane + 1)) - 1ULL);
-    const int run = __popcll(heads & upto);
-    bool inseg[6];
-#pragma unroll
-    for (int st = 0; st < 6; ++st) {
-        const int ro = __shfl_up(run, 1 << st, kWave);
-        inseg[st] = lane >= (1 << st) && ro == run;
-    }
-    const bool run_last = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ULL);
-#pragma unroll
-    for (int i = 0; i < NA; ++i)
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            const double s = seg_scan(w * kac[i * NC + k], inseg);
-            if (run_last && s != 0.0) atomic_add(K + (size_t)(oa + i) * N + oc + k, s);
-        }
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            const double s = seg_scan(w * kbc[j * NC + k], inseg);
-            if (run_last && s != 0.0) atomic_add(K + (size_t)(ob + j) * N + oc + k, s);
-        }
-    if (act) {
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-#pragma unroll
-            for (int l = 0; l < ND; ++l) atomic_add(J + (size_t)(oc + k) * N + od + l, w2 * jcd[k * ND + l]);
-#pragma unroll
-        for (int i = 0; i < NA; ++i)
-#pragma unroll
-            for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(oa + i) * N + od + l, w * kad[i * ND + l]);
-#pragma unroll
-        for (int j = 0; j < NB; ++j)
-#pragma unroll
-            for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(ob + j) * N + od + l, w * kbd[j * ND + l]);
-    }
 }
 
+// The wavefront of this lane's work item.  Workgroups are dealt to the kXcds dies round-robin (workgroup b runs on
+// die b mod kXcds); workgroup b is mapped to the (b / kXcds)-th workgroup of a contiguous share of the item list
+// owned by die b mod kXcds, so items that read the same ket chunk share one die's L2.
+__device__ __forceinline__ long long wave_item() {
+    const long long nb = gridDim.x, b = blockIdx.x;
+    const long long per = nb / kXcds, rem = nb % kXcds, x = b % kXcds, k = b / kXcds;
+    const long long blk = x * per + (x < rem ? x : rem) + k;
+    return blk * (kBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
+
+// Task holding launch-wide item `item` (task_begin ascending, task_begin[0] == 0).
+__device__ __forceinline__ int find_task(const long long* __restrict__ task_begin, int ntask, long long item) {
+    int lo = 0, hi = ntask - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (task_begin[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Partial sums a wavefront keeps across its group of bra pairs: J_cd for the whole group, K_ad and K_ac while the
+// bra's first shell a stays the same (bra pairs of a chunk are ordered by a), each where registers allow.
+#ifndef UQC_KEEP_LIMIT
+#define UQC_KEEP_LIMIT 24
+#endif
+constexpr int kKeepLimit = UQC_KEEP_LIMIT;
+
+// Quartet kernel of one class.  Work item = one chunk of 64 ket pairs x a group of bra pairs (TaskDev); lane l
+// holds ket pair 64 * chunk + l for the whole group and loops over the bra pairs, which are wavefront-uniform.
+// Per bra pair: exact per-lane screening and precision routing (the item's ranges are decade-accurate), the
+// primitive sums, horizontal recursion, partial J/K sums.  Reductions: J_ab (one bra pair for all lanes) over the
+// wavefront, then one atomic add; K_ac and K_bc over each run of adjacent lanes sharing the first ket shell c,
+// then one atomic add per run; J_cd, K_ad (and K_bd) per lane.  Idle lanes compute a valid quartet with weight 0.
 template <int LA, int LB, int LC, int LD, bool MIXED>
 __global__ __launch_bounds__(kBlock) void k_digest(const TaskDev* __restrict__ tasks,
                                                    const long long* __restrict__ task_begin, int ntask,
-                                                   long long nitems, unsigned long long perm,
-                                                   const double* __restrict__ boys64tab,
+                                                   long long nitems, const double* __restrict__ boys64tab,
                                                    const float* __restrict__ boys32tab) {
     using C = EriClass<LA, LB, LC, LD>;
-    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const int lane = (int)(threadIdx.x % kWave);
-    const long long slot = (long long)blockIdx.x * (kBlock / kWave) + wid;
-    if (slot >= nitems) return;
-    // Items of one bra pair are consecutive in the work list; a bijective scatter (slot * perm mod nitems, perm
-    // coprime to nitems) makes the wavefronts in flight work on different bra pairs, so their atomic updates of
-    // J_ab and of the K rows of shells a and b do not pile onto the same addresses.
-    const long long item = (long long)(((unsigned long long)slot * perm) % (unsigned long long)nitems);
-    int t = 0;
-    {
-        int lo = 0, hi = ntask - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (task_begin[mid] <= item) lo = mid; else hi = mid - 1;
-        }
-        t = lo;
-    }
-    const TaskDev& tk = tasks[t];
+    constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
+    constexpr int NAB = NA * NB, NCD = NC * ND;
+    constexpr bool KEEP_KAD = NCD + NA * ND <= kKeepLimit;
+    constexpr bool KEEP_KAC = KEEP_KAD && NCD + NA * ND + NA * NC <= kKeepLimit;
+    const long long item = wave_item();
+    if (item >= nitems) return;
+    const TaskDev& tk = tasks[find_task(task_begin, ntask, item)];
     const long long li = item - tk.item_begin;
-    int bra = 0;
-    {
-        int lo = 0, hi = tk.nbra - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (tk.item_off[mid] <= li) lo = mid; else hi = mid - 1;
-        }
-        bra = lo;
-    }
-    const int kend = tk.hi[bra];
-    int ket = tk.lo[bra] + (int)(li - tk.item_off[bra]) * kWave + lane;
-    bool act = ket < kend;
-    if (!act) ket = kend - 1;  // idle lanes recompute a valid quartet with weight 0 (keeps the wave converged)
-    {
-        // exact screening and precision routing per lane (the work range is only decade-accurate)
-        const double q = tk.bra.Q[bra] * tk.ket.Q[ket];
-        act = act && q >= tk.tau && q > tk.lo_excl && q <= tk.hi_incl;
-    }
-    const unsigned long long live = __ballot(act);
-    if (live == 0ULL) return;  // uniform: nothing of this item survives screening
-    if (lane == 0) atomicAdd(tk.count, (unsigned long long)__popcll(live));
-
-    double acc[C::NACC];
-#pragma unroll
-    for (int x = 0; x < C::NACC; ++x) acc[x] = 0.0;
-    accumulate<C, MIXED>(tk.bra, bra, tk.ket, ket, boys64tab, boys32tab, acc);
-
+    const int2 it = tk.items[li];
+    const int gend = tk.items[li + 1].x;
     const BinDev& B = tk.bra;
     const BinDev& Kt = tk.ket;
-    double out[C::NA * C::NB * C::NC * C::ND];
-    C::hrr(acc, B.AB[bra], B.AB[B.np + bra], B.AB[2 * B.np + bra], Kt.AB[ket], Kt.AB[Kt.np + ket],
-           Kt.AB[2 * Kt.np + ket], out);
-    double w = act ? B.sdeg[bra] * Kt.sdeg[ket] : 0.0;
-    if (tk.same && ket == bra) w *= 0.5;
-    digest<C::NA, C::NB, C::NC, C::ND>(out, w, act, lane, B.off_a[bra], B.off_b[bra], Kt.off_a[ket],
-                                       Kt.off_b[ket], tk.D, tk.J, tk.K, tk.nbf);
+    const int lane = (int)(threadIdx.x % kWave);
+    const int ket = it.y * kWave + lane;
+    const bool ket_ok = ket < Kt.np;
+    const int kc = ket_ok ? ket : Kt.np - 1;
+    const double qk = Kt.Q[kc];
+    const double* __restrict__ D = tk.D;
+    double* __restrict__ J = tk.J;
+    double* __restrict__ K = tk.K;
+    const int N = tk.nbf;
+    // Only the ket index, its bound and the kept sums live across the loop; everything else about the ket is
+    // re-read (from cache) through an index the compiler cannot see through, which keeps register use low.
+    auto opaque = [](int x) {
+        asm volatile("" : "+v"(x));
+        return x;
+    };
+    // runs of adjacent lanes with equal first ket shell; the same shell may recur in a later, separate run (a
+    // chunk can span two decades of the ket order), so runs are told apart by their index, not by the shell
+    auto runs = [&](int oc, bool* inseg, bool& run_last) {
+        const int kprev = __shfl_up(oc, 1, kWave);
+        const bool head = lane == 0 || kprev != oc;
+        const unsigned long long heads = __ballot(head);
+        const unsigned long long upto = lane == kWave - 1 ? ~0ULL : ((1ULL << (lane + 1)) - 1ULL);
+        const int run = __popcll(heads & upto);
+#pragma unroll
+        for (int st = 0; st < 6; ++st) {
+            const int ro = __shfl_up(run, 1 << st, kWave);
+            inseg[st] = lane >= (1 << st) && ro == run;
+        }
+        run_last = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ULL);
+    };
+
+    double jcd_s[NCD], kad_s[KEEP_KAD ? NA * ND : 1], kac_s[KEEP_KAC ? NA * NC : 1];
+#pragma unroll
+    for (int x = 0; x < NCD; ++x) jcd_s[x] = 0.0;
+#pragma unroll
+    for (int x = 0; x < (KEEP_KAD ? NA * ND : 1); ++x) kad_s[x] = 0.0;
+#pragma unroll
+    for (int x = 0; x < (KEEP_KAC ? NA * NC : 1); ++x) kac_s[x] = 0.0;
+    int cur_a = -1;  // wavefront-uniform: first shell of the bra pairs whose K_ad / K_ac sums are held
+    auto flush_a = [&]() {
+        const int kl = opaque(kc);
+        const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
+        if constexpr (KEEP_KAD) {
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int l = 0; l < ND; ++l) {
+                    const double s = kad_s[i * ND + l];
+                    if (s != 0.0) atomic_add(K + (size_t)(cur_a + i) * N + od + l, s);
+                    kad_s[i * ND + l] = 0.0;
+                }
+        }
+        if constexpr (KEEP_KAC) {
+            bool inseg[6], run_last;
+            runs(oc, inseg, run_last);
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    const double s = seg_scan(kac_s[i * NC + k], inseg);
+                    if (run_last && s != 0.0) atomic_add(K + (size_t)(cur_a + i) * N + oc + k, s);
+                    kac_s[i * NC + k] = 0.0;
+                }
+        }
+    };
+    unsigned long long cnt = 0;
+    for (int e = it.x; e < gend; ++e) {
+        const int bra = __builtin_amdgcn_readfirstlane(as_const(tk.blist)[e]);  // wavefront-uniform
+        const cdptr bh = as_const(B.hdr) + (size_t)bra * kHdr;  // AB, sdeg, Q, offsets of the bra pair
+        const double q = bh[4] * qk;
+        const bool act = ket_ok && ket >= as_const(tk.lo)[bra] && ket < as_const(tk.hi)[bra] && q >= tk.tau &&
+                         q > tk.lo_excl && q <= tk.hi_incl;
+        const unsigned long long live = __ballot(act);
+        if (live == 0ULL) continue;  // uniform: no quartet of this bra pair survives in the chunk
+        cnt += (unsigned long long)__popcll(live);
+        const int oa = ((ciptr)(bh + 5))[0], ob = ((ciptr)(bh + 5))[1];
+        if (oa != cur_a) {
+            if (cur_a >= 0) flush_a();
+            cur_a = oa;
+        }
+        const int kl = opaque(kc);
+        double out[NAB * NCD];
+        {
+            double acc[C::NACC];
+#pragma unroll
+            for (int x = 0; x < C::NACC; ++x) acc[x] = 0.0;
+            accumulate<C, MIXED>(B, bra, Kt, kl, boys64tab, boys32tab, acc);
+            C::hrr(acc, bh[0], bh[1], bh[2], Kt.AB[kl], Kt.AB[Kt.np + kl],
+                   Kt.AB[2 * Kt.np + kl], out);
+        }
+        const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
+        double w = act ? bh[3] * Kt.sdeg[kl] : 0.0;
+        if (tk.same && ket == bra) w *= 0.5;
+        double dab[NAB], dcd[NCD], dbd[NB * ND], dbc[NB * NC], dad[NA * ND], dac[NA * NC];
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) dab[i * NB + j] = as_const(D)[(size_t)(oa + i) * N + ob + j];
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+            for (int l = 0; l < ND; ++l) dcd[k * ND + l] = D[(size_t)(oc + k) * N + od + l];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+#pragma unroll
+            for (int l = 0; l < ND; ++l) dbd[j * ND + l] = D[(size_t)(ob + j) * N + od + l];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) dbc[j * NC + k] = D[(size_t)(ob + j) * N + oc + k];
+        }
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+#pragma unroll
+            for (int l = 0; l < ND; ++l) dad[i * ND + l] = D[(size_t)(oa + i) * N + od + l];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) dac[i * NC + k] = D[(size_t)(oa + i) * N + oc + k];
+        }
+        double jab[NAB], jcd[NCD], kac[NA * NC], kad[NA * ND], kbc[NB * NC], kbd[NB * ND];
+        partials<NA, NB, NC, ND>(out, dab, dcd, dbd, dbc, dad, dac, jab, jcd, kac, kad, kbc, kbd);
+        const double w2 = 2.0 * w;
+#pragma unroll
+        for (int x = 0; x < NAB; ++x) {
+            const double s = wave_sum(w2 * jab[x]);
+            if (lane == 0) atomic_add(J + (size_t)(oa + x / NB) * N + ob + x % NB, s);
+        }
+#pragma unroll
+        for (int x = 0; x < NCD; ++x) jcd_s[x] = fma(w2, jcd[x], jcd_s[x]);
+        bool inseg[6], run_last;
+        runs(oc, inseg, run_last);
+        if constexpr (KEEP_KAC) {
+#pragma unroll
+            for (int x = 0; x < NA * NC; ++x) kac_s[x] = fma(w, kac[x], kac_s[x]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    const double s = seg_scan(w * kac[i * NC + k], inseg);
+                    if (run_last && s != 0.0) atomic_add(K + (size_t)(oa + i) * N + oc + k, s);
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                const double s = seg_scan(w * kbc[j * NC + k], inseg);
+                if (run_last && s != 0.0) atomic_add(K + (size_t)(ob + j) * N + oc + k, s);
+            }
+        if constexpr (KEEP_KAD) {
+#pragma unroll
+            for (int x = 0; x < NA * ND; ++x) kad_s[x] = fma(w, kad[x], kad_s[x]);
+        }
+        if (act) {
+            if constexpr (!KEEP_KAD) {
+#pragma unroll
+                for (int i = 0; i < NA; ++i)
+#pragma unroll
+                    for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(oa + i) * N + od + l, w * kad[i * ND + l]);
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(ob + j) * N + od + l, w * kbd[j * ND + l]);
+        }
+    }
+    if (cur_a >= 0) flush_a();
+    {
+        const int kl = opaque(kc);
+        const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+#pragma unroll
+            for (int l = 0; l < ND; ++l) {
+                const double s = jcd_s[k * ND + l];
+                if (s != 0.0) atomic_add(J + (size_t)(oc + k) * N + od + l, s);
+            }
+    }
+    if (lane == 0 && cnt) atomicAdd(tk.count, cnt);
 }
 
 template <int LA, int LB, int LC, int LD, bool MIXED, int MODE>

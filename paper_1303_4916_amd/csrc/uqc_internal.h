@@ -9,26 +9,35 @@ constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kBlock = 256;            // threads per block of the quartet kernels (4 wavefronts)
 constexpr int kMaxK = 16;              // maximum contraction depth
 constexpr int kBoysGridPerUnit = 8;    // Boys Taylor grid: T_g = g / 8 (exact in binary, same points in FP32/FP64)
-constexpr int kBoysTmax = 40;          // grid covers [0, 40); asymptotic form beyond
+constexpr int kBoysTmax = 60;          // grid covers [0, 60); asymptotic form beyond
 constexpr int kBoysNg = kBoysTmax * kBoysGridPerUnit + 1;
 constexpr int kBoysNm = 18;            // per grid point: F_0 .. F_16 (m <= 8 plus Taylor order 8), then exp(-T_g)
 constexpr int kBoysExpCol = 17;
-// Device layout of the FP64 table: one slice per highest order L = 0..8, each row holding F_L .. F_{L+8} and
-// exp(-T_g) (10 doubles, 80 bytes, 16-byte aligned), so a Boys evaluation reads one row with five 16-byte loads.
+// Device layout of the FP64 table: one slice per highest order L = 0..8, each row holding the Taylor coefficients
+// F_{L+k}(T_g) / k!, k = 0..8, and exp(-T_g) (10 doubles, 80 bytes, 16-byte aligned), so a Boys evaluation reads
+// one row with five 16-byte loads.
 constexpr int kBoysRow = 10;
 constexpr int kBoysLmax = 8;
 constexpr int kBoysTmax32 = 30;        // FP32 evaluation limit in mixed mode
 constexpr int kNumClasses = 21;
 constexpr int kTeamKets = 10;          // ket pairs per wavefront in the six-lane team kernels
+constexpr int kGroupBras = 8;          // bra pairs per work item (one wavefront), 64-ket kernels
+constexpr int kTeamGroupBras = 4;      // bra pairs per work item, team kernels
+constexpr int kXcds = 8;               // accelerator complex dies; workgroups are dealt to them round-robin
 
-// Primitive-pair fields, stored field-major: prim[field][k][np] (consecutive pairs contiguous)
+// Primitive-pair fields, stored field-major: prim[field][k][np] (consecutive pairs contiguous; the ket side, one
+// pair per lane), and again pair-major: rec[np][k][kRec] (the bra side, one pair per wavefront, scalar loads)
 enum PrimField { F_Z = 0, F_PX, F_PY, F_PZ, F_PAX, F_PAY, F_PAZ, F_PREF, F_O2Z, kNumFields };
+constexpr int kRec = 10;               // doubles per pair-major primitive record (kNumFields + 1 pad)
+constexpr int kHdr = 8;                // doubles per pair header: A-B (3), sdeg, Q, {off_a, off_b} (two ints), pad
 
 // One bin of shell pairs with the same (l_a, l_b, K_a, K_b).  Pairs are ordered by decade of their Schwarz bound
 // (descending), then by their first shell, so that the ket range of any bra pair is a prefix at decade granularity
 // and kets sharing their first shell are adjacent inside a wavefront.
 struct BinDev {
     const double* prim;   // [kNumFields][K][np]
+    const double* rec;    // [np][K][kRec] the same fields, pair-major
+    const double* hdr;    // [np][kHdr] AB, sdeg, Q and the two offsets of every pair
     const double* AB;     // [3][np]  A - B
     const int* off_a;     // [np] first basis function of shell a (the higher-l shell)
     const int* off_b;     // [np]
@@ -38,13 +47,17 @@ struct BinDev {
     int K;                // primitive pairs per shell pair (K_a * K_b)
 };
 
-// One (bra bin, ket bin) block of the quartet work list of a Fock build.
+// One (bra bin, ket bin) block of the quartet work list of a Fock build.  The ket bin is cut into chunks of S
+// consecutive ket pairs (S = 64, or 10 for the team kernels); a work item is one chunk and a group of up to
+// kGroupBras (kTeamGroupBras) bra pairs whose ket ranges meet that chunk.  Items are ordered chunk by chunk, and
+// inside a chunk the bra pairs are ordered by their first shell, so a wavefront keeps its kets (and their partial
+// J_cd, K_ad, K_ac sums) across the group, and the items that share a chunk run on one die close in time.
 struct TaskDev {
     BinDev bra, ket;
     const int* lo;             // [nbra] first ket index (in the ket bin)
     const int* hi;             // [nbra] one past the last ket index
-    const long long* item_off; // [nbra + 1] exclusive prefix of ceil((hi - lo) / kets per item: 64, or 10 for
-                               // the team kernels)
+    const int* blist;          // bra indices, chunk by chunk
+    const int2* items;         // [nitems + 1] {first blist entry, chunk}; the group ends at the next item's entry
     long long item_begin;      // first work item of this task within its launch
     long long nitems;
     double tau;                // a quartet in the range is computed iff Q_ab Q_cd >= tau
@@ -72,8 +85,7 @@ enum Mode { MODE_STORE = 0, MODE_SCHWARZ = 1 };
 // Host launchers of one angular-momentum class (defined in uqc_eri_class.hip, one object per class).
 struct ClassLaunchers {
     hipError_t (*digest)(bool mixed, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
-                         long long nitems, unsigned long long perm, const double* boys64, const float* boys32,
-                         hipStream_t s);
+                         long long nitems, const double* boys64, const float* boys32, hipStream_t s);
     hipError_t (*list)(bool mixed, int mode, const ListDev& list, const double* boys64, const float* boys32,
                        hipStream_t s);
 };

@@ -48,19 +48,7 @@ hipError_t launch_digest(int cls, bool mixed, const TaskDev* d_tasks, const long
                          long long nitems, const double* boys64tab, const float* boys32tab, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     if (cls < 0 || cls >= kNumClasses) return hipErrorInvalidValue;
-    // scatter multiplier: near nitems / golden ratio, coprime to nitems, small enough that slot * perm < 2^63
-    unsigned long long n = (unsigned long long)nitems;
-    unsigned long long p = (unsigned long long)((double)n * 0.6180339887498949) | 1ULL;
-    const unsigned long long pmax = (1ULL << 62) / (n + 1);
-    if (p > pmax) p = pmax | 1ULL;
-    if (p < 1) p = 1;
-    auto gcd = [](unsigned long long a, unsigned long long b) {
-        while (b) { const unsigned long long t = a % b; a = b; b = t; }
-        return a;
-    };
-    while (n > 1 && gcd(p, n) != 1) p += 2;
-    if (n <= 1) p = 1;
-    return launchers(cls).digest(mixed, d_tasks, d_task_begin, ntask, nitems, p, boys64tab, boys32tab, s);
+    return launchers(cls).digest(mixed, d_tasks, d_task_begin, ntask, nitems, boys64tab, boys32tab, s);
 }
 
 hipError_t launch_list(int cls, bool mixed, int mode, const ListDev& list, const double* boys64tab,
