@@ -52,22 +52,31 @@ __device__ __forceinline__ double rsqrt64(double x) {
 // For T >= 60: F_0 = sqrt(pi/T)/2 (erf(sqrt(T)) = 1 to double precision) and the upward recursion
 // F_{m+1} = (2m+1) F_m / (2T); the exp(-T) term the exact recursion subtracts is below 1e-26 and changes no F_m,
 // m <= 8, by more than 2e-17 of its value.
+// The two halves of boys64: the table row for T (grid index clamped, so the row can be fetched ahead of the test
+// on T), then the evaluation from that row.
 template <int L>
-__device__ __forceinline__ void boys64(double T, double pref, const double* __restrict__ tab, double* F) {
+__device__ __forceinline__ void boys64_row(double T, const double* __restrict__ tab, double2* r) {
+    const double gd = fmin(T * (double)kBoysGridPerUnit + 0.5, (double)(kBoysNg - 1));
+    const int g = (int)gd;
+    const double2* row = reinterpret_cast<const double2*>(tab + ((size_t)L * kBoysNg + g) * kBoysRow);
+#pragma unroll
+    for (int x = 0; x < kBoysRow / 2; ++x) r[x] = row[x];
+}
+
+template <int L>
+__device__ __forceinline__ void boys64_eval(double T, double pref, const double2* r, double* F) {
     if (T < (double)kBoysTmax) {
         const int g = (int)(T * (double)kBoysGridPerUnit + 0.5);
         const double d = (double)g * (1.0 / kBoysGridPerUnit) - T;  // exact grid point
-        const double2* row = reinterpret_cast<const double2*>(tab + ((size_t)L * kBoysNg + g) * kBoysRow);
-        const double2 r01 = row[0], r23 = row[1], r45 = row[2], r67 = row[3], r8e = row[4];
-        double p = r8e.x;
-        p = fma(p, d, r67.y);
-        p = fma(p, d, r67.x);
-        p = fma(p, d, r45.y);
-        p = fma(p, d, r45.x);
-        p = fma(p, d, r23.y);
-        p = fma(p, d, r23.x);
-        p = fma(p, d, r01.y);
-        p = fma(p, d, r01.x);
+        double p = r[4].x;
+        p = fma(p, d, r[3].y);
+        p = fma(p, d, r[3].x);
+        p = fma(p, d, r[2].y);
+        p = fma(p, d, r[2].x);
+        p = fma(p, d, r[1].y);
+        p = fma(p, d, r[1].x);
+        p = fma(p, d, r[0].y);
+        p = fma(p, d, r[0].x);
         F[L] = p * pref;
         if constexpr (L > 0) {
             double x = 1.0 / 362880.0;
@@ -80,20 +89,27 @@ __device__ __forceinline__ void boys64(double T, double pref, const double* __re
             x = fma(x, d, 0.5);
             x = fma(x, d, 1.0);
             x = fma(x, d, 1.0);
-            const double e = r8e.y * x * pref;
+            const double e = r[4].y * x * pref;
             const double t2 = T + T;
 #pragma unroll
             for (int m = L - 1; m >= 0; --m) F[m] = fma(t2, F[m + 1], e) * (1.0 / (2 * m + 1));
         }
     } else {
-        const double r = rsqrt64(T);
-        F[0] = (0.88622692545275801365 * pref) * r;  // sqrt(pi)/2
+        const double rs = rsqrt64(T);
+        F[0] = (0.88622692545275801365 * pref) * rs;  // sqrt(pi)/2
         if constexpr (L > 0) {
-            const double h = 0.5 * r * r;
+            const double h = 0.5 * rs * rs;
 #pragma unroll
             for (int m = 0; m < L; ++m) F[m + 1] = ((double)(2 * m + 1) * h) * F[m];
         }
     }
+}
+
+template <int L>
+__device__ __forceinline__ void boys64(double T, double pref, const double* __restrict__ tab, double* F) {
+    double2 r[kBoysRow / 2];
+    boys64_row<L>(T, tab, r);
+    boys64_eval<L>(T, pref, r, F);
 }
 
 // FP32 variant (mixed mode, T <= 30 only): Taylor order 5 around the same grid points (truncation < 1e-10

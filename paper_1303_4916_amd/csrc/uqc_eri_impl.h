@@ -105,26 +105,21 @@ __device__ __forceinline__ double seg_scan(double x, const bool* inseg) {
     return x;
 }
 
-// Partial J/K sums of one contracted quartet block v = (ab|cd) (raw components) against the scaled density:
-// jab = v.D_cd, jcd = v.D_ab, kac = v.D_bd, kad = v.D_bc, kbc = v.D_ad, kbd = v.D_ac (Eq. 12 with the 8-fold
-// permutational symmetry; the accumulators are symmetrised, J + J^T and K + K^T, in the finalize step).
-template <int NA, int NB, int NC, int ND>
-__device__ __forceinline__ void partials(const double* __restrict__ v, const double* dab, const double* dcd,
-                                         const double* dbd, const double* dbc, const double* dad, const double* dac,
-                                         double* jab, double* jcd, double* kac, double* kad, double* kbc,
-                                         double* kbd) {
+// Partial J/K sums of one contracted quartet block v = (ab|cd) (raw components) against the scaled density, two
+// at a time (Eq. 12 with the 8-fold permutational symmetry; the accumulators are symmetrised, J + J^T and K + K^T,
+// in the finalize step):
+//   P = 0:  x = v.D_cd  [NA*NB],  y = v.D_ab  [NC*ND]    (J_ab, J_cd)     -- d1 = D_cd, d2 = D_ab
+//   P = 1:  x = v.D_bd  [NA*NC],  y = v.D_ac  [NB*ND]    (K_ac, K_bd)     -- d1 = D_bd, d2 = D_ac
+//   P = 2:  x = v.D_bc  [NA*ND],  y = v.D_ad  [NB*NC]    (K_ad, K_bc)     -- d1 = D_bc, d2 = D_ad
+template <int NA, int NB, int NC, int ND, int P>
+__device__ __forceinline__ void contract_pair(const double* __restrict__ v, const double* d1, const double* d2,
+                                              double* x, double* y) {
+    constexpr int NX = P == 0 ? NA * NB : (P == 1 ? NA * NC : NA * ND);
+    constexpr int NY = P == 0 ? NC * ND : (P == 1 ? NB * ND : NB * NC);
 #pragma unroll
-    for (int x = 0; x < NA * NB; ++x) jab[x] = 0.0;
+    for (int e = 0; e < NX; ++e) x[e] = 0.0;
 #pragma unroll
-    for (int x = 0; x < NC * ND; ++x) jcd[x] = 0.0;
-#pragma unroll
-    for (int x = 0; x < NA * NC; ++x) kac[x] = 0.0;
-#pragma unroll
-    for (int x = 0; x < NA * ND; ++x) kad[x] = 0.0;
-#pragma unroll
-    for (int x = 0; x < NB * NC; ++x) kbc[x] = 0.0;
-#pragma unroll
-    for (int x = 0; x < NB * ND; ++x) kbd[x] = 0.0;
+    for (int e = 0; e < NY; ++e) y[e] = 0.0;
 #pragma unroll
     for (int i = 0; i < NA; ++i)
 #pragma unroll
@@ -133,13 +128,17 @@ __device__ __forceinline__ void partials(const double* __restrict__ v, const dou
             for (int k = 0; k < NC; ++k)
 #pragma unroll
                 for (int l = 0; l < ND; ++l) {
-                    const double x = v[((i * NB + j) * NC + k) * ND + l];
-                    jab[i * NB + j] = fma(x, dcd[k * ND + l], jab[i * NB + j]);
-                    jcd[k * ND + l] = fma(x, dab[i * NB + j], jcd[k * ND + l]);
-                    kac[i * NC + k] = fma(x, dbd[j * ND + l], kac[i * NC + k]);
-                    kad[i * ND + l] = fma(x, dbc[j * NC + k], kad[i * ND + l]);
-                    kbc[j * NC + k] = fma(x, dad[i * ND + l], kbc[j * NC + k]);
-                    kbd[j * ND + l] = fma(x, dac[i * NC + k], kbd[j * ND + l]);
+                    const double t = v[((i * NB + j) * NC + k) * ND + l];
+                    if constexpr (P == 0) {
+                        x[i * NB + j] = fma(t, d1[k * ND + l], x[i * NB + j]);
+                        y[k * ND + l] = fma(t, d2[i * NB + j], y[k * ND + l]);
+                    } else if constexpr (P == 1) {
+                        x[i * NC + k] = fma(t, d1[j * ND + l], x[i * NC + k]);
+                        y[j * ND + l] = fma(t, d2[i * NC + k], y[j * ND + l]);
+                    } else {
+                        x[i * ND + l] = fma(t, d1[j * NC + k], x[i * ND + l]);
+                        y[j * NC + k] = fma(t, d2[i * ND + l], y[j * NC + k]);
+                    }
                 }
 }
 
@@ -163,12 +162,20 @@ __device__ __forceinline__ int find_task(const long long* __restrict__ task_begi
     return lo;
 }
 
+#ifndef UQC_WAVES_ATTR
+#define UQC_WAVES_ATTR
+#endif
+
 // Partial sums a wavefront keeps across its group of bra pairs: J_cd for the whole group, K_ad and K_ac while the
 // bra's first shell a stays the same (bra pairs of a chunk are ordered by a), each where registers allow.
 #ifndef UQC_KEEP_LIMIT
 #define UQC_KEEP_LIMIT 24
 #endif
+#ifndef UQC_KAC_LDS
+#define UQC_KAC_LDS 1
+#endif
 constexpr int kKeepLimit = UQC_KEEP_LIMIT;
+constexpr bool kKacInLds = UQC_KAC_LDS != 0;
 
 // Quartet kernel of one class.  Work item = one chunk of 64 ket pairs x a group of bra pairs (TaskDev); lane l
 // holds ket pair 64 * chunk + l for the whole group and loops over the bra pairs, which are wavefront-uniform.
@@ -177,15 +184,21 @@ constexpr int kKeepLimit = UQC_KEEP_LIMIT;
 // wavefront, then one atomic add; K_ac and K_bc over each run of adjacent lanes sharing the first ket shell c,
 // then one atomic add per run; J_cd, K_ad (and K_bd) per lane.  Idle lanes compute a valid quartet with weight 0.
 template <int LA, int LB, int LC, int LD, bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_digest(const TaskDev* __restrict__ tasks,
+__global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev* __restrict__ tasks,
                                                    const long long* __restrict__ task_begin, int ntask,
                                                    long long nitems, const double* __restrict__ boys64tab,
                                                    const float* __restrict__ boys32tab) {
     using C = EriClass<LA, LB, LC, LD>;
     constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
     constexpr int NAB = NA * NB, NCD = NC * ND;
-    constexpr bool KEEP_KAD = NCD + NA * ND <= kKeepLimit;
-    constexpr bool KEEP_KAC = KEEP_KAD && NCD + NA * ND + NA * NC <= kKeepLimit;
+    // where the K_ad and K_ac sums of a same-a run are kept: 1 = registers, 2 = the lane's private LDS slots,
+    // 0 = not kept (summed over the lanes of each c-run and added per bra pair)
+    constexpr int KAD_MODE = NCD + NA * ND <= kKeepLimit ? 1 : 2;
+    constexpr int KAC_MODE = (KAD_MODE == 1 && NCD + NA * ND + NA * NC <= kKeepLimit) ? 1 : (kKacInLds ? 2 : 0);
+    constexpr bool KEEP_KAD = KAD_MODE != 0;
+    constexpr bool KEEP_KAC = KAC_MODE != 0;
+    constexpr int SLOTS = (KAD_MODE == 2 ? NA * ND : 0) + (KAC_MODE == 2 ? NA * NC : 0);
+    __shared__ double slots[kBlock / kWave][SLOTS > 0 ? SLOTS * kWave : 1];
     const long long item = wave_item();
     if (item >= nitems) return;
     const TaskDev& tk = tasks[find_task(task_begin, ntask, item)];
@@ -225,13 +238,24 @@ __global__ __launch_bounds__(kBlock) void k_digest(const TaskDev* __restrict__ t
         run_last = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ULL);
     };
 
-    double jcd_s[NCD], kad_s[KEEP_KAD ? NA * ND : 1], kac_s[KEEP_KAC ? NA * NC : 1];
+    double jcd_s[NCD], kad_s[KAD_MODE == 1 ? NA * ND : 1], kac_s[KAC_MODE == 1 ? NA * NC : 1];
 #pragma unroll
     for (int x = 0; x < NCD; ++x) jcd_s[x] = 0.0;
 #pragma unroll
-    for (int x = 0; x < (KEEP_KAD ? NA * ND : 1); ++x) kad_s[x] = 0.0;
+    for (int x = 0; x < (KAD_MODE == 1 ? NA * ND : 1); ++x) kad_s[x] = 0.0;
 #pragma unroll
-    for (int x = 0; x < (KEEP_KAC ? NA * NC : 1); ++x) kac_s[x] = 0.0;
+    for (int x = 0; x < (KAC_MODE == 1 ? NA * NC : 1); ++x) kac_s[x] = 0.0;
+    // LDS slots of this lane: slot x at kept[x * kWave] (lane-contiguous, no bank conflicts, private to the lane)
+    double* kept_ad = &slots[threadIdx.x / kWave][lane];
+    double* kept_ac = kept_ad + (KAD_MODE == 2 ? NA * ND * kWave : 0);
+#pragma unroll
+    for (int x = 0; x < SLOTS; ++x) kept_ad[x * kWave] = 0.0;
+    auto kad_get = [&](int x) -> double& {
+        if constexpr (KAD_MODE == 2) return kept_ad[x * kWave]; else return kad_s[x];
+    };
+    auto kac_get = [&](int x) -> double& {
+        if constexpr (KAC_MODE == 2) return kept_ac[x * kWave]; else return kac_s[x];
+    };
     int cur_a = -1;  // wavefront-uniform: first shell of the bra pairs whose K_ad / K_ac sums are held
     auto flush_a = [&]() {
         const int kl = opaque(kc);
@@ -241,9 +265,10 @@ __global__ __launch_bounds__(kBlock) void k_digest(const TaskDev* __restrict__ t
             for (int i = 0; i < NA; ++i)
 #pragma unroll
                 for (int l = 0; l < ND; ++l) {
-                    const double s = kad_s[i * ND + l];
+                    double& r = kad_get(i * ND + l);
+                    const double s = r;
+                    r = 0.0;
                     if (s != 0.0) atomic_add(K + (size_t)(cur_a + i) * N + od + l, s);
-                    kad_s[i * ND + l] = 0.0;
                 }
         }
         if constexpr (KEEP_KAC) {
@@ -253,9 +278,10 @@ __global__ __launch_bounds__(kBlock) void k_digest(const TaskDev* __restrict__ t
             for (int i = 0; i < NA; ++i)
 #pragma unroll
                 for (int k = 0; k < NC; ++k) {
-                    const double s = seg_scan(kac_s[i * NC + k], inseg);
+                    double& r = kac_get(i * NC + k);
+                    const double s = seg_scan(r, inseg);
+                    r = 0.0;
                     if (run_last && s != 0.0) atomic_add(K + (size_t)(cur_a + i) * N + oc + k, s);
-                    kac_s[i * NC + k] = 0.0;
                 }
         }
     };
@@ -287,75 +313,87 @@ __global__ __launch_bounds__(kBlock) void k_digest(const TaskDev* __restrict__ t
         const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
         double w = act ? bh[3] * Kt.sdeg[kl] : 0.0;
         if (tk.same && ket == bra) w *= 0.5;
-        double dab[NAB], dcd[NCD], dbd[NB * ND], dbc[NB * NC], dad[NA * ND], dac[NA * NC];
-#pragma unroll
-        for (int i = 0; i < NA; ++i)
-#pragma unroll
-            for (int j = 0; j < NB; ++j) dab[i * NB + j] = as_const(D)[(size_t)(oa + i) * N + ob + j];
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-#pragma unroll
-            for (int l = 0; l < ND; ++l) dcd[k * ND + l] = D[(size_t)(oc + k) * N + od + l];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-#pragma unroll
-            for (int l = 0; l < ND; ++l) dbd[j * ND + l] = D[(size_t)(ob + j) * N + od + l];
-#pragma unroll
-            for (int k = 0; k < NC; ++k) dbc[j * NC + k] = D[(size_t)(ob + j) * N + oc + k];
-        }
-#pragma unroll
-        for (int i = 0; i < NA; ++i) {
-#pragma unroll
-            for (int l = 0; l < ND; ++l) dad[i * ND + l] = D[(size_t)(oa + i) * N + od + l];
-#pragma unroll
-            for (int k = 0; k < NC; ++k) dac[i * NC + k] = D[(size_t)(oa + i) * N + oc + k];
-        }
-        double jab[NAB], jcd[NCD], kac[NA * NC], kad[NA * ND], kbc[NB * NC], kbd[NB * ND];
-        partials<NA, NB, NC, ND>(out, dab, dcd, dbd, dbc, dad, dac, jab, jcd, kac, kad, kbc, kbd);
+        // Digest in three passes over the block (J; K_ac with K_bd; K_ad with K_bc), so that only two density
+        // slices and two partial blocks are live at a time.
         const double w2 = 2.0 * w;
-#pragma unroll
-        for (int x = 0; x < NAB; ++x) {
-            const double s = wave_sum(w2 * jab[x]);
-            if (lane == 0) atomic_add(J + (size_t)(oa + x / NB) * N + ob + x % NB, s);
-        }
-#pragma unroll
-        for (int x = 0; x < NCD; ++x) jcd_s[x] = fma(w2, jcd[x], jcd_s[x]);
-        bool inseg[6], run_last;
-        runs(oc, inseg, run_last);
-        if constexpr (KEEP_KAC) {
-#pragma unroll
-            for (int x = 0; x < NA * NC; ++x) kac_s[x] = fma(w, kac[x], kac_s[x]);
-        } else {
+        {
+            double dab[NAB], dcd[NCD], jab[NAB], jcd[NCD];
 #pragma unroll
             for (int i = 0; i < NA; ++i)
 #pragma unroll
-                for (int k = 0; k < NC; ++k) {
-                    const double s = seg_scan(w * kac[i * NC + k], inseg);
-                    if (run_last && s != 0.0) atomic_add(K + (size_t)(oa + i) * N + oc + k, s);
-                }
-        }
+                for (int j = 0; j < NB; ++j) dab[i * NB + j] = as_const(D)[(size_t)(oa + i) * N + ob + j];
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
+            for (int k = 0; k < NC; ++k)
 #pragma unroll
-            for (int k = 0; k < NC; ++k) {
-                const double s = seg_scan(w * kbc[j * NC + k], inseg);
-                if (run_last && s != 0.0) atomic_add(K + (size_t)(ob + j) * N + oc + k, s);
+                for (int l = 0; l < ND; ++l) dcd[k * ND + l] = D[(size_t)(oc + k) * N + od + l];
+            contract_pair<NA, NB, NC, ND, 0>(out, dcd, dab, jab, jcd);
+#pragma unroll
+            for (int x = 0; x < NAB; ++x) {
+                const double s = wave_sum(w2 * jab[x]);
+                if (lane == 0) atomic_add(J + (size_t)(oa + x / NB) * N + ob + x % NB, s);
             }
-        if constexpr (KEEP_KAD) {
 #pragma unroll
-            for (int x = 0; x < NA * ND; ++x) kad_s[x] = fma(w, kad[x], kad_s[x]);
+            for (int x = 0; x < NCD; ++x) jcd_s[x] = fma(w2, jcd[x], jcd_s[x]);
         }
-        if (act) {
-            if constexpr (!KEEP_KAD) {
+        bool inseg[6], run_last;
+        runs(oc, inseg, run_last);
+        {
+            double dbd[NB * ND], dac[NA * NC], kac[NA * NC], kbd[NB * ND];
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int l = 0; l < ND; ++l) dbd[j * ND + l] = D[(size_t)(ob + j) * N + od + l];
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) dac[i * NC + k] = D[(size_t)(oa + i) * N + oc + k];
+            contract_pair<NA, NB, NC, ND, 1>(out, dbd, dac, kac, kbd);
+            if constexpr (KEEP_KAC) {
+#pragma unroll
+                for (int x = 0; x < NA * NC; ++x) kac_get(x) += w * kac[x];
+            } else {
+#pragma unroll
+                for (int i = 0; i < NA; ++i)
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+                        const double s = seg_scan(w * kac[i * NC + k], inseg);
+                        if (run_last && s != 0.0) atomic_add(K + (size_t)(oa + i) * N + oc + k, s);
+                    }
+            }
+            if (act) {
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(ob + j) * N + od + l, w * kbd[j * ND + l]);
+            }
+        }
+        {
+            double dbc[NB * NC], dad[NA * ND], kad[NA * ND], kbc[NB * NC];
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) dbc[j * NC + k] = D[(size_t)(ob + j) * N + oc + k];
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int l = 0; l < ND; ++l) dad[i * ND + l] = D[(size_t)(oa + i) * N + od + l];
+            contract_pair<NA, NB, NC, ND, 2>(out, dbc, dad, kad, kbc);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    const double s = seg_scan(w * kbc[j * NC + k], inseg);
+                    if (run_last && s != 0.0) atomic_add(K + (size_t)(ob + j) * N + oc + k, s);
+                }
+            if constexpr (KEEP_KAD) {
+#pragma unroll
+                for (int x = 0; x < NA * ND; ++x) kad_get(x) += w * kad[x];
+            } else if (act) {
 #pragma unroll
                 for (int i = 0; i < NA; ++i)
 #pragma unroll
                     for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(oa + i) * N + od + l, w * kad[i * ND + l]);
             }
-#pragma unroll
-            for (int j = 0; j < NB; ++j)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(ob + j) * N + od + l, w * kbd[j * ND + l]);
         }
     }
     if (cur_a >= 0) flush_a();
