@@ -108,10 +108,13 @@ __global__ __launch_bounds__(kBlock) void k_digest_team(const TaskDev* __restric
     using TC = TeamClass<LA, LB, LC, LD>;
     constexpr int NA = TC::NA, NB = TC::NB, NC = TC::NC, ND = TC::ND;
     constexpr int NAB = NA * NB, NCD = NC * ND;
-    // per-team partial blocks: J_cd, K_ac, K_ad, K_bc, K_bd; per-wavefront partial J_ab
+    // per-team partial blocks: J_cd, K_ac, K_ad, K_bc, K_bd, J_ab (J_ab summed over the teams when flushed); the
+    // team stride is padded to 1 mod 32 doubles, so the same entry of different teams falls in different LDS banks
     constexpr int R_JCD = 0, R_KAC = NCD, R_KAD = R_KAC + NA * NC, R_KBC = R_KAD + NA * ND, R_KBD = R_KBC + NB * NC;
-    constexpr int R = R_KBD + NB * ND;
-    constexpr int WAVE_LDS = (kTeamsPerWave + 1) * R + NAB;
+    constexpr int R_JAB = R_KBD + NB * ND;
+    constexpr int R = R_JAB + NAB;
+    constexpr int RS = R + ((33 - R % 32) % 32);
+    constexpr int WAVE_LDS = (kTeamsPerWave + 1) * RS;
     __shared__ double lds[kBlock / kWave][WAVE_LDS];
 
     const long long item = wave_item();
@@ -144,8 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_digest_team(const TaskDev* __restric
     double* my = &lds[wid][0];
     for (int x = lane; x < WAVE_LDS; x += kWave) my[x] = 0.0;
     wave_lds_sync();
-    double* tm = my + team * R;
-    double* wj = my + (kTeamsPerWave + 1) * R;
+    double* tm = my + team * RS;
     // flush of the team's partial sums in [e0, e1) of its LDS block (each entry by one lane of the team), then zero
     auto flush = [&](int e0, int e1, int oa, int ob) {
         const int kl = opaque(kc);
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_digest_team(const TaskDev* __restric
 #pragma unroll
         for (int i = 0; i < NA; ++i)
 #pragma unroll
-            for (int j = 0; j < NB; ++j) atomic_add_lds(wj + pcA[i] * NB + pcB[j], jab[i * NB + j]);
+            for (int j = 0; j < NB; ++j) atomic_add_lds(tm + R_JAB + pcA[i] * NB + pcB[j], jab[i * NB + j]);
 #pragma unroll
         for (int k = 0; k < NC; ++k)
 #pragma unroll
@@ -276,11 +278,15 @@ __global__ __launch_bounds__(kBlock) void k_digest_team(const TaskDev* __restric
         wave_lds_sync();
         // J_ab by the wavefront and the K_bc / K_bd blocks of this bra pair by each team, then cleared
         if (lane < NAB) {
-            const double s = wj[lane];
-            wj[lane] = 0.0;
+            double s = 0.0;
+#pragma unroll
+            for (int t = 0; t < kTeamsPerWave; ++t) {
+                s += my[t * RS + R_JAB + lane];
+                my[t * RS + R_JAB + lane] = 0.0;
+            }
             if (s != 0.0) atomic_add(J + (size_t)(oa + lane / NB) * N + ob + lane % NB, 2.0 * s);
         }
-        flush(R_KBC, R, oa, ob);
+        flush(R_KBC, R_JAB, oa, ob);
         wave_lds_sync();
     }
     if (cur_a >= 0) flush(R_JCD, R_KBC, cur_a, 0);
