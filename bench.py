@@ -370,7 +370,7 @@ def bench_mixed(a):
         "dtype": "f32 recursions + f64 accumulation", "data": "synthetic",
         "config": {"workload": w.name + (": 150 atoms, N=1650, first s K=6, tau=1e-12" if a.workload == "mixed150"
                                          else ": 400 atoms, N=4400, K=3 on every shell, tau=1e-11"),
-                   "nbf": N, "tau": w.tau, "fp64_bound": 1e-5},
+                   "nbf": N, "tau": w.tau, "fp64_bound": uqc.default_opts().fp64_bound},
         "plan_ms": plan_ms,
         "fp64_build_ms": res["fp64"]["ms"], "mixed_build_ms": res["mixed"]["ms"],
         "mixed_speedup_vs_fp64": res["fp64"]["ms"] / res["mixed"]["ms"],

@@ -113,7 +113,9 @@ __device__ __forceinline__ void boys64(double T, double pref, const double* __re
 }
 
 // FP32 variant (mixed mode, T <= 30 only): Taylor order 5 around the same grid points (truncation < 1e-10
-// relative); the grid offset d is exact in FP32 because the grid spacing is a power of two.
+// relative); the grid offset d is exact in FP32 because the grid spacing is a power of two.  No step rounds the
+// same way for every argument (no library exp, no rounded reciprocal constant), so the FP32 errors of many small
+// integrals do not add up to a bias.
 template <int L>
 __device__ __forceinline__ void boys32(float T, const float* __restrict__ tab, float* F) {
     const int g = (int)(T * (float)kBoysGridPerUnit + 0.5f);
@@ -127,10 +129,22 @@ __device__ __forceinline__ void boys32(float T, const float* __restrict__ tab, f
     p = fmaf(p, d, r[0]);
     F[L] = p;
     if constexpr (L > 0) {
-        const float e = expf(-T);
+        // exp(-T) = exp(-T_g) exp(d), exp(d) to order 5 (truncation < 1e-10); the division by 2m+1 uses the
+        // reciprocal split into two floats, so that its rounding does not bias every result the same way
+        float x = fmaf(d, 1.0f / 120.0f, 1.0f / 24.0f);
+        x = fmaf(x, d, 1.0f / 6.0f);
+        x = fmaf(x, d, 0.5f);
+        x = fmaf(x, d, 1.0f);
+        x = fmaf(x, d, 1.0f);
+        const float e = tab[g * kBoysNm + kBoysExpCol] * x;
         const float t2 = T + T;
 #pragma unroll
-        for (int m = L - 1; m >= 0; --m) F[m] = fmaf(t2, F[m + 1], e) * (1.0f / (2 * m + 1));
+        for (int m = L - 1; m >= 0; --m) {
+            const float rh = (float)(1.0 / (2 * m + 1));
+            const float rl = (float)(1.0 / (2 * m + 1) - (double)rh);
+            const float y = fmaf(t2, F[m + 1], e);
+            F[m] = fmaf(y, rh, y * rl);
+        }
     }
 }
 
