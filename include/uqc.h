@@ -57,7 +57,7 @@ typedef struct {
     int precision;        /* uqc_precision.  UQC_MIXED: primitive recursions in FP32 with FP64 accumulation, except
                              quartets with Q_ab Q_cd > fp64_bound (whole quartet in FP64) and Boys arguments
                              T > 30 (Boys function evaluated in FP64); J, K, G, E2 always accumulated in FP64 */
-    double fp64_bound;    /* default 1e-6 */
+    double fp64_bound;    /* default 1e-8 */
     int timing;           /* 1: time every class launch with HIP events (reported in uqc_stats) */
 } uqc_fock_opts;
 
@@ -80,7 +80,7 @@ typedef struct {
     long long class_quartets[UQC_MAX_CLASS_STATS];
 } uqc_stats;
 
-/* Fills *o with: tau = 1e-12, precision = UQC_FP64, fp64_bound = 1e-6, timing = 0. */
+/* Fills *o with: tau = 1e-12, precision = UQC_FP64, fp64_bound = 1e-8, timing = 0. */
 void uqc_fock_opts_default(uqc_fock_opts* o);
 
 /* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t the library launches on (NULL: the

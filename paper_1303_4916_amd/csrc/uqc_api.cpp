@@ -27,7 +27,7 @@ void uqc_fock_opts_default(uqc_fock_opts* o) {
     if (!o) return;
     o->schwarz_tau = 1e-12;
     o->precision = UQC_FP64;
-    o->fp64_bound = 1e-6;
+    o->fp64_bound = 1e-8;
     o->timing = 0;
 }
 

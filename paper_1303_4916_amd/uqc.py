@@ -152,7 +152,7 @@ def _ip(a: np.ndarray):
     return a.ctypes.data_as(_I)
 
 
-def default_opts(tau: float = 1e-12, precision: int = FP64, fp64_bound: float = 1e-6, timing: bool = False):
+def default_opts(tau: float = 1e-12, precision: int = FP64, fp64_bound: float = 1e-8, timing: bool = False):
     o = FockOpts()
     load().uqc_fock_opts_default(ctypes.byref(o))
     o.schwarz_tau = float(tau)

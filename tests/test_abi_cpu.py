@@ -34,7 +34,7 @@ def test_library_has_gfx950_code_object():
 
 def test_default_options():
     o = uqc.default_opts()
-    assert o.schwarz_tau == 1e-12 and o.precision == uqc.FP64 and o.fp64_bound == 1e-6 and o.timing == 0
+    assert o.schwarz_tau == 1e-12 and o.precision == uqc.FP64 and o.fp64_bound == 1e-8 and o.timing == 0
 
 
 def test_null_arguments_rejected_before_device_use():
