@@ -168,7 +168,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--workload", default="medium", choices=["medium", "mixed150", "large400", "serve", "copy"],
+    ap.add_argument("--workload", default="medium",
+                    choices=["medium", "mixed150", "large400", "large400kd1", "serve", "copy"],
                     help="medium (default, the benchmark line); mixed150 / large400: mixed vs FP64 accuracy and "
                          "speed; serve: Poisson request stream through the continuous-batching server")
     ap.add_argument("--nreq", type=int, default=32, help="serve: requests taken from the 512-request stream")
@@ -194,7 +195,7 @@ def main():
         return bench_serve(a)
     if a.workload == "copy":
         return bench_copy(a)
-    if a.workload in ("mixed150", "large400"):
+    if a.workload in ("mixed150", "large400", "large400kd1"):
         return bench_mixed(a)
 
     import torch
@@ -326,7 +327,10 @@ def bench_mixed(a):
     from paper_1303_4916_amd import workloads as wl
     import oracle
 
-    w = wl.mixed150(ndens=1) if a.workload == "mixed150" else wl.large400(ndens=1)
+    if a.workload == "mixed150":
+        w = wl.mixed150(ndens=1)
+    else:
+        w = wl.large400(ndens=1, k_d=1 if a.workload == "large400kd1" else 3)
     ctx = uqc.Context(0)
     t = time.perf_counter()
     B = uqc.Basis(ctx, w.shells)
@@ -368,8 +372,10 @@ def bench_mixed(a):
         "n_gpus": 1, "steps": a.steps, "warmup": 0,
         "ms_per_step": res["mixed"]["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 recursions + f64 accumulation", "data": "synthetic",
-        "config": {"workload": w.name + (": 150 atoms, N=1650, first s K=6, tau=1e-12" if a.workload == "mixed150"
-                                         else ": 400 atoms, N=4400, K=3 on every shell, tau=1e-11"),
+        "config": {"workload": w.name + {"mixed150": ": 150 atoms, N=1650, first s K=6, tau=1e-12",
+                                         "large400": ": 400 atoms, N=4400, K=3 on every shell, tau=1e-11",
+                                         "large400kd1": ": 400 atoms, N=4400, K=3 on s and p, K=1 on d, "
+                                                        "tau=1e-11"}[a.workload],
                    "nbf": N, "tau": w.tau, "fp64_bound": uqc.default_opts().fp64_bound},
         "plan_ms": plan_ms,
         "fp64_build_ms": res["fp64"]["ms"], "mixed_build_ms": res["mixed"]["ms"],

@@ -41,7 +41,7 @@ typedef enum {
     UQC_OK = 0,
     UQC_PENDING = 1,            /* uqc_poll: request not finished yet */
     UQC_E_ARG = -1,             /* invalid argument (null pointer, index out of range, non-finite value, ...) */
-    UQC_E_UNSUPPORTED = -2,     /* l > 2 or contraction depth > 16 */
+    UQC_E_UNSUPPORTED = -2,     /* l > 2, contraction depth > 16, or more than 65535 basis functions */
     UQC_E_NOMEM = -3,           /* device allocation failed, or a request exceeds the whole HBM budget */
     UQC_E_DEVICE = -4,          /* a HIP runtime call failed */
     UQC_E_NOT_SYMMETRIC = -5,   /* max|D - D^T| > 1e-12 max|D| */

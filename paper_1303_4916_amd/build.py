@@ -32,7 +32,7 @@ PAIR = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 
 # classes whose quartet kernel is asked to fit two wavefronts per SIMD (a few bytes of spill buy twice the
 # occupancy); the others keep the compiler's register choice
-TWO_WAVES = {(2, 0, 1, 1)}
+TWO_WAVES = {(2, 0, 1, 1), (2, 1, 2, 1), (2, 2, 1, 1)}
 # classes that do not keep their K_ac sums in LDS (the slots would cost them a wavefront per SIMD)
 KAC_NOT_IN_LDS = {(2, 1, 1, 0)}
 

@@ -284,6 +284,9 @@ def gen_hrr(c, es, fs):
 PERMS = list(itertools.permutations(range(3)))
 TEAM_CLASSES = [(2, 1, 2, 1), (2, 2, 1, 1), (2, 2, 2, 0), (2, 2, 2, 1), (2, 2, 2, 2)]
 TEAM_SIZE = 6
+# classes whose lanes digest every output as soon as it is formed (all six partial blocks live at once) instead
+# of holding the outputs for three two-block passes: (dd|dd) has 224 outputs per lane, too many to hold
+TEAM_STREAM_DIGEST = {(2, 2, 2, 2)}
 
 
 def perm_q(t, p):
@@ -391,6 +394,7 @@ def gen_team(c):
     na, nb, nc, nd = ncart(la), ncart(lb), ncart(lc), ncart(ld)
     ia, ib, ic, idd = ({t: i for i, t in enumerate(x)} for x in (ca, cb, cc, cd))
     masks = []
+    stream = []   # the same outputs, each digested at once into all six partial blocks (streaming form)
     for o in out_reps:
         a, b, cx, d = o
         terms = []
@@ -417,17 +421,56 @@ def gen_team(c):
             if ip == min(coset):
                 mask |= 1 << ip
         masks.append(mask)
-        i, j, k, l = ia[a], ib[b], ic[cx], idd[d]
         wexpr = "w" if mask == (1 << TEAM_SIZE) - 1 else "(((%d >> pidx) & 1) ? w : 0.0)" % mask
-        hl.append("{ const double x = (%s) * %s;" % (expr, wexpr))
-        hl.append("  jab[%d] = fma(x, dcd[%d], jab[%d]); jcd[%d] = fma(x, dab[%d], jcd[%d]);"
-                  % (i * nb + j, k * nd + l, i * nb + j, k * nd + l, i * nb + j, k * nd + l))
-        hl.append("  kac[%d] = fma(x, dbd[%d], kac[%d]); kad[%d] = fma(x, dbc[%d], kad[%d]);"
-                  % (i * nc + k, j * nd + l, i * nc + k, i * nd + l, j * nc + k, i * nd + l))
-        hl.append("  kbc[%d] = fma(x, dad[%d], kbc[%d]); kbd[%d] = fma(x, dac[%d], kbd[%d]); }"
-                  % (j * nc + k, i * nd + l, j * nc + k, j * nd + l, i * nc + k, j * nd + l))
-    return {"vrr": vrr_lines, "nrep": len(reps), "reps": reps, "out_reps": out_reps, "hrr_digest": hl,
-            "masks": masks, "v": v, "hrr_flops": flops[0]}
+        hl.append("out[%d] = (%s) * %s;" % (len(masks) - 1, expr, wexpr))
+        i, j, k, l = ia[a], ib[b], ic[cx], idd[d]
+        stream.append("{ const double x = (%s) * %s;" % (expr, wexpr))
+        stream.append("  jab[%d] = fma(x, dcd[%d], jab[%d]); jcd[%d] = fma(x, dab[%d], jcd[%d]);"
+                      % (i * nb + j, k * nd + l, i * nb + j, k * nd + l, i * nb + j, k * nd + l))
+        stream.append("  kac[%d] = fma(x, dbd[%d], kac[%d]); kad[%d] = fma(x, dbc[%d], kad[%d]);"
+                      % (i * nc + k, j * nd + l, i * nc + k, i * nd + l, j * nc + k, i * nd + l))
+        stream.append("  kbc[%d] = fma(x, dad[%d], kbc[%d]); kbd[%d] = fma(x, dac[%d], kbd[%d]); }"
+                      % (j * nc + k, i * nd + l, j * nc + k, j * nd + l, i * nc + k, j * nd + l))
+    # Digest passes over the lane's weighted outputs, two partial blocks each (the same pairing as the 64-ket
+    # kernels): P = 0: x = out.D_cd -> J_ab, y = out.D_ab -> J_cd; P = 1: x = out.D_bd -> K_ac, y = out.D_ac -> K_bd;
+    # P = 2: x = out.D_bc -> K_ad, y = out.D_ad -> K_bc.  D slices and partials are in the lane's own frame; every
+    # partial is assigned at its first term (no zero fill) and untouched ones are set to zero.
+    digest = []
+    sizes = [(na * nb, nc * nd), (na * nc, nb * nd), (na * nd, nb * nc)]
+    for P in range(3):
+        lines = []
+        seen_x, seen_y = set(), set()
+        for n, o in enumerate(out_reps):
+            a, b, cx, d = o
+            i, j, k, l = ia[a], ib[b], ic[cx], idd[d]
+            xe, d1e, ye, d2e = [(i * nb + j, k * nd + l, k * nd + l, i * nb + j),
+                                (i * nc + k, j * nd + l, j * nd + l, i * nc + k),
+                                (i * nd + l, j * nc + k, j * nc + k, i * nd + l)][P]
+            for arr, e, darr, de, seen in (("x", xe, "d1", d1e, seen_x), ("y", ye, "d2", d2e, seen_y)):
+                if e in seen:
+                    lines.append("%s[%d] = fma(out[%d], %s[%d], %s[%d]);" % (arr, e, n, darr, de, arr, e))
+                else:
+                    lines.append("%s[%d] = out[%d] * %s[%d];" % (arr, e, n, darr, de))
+                    seen.add(e)
+        for e in range(sizes[P][0]):
+            if e not in seen_x:
+                lines.append("x[%d] = 0.0;" % e)
+        for e in range(sizes[P][1]):
+            if e not in seen_y:
+                lines.append("y[%d] = 0.0;" % e)
+        digest.append(lines)
+    # the streaming form shares the memoised intermediate lines of the horizontal recursion
+    hrr_stream = [x for x in hl if not x.startswith("out[")]
+    pos = 0
+    merged = []
+    for x in hl:
+        if x.startswith("out["):
+            merged += stream[4 * pos:4 * pos + 4]
+            pos += 1
+        else:
+            merged.append(x)
+    return {"vrr": vrr_lines, "nrep": len(reps), "reps": reps, "out_reps": out_reps, "hrr": hl,
+            "digest": digest, "hrr_digest": merged, "masks": masks, "v": v, "hrr_flops": flops[0]}
 
 
 def perm_comp_table():
@@ -581,17 +624,35 @@ def main(outdir):
         th.append("    (void)PAx; (void)PAy; (void)PAz; (void)WPx; (void)WPy; (void)WPz;")
         th.append("    (void)QCx; (void)QCy; (void)QCz; (void)WQx; (void)WQy; (void)WQz;")
         th.append("  }")
-        th.append("  __device__ static __forceinline__ void hrr_digest(const double* __restrict__ acc, "
+        th.append("  static constexpr int NOUT = %d;  // representative outputs held by a lane" % len(t["out_reps"]))
+        th.append("  static constexpr bool STREAM = %s;" % ("true" if c in TEAM_STREAM_DIGEST else "false"))
+        if c in TEAM_STREAM_DIGEST:
+            th.append("  __device__ static __forceinline__ void hrr_digest(const double* __restrict__ acc, "
+                      "const int* __restrict__ src, int pidx, double w, double ABx, double ABy, double ABz, "
+                      "double CDx, double CDy, double CDz, const double* __restrict__ dab, "
+                      "const double* __restrict__ dcd, const double* __restrict__ dbd, "
+                      "const double* __restrict__ dbc, const double* __restrict__ dad, "
+                      "const double* __restrict__ dac, double* __restrict__ jab, double* __restrict__ jcd, "
+                      "double* __restrict__ kac, double* __restrict__ kad, double* __restrict__ kbc, "
+                      "double* __restrict__ kbd) {")
+            for line in t["hrr_digest"]:
+                th.append("    " + line)
+            th.append("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz; (void)src; (void)pidx;")
+            th.append("  }")
+        th.append("  __device__ static __forceinline__ void hrr(const double* __restrict__ acc, "
                   "const int* __restrict__ src, int pidx, double w, double ABx, double ABy, double ABz, "
-                  "double CDx, double CDy, double CDz, const double* __restrict__ dab, "
-                  "const double* __restrict__ dcd, const double* __restrict__ dbd, const double* __restrict__ dbc, "
-                  "const double* __restrict__ dad, const double* __restrict__ dac, double* __restrict__ jab, "
-                  "double* __restrict__ jcd, double* __restrict__ kac, double* __restrict__ kad, "
-                  "double* __restrict__ kbc, double* __restrict__ kbd) {")
-        for line in t["hrr_digest"]:
+                  "double CDx, double CDy, double CDz, double* __restrict__ out) {")
+        for line in t["hrr"]:
             th.append("    " + line)
         th.append("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz; (void)src; (void)pidx;")
         th.append("  }")
+        for P in range(3):
+            th.append("  __device__ static __forceinline__ void digest%d(const double* __restrict__ out, "
+                      "const double* __restrict__ d1, const double* __restrict__ d2, double* __restrict__ x, "
+                      "double* __restrict__ y) {" % P)
+            for line in t["digest"][P]:
+                th.append("    " + line)
+            th.append("  }")
         th.append("};")
         th.append("")
     _write(os.path.join(outdir, "eri_team.h"), "\n".join(th) + "\n")

@@ -328,6 +328,10 @@ uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* n
         p += sh.K;
     }
     B->nbf = off;
+    if (off > kMaxNbf) {  // the kernels index N x N matrices with 32-bit offsets
+        delete B;
+        return uqc_fail(UQC_E_UNSUPPORTED, "uqc_basis_create: more than 65535 basis functions");
+    }
     B->fcomp.resize(B->nbf);
     for (int s = 0; s < nshell; ++s)
         for (int c = 0; c < ncart(B->shells[s].l); ++c)

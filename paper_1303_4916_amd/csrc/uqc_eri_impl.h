@@ -213,6 +213,8 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
     const int kc = ket_ok ? ket : Kt.np - 1;
     const double qk = Kt.Q[kc];
     const double* __restrict__ D = tk.D;
+    // D is read-only while the kernel runs: read through the constant address space with 32-bit offsets (N < 2^16)
+    const cdptr Dc = as_const(D);
     double* __restrict__ J = tk.J;
     double* __restrict__ K = tk.K;
     const int N = tk.nbf;
@@ -321,11 +323,11 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
 #pragma unroll
             for (int i = 0; i < NA; ++i)
 #pragma unroll
-                for (int j = 0; j < NB; ++j) dab[i * NB + j] = as_const(D)[(size_t)(oa + i) * N + ob + j];
+                for (int j = 0; j < NB; ++j) dab[i * NB + j] = Dc[(unsigned)(oa + i) * (unsigned)N + (unsigned)(ob + j)];
 #pragma unroll
             for (int k = 0; k < NC; ++k)
 #pragma unroll
-                for (int l = 0; l < ND; ++l) dcd[k * ND + l] = D[(size_t)(oc + k) * N + od + l];
+                for (int l = 0; l < ND; ++l) dcd[k * ND + l] = Dc[(unsigned)(oc + k) * (unsigned)N + (unsigned)(od + l)];
             contract_pair<NA, NB, NC, ND, 0>(out, dcd, dab, jab, jcd);
 #pragma unroll
             for (int x = 0; x < NAB; ++x) {
@@ -342,11 +344,11 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
 #pragma unroll
             for (int j = 0; j < NB; ++j)
 #pragma unroll
-                for (int l = 0; l < ND; ++l) dbd[j * ND + l] = D[(size_t)(ob + j) * N + od + l];
+                for (int l = 0; l < ND; ++l) dbd[j * ND + l] = Dc[(unsigned)(ob + j) * (unsigned)N + (unsigned)(od + l)];
 #pragma unroll
             for (int i = 0; i < NA; ++i)
 #pragma unroll
-                for (int k = 0; k < NC; ++k) dac[i * NC + k] = D[(size_t)(oa + i) * N + oc + k];
+                for (int k = 0; k < NC; ++k) dac[i * NC + k] = Dc[(unsigned)(oa + i) * (unsigned)N + (unsigned)(oc + k)];
             contract_pair<NA, NB, NC, ND, 1>(out, dbd, dac, kac, kbd);
             if constexpr (KEEP_KAC) {
 #pragma unroll
@@ -372,11 +374,11 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
 #pragma unroll
             for (int j = 0; j < NB; ++j)
 #pragma unroll
-                for (int k = 0; k < NC; ++k) dbc[j * NC + k] = D[(size_t)(ob + j) * N + oc + k];
+                for (int k = 0; k < NC; ++k) dbc[j * NC + k] = Dc[(unsigned)(ob + j) * (unsigned)N + (unsigned)(oc + k)];
 #pragma unroll
             for (int i = 0; i < NA; ++i)
 #pragma unroll
-                for (int l = 0; l < ND; ++l) dad[i * ND + l] = D[(size_t)(oa + i) * N + od + l];
+                for (int l = 0; l < ND; ++l) dad[i * ND + l] = Dc[(unsigned)(oa + i) * (unsigned)N + (unsigned)(od + l)];
             contract_pair<NA, NB, NC, ND, 2>(out, dbc, dad, kad, kbc);
 #pragma unroll
             for (int j = 0; j < NB; ++j)

@@ -100,8 +100,86 @@ __device__ __forceinline__ void team_accumulate(const BinDev& B, int bra, const 
     }
 }
 
+// Streaming digest of one lane (classes with too many outputs to hold): all six density slices gathered in the
+// lane's frame, every output digested into the six partial blocks as it is formed, then the blocks added into the
+// team's LDS block at the true component indices.
+template <class TC, int LA, int LB, int LC, int LD>
+__device__ __forceinline__ void team_digest_stream(const double* acc, const int* src, int pidx, double w, cdptr bh,
+                                                   const BinDev& Kt, int kl, int q0, int q1, int q2, cdptr Dc, int N,
+                                                   int oa, int ob, int oc, int od, const int* pcA, const int* pcB,
+                                                   const int* pcC, const int* pcD, double* t_jab, double* t_jcd,
+                                                   double* t_kac, double* t_kad, double* t_kbc, double* t_kbd) {
+    constexpr int NA = TC::NA, NB = TC::NB, NC = TC::NC, ND = TC::ND;
+    auto Dp = [&](int r, int c) { return Dc[(unsigned)r * (unsigned)N + (unsigned)c]; };
+    double dab[NA * NB], dcd[NC * ND], dbd[NB * ND], dbc[NB * NC], dad[NA * ND], dac[NA * NC];
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) dab[i * NB + j] = Dp(oa + pcA[i], ob + pcB[j]);
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+        for (int l = 0; l < ND; ++l) dcd[k * ND + l] = Dp(oc + pcC[k], od + pcD[l]);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+#pragma unroll
+        for (int l = 0; l < ND; ++l) dbd[j * ND + l] = Dp(ob + pcB[j], od + pcD[l]);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) dbc[j * NC + k] = Dp(ob + pcB[j], oc + pcC[k]);
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+#pragma unroll
+        for (int l = 0; l < ND; ++l) dad[i * ND + l] = Dp(oa + pcA[i], od + pcD[l]);
+#pragma unroll
+        for (int k = 0; k < NC; ++k) dac[i * NC + k] = Dp(oa + pcA[i], oc + pcC[k]);
+    }
+    double jab[NA * NB], jcd[NC * ND], kac[NA * NC], kad[NA * ND], kbc[NB * NC], kbd[NB * ND];
+#pragma unroll
+    for (int x = 0; x < NA * NB; ++x) jab[x] = 0.0;
+#pragma unroll
+    for (int x = 0; x < NC * ND; ++x) jcd[x] = 0.0;
+#pragma unroll
+    for (int x = 0; x < NA * NC; ++x) kac[x] = 0.0;
+#pragma unroll
+    for (int x = 0; x < NA * ND; ++x) kad[x] = 0.0;
+#pragma unroll
+    for (int x = 0; x < NB * NC; ++x) kbc[x] = 0.0;
+#pragma unroll
+    for (int x = 0; x < NB * ND; ++x) kbd[x] = 0.0;
+    const double ABx = sel3(bh[0], bh[1], bh[2], q0), ABy = sel3(bh[0], bh[1], bh[2], q1);
+    const double ABz = sel3(bh[0], bh[1], bh[2], q2);
+    const double CDx = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q0);
+    const double CDy = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q1);
+    const double CDz = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q2);
+    TC::hrr_digest(acc, src, pidx, w, ABx, ABy, ABz, CDx, CDy, CDz, dab, dcd, dbd, dbc, dad, dac, jab, jcd, kac, kad,
+                   kbc, kbd);
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) atomic_add_lds(t_jab + pcA[i] * NB + pcB[j], jab[i * NB + j]);
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+        for (int l = 0; l < ND; ++l) atomic_add_lds(t_jcd + pcC[k] * ND + pcD[l], jcd[k * ND + l]);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) atomic_add_lds(t_kac + pcA[i] * NC + pcC[k], kac[i * NC + k]);
+#pragma unroll
+        for (int l = 0; l < ND; ++l) atomic_add_lds(t_kad + pcA[i] * ND + pcD[l], kad[i * ND + l]);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) atomic_add_lds(t_kbc + pcB[j] * NC + pcC[k], kbc[j * NC + k]);
+#pragma unroll
+        for (int l = 0; l < ND; ++l) atomic_add_lds(t_kbd + pcB[j] * ND + pcD[l], kbd[j * ND + l]);
+    }
+}
+
 template <int LA, int LB, int LC, int LD, bool MIXED>
-__global__ __launch_bounds__(kBlock) void k_digest_team(const TaskDev* __restrict__ tasks,
+__global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const TaskDev* __restrict__ tasks,
                                                         const long long* __restrict__ task_begin, int ntask,
                                                         long long nitems, const double* __restrict__ boys64tab,
                                                         const float* __restrict__ boys32tab) {
@@ -133,6 +211,8 @@ __global__ __launch_bounds__(kBlock) void k_digest_team(const TaskDev* __restric
     const int kc = ket_ok ? ket : Kt.np - 1;  // idle teams compute a valid quartet with weight 0
     const double qk = Kt.Q[kc];
     const double* __restrict__ D = tk.D;
+    // D is read-only while the kernel runs: read through the constant address space with 32-bit offsets (N < 2^16)
+    const cdptr Dc = as_const(D);
     double* __restrict__ J = tk.J;
     double* __restrict__ K = tk.K;
     const int N = tk.nbf;
@@ -205,75 +285,86 @@ __global__ __launch_bounds__(kBlock) void k_digest_team(const TaskDev* __restric
 #pragma unroll
         for (int k = 0; k < ND; ++k) pcD[k] = kPermComp[LD][pidx][k];
         const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
-        double dab[NAB], dcd[NCD], dbd[NB * ND], dbc[NB * NC], dad[NA * ND], dac[NA * NC];
-#pragma unroll
-        for (int i = 0; i < NA; ++i)
-#pragma unroll
-            for (int j = 0; j < NB; ++j) dab[i * NB + j] = D[(size_t)(oa + pcA[i]) * N + ob + pcB[j]];
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-#pragma unroll
-            for (int l = 0; l < ND; ++l) dcd[k * ND + l] = D[(size_t)(oc + pcC[k]) * N + od + pcD[l]];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-#pragma unroll
-            for (int l = 0; l < ND; ++l) dbd[j * ND + l] = D[(size_t)(ob + pcB[j]) * N + od + pcD[l]];
-#pragma unroll
-            for (int k = 0; k < NC; ++k) dbc[j * NC + k] = D[(size_t)(ob + pcB[j]) * N + oc + pcC[k]];
-        }
-#pragma unroll
-        for (int i = 0; i < NA; ++i) {
-#pragma unroll
-            for (int l = 0; l < ND; ++l) dad[i * ND + l] = D[(size_t)(oa + pcA[i]) * N + od + pcD[l]];
-#pragma unroll
-            for (int k = 0; k < NC; ++k) dac[i * NC + k] = D[(size_t)(oa + pcA[i]) * N + oc + pcC[k]];
-        }
         double w = act ? bh[3] * Kt.sdeg[kl] : 0.0;
         if (tk.same && ket == bra) w *= 0.5;
-        double jab[NAB], jcd[NCD], kac[NA * NC], kad[NA * ND], kbc[NB * NC], kbd[NB * ND];
-#pragma unroll
-        for (int x = 0; x < NAB; ++x) jab[x] = 0.0;
-#pragma unroll
-        for (int x = 0; x < NCD; ++x) jcd[x] = 0.0;
-#pragma unroll
-        for (int x = 0; x < NA * NC; ++x) kac[x] = 0.0;
-#pragma unroll
-        for (int x = 0; x < NA * ND; ++x) kad[x] = 0.0;
-#pragma unroll
-        for (int x = 0; x < NB * NC; ++x) kbc[x] = 0.0;
-#pragma unroll
-        for (int x = 0; x < NB * ND; ++x) kbd[x] = 0.0;
-        const double ABx = sel3(bh[0], bh[1], bh[2], q0);
-        const double ABy = sel3(bh[0], bh[1], bh[2], q1);
-        const double ABz = sel3(bh[0], bh[1], bh[2], q2);
-        const double CDx = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q0);
-        const double CDy = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q1);
-        const double CDz = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q2);
-        TC::hrr_digest(acc, src, pidx, w, ABx, ABy, ABz, CDx, CDy, CDz, dab, dcd, dbd, dbc, dad, dac, jab, jcd, kac,
-                       kad, kbc, kbd);
-
-        // team and wavefront sums at the true component indices
-#pragma unroll
-        for (int i = 0; i < NA; ++i)
-#pragma unroll
-            for (int j = 0; j < NB; ++j) atomic_add_lds(tm + R_JAB + pcA[i] * NB + pcB[j], jab[i * NB + j]);
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-#pragma unroll
-            for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_JCD + pcC[k] * ND + pcD[l], jcd[k * ND + l]);
-#pragma unroll
-        for (int i = 0; i < NA; ++i) {
-#pragma unroll
-            for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KAC + pcA[i] * NC + pcC[k], kac[i * NC + k]);
-#pragma unroll
-            for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KAD + pcA[i] * ND + pcD[l], kad[i * ND + l]);
+        if constexpr (TC::STREAM) {
+            team_digest_stream<TC, LA, LB, LC, LD>(acc, src, pidx, w, bh, Kt, kl, q0, q1, q2, Dc, N, oa, ob, oc, od,
+                                                   pcA, pcB, pcC, pcD, tm + R_JAB, tm + R_JCD, tm + R_KAC,
+                                                   tm + R_KAD, tm + R_KBC, tm + R_KBD);
+        } else {
+        double out[TC::NOUT];
+        {
+            const double ABx = sel3(bh[0], bh[1], bh[2], q0);
+            const double ABy = sel3(bh[0], bh[1], bh[2], q1);
+            const double ABz = sel3(bh[0], bh[1], bh[2], q2);
+            const double CDx = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q0);
+            const double CDy = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q1);
+            const double CDz = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q2);
+            TC::hrr(acc, src, pidx, w, ABx, ABy, ABz, CDx, CDy, CDz, out);
         }
+        // Digest in three passes (J_ab with J_cd; K_ac with K_bd; K_ad with K_bc), each gathering its two density
+        // slices in the lane's frame and adding its two partial blocks into LDS at the true component indices.
+        auto Dp = [&](int r, int c) { return Dc[(unsigned)r * (unsigned)N + (unsigned)c]; };
+        {
+            double d1[NCD], d2[NAB], x[NAB], y[NCD];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
+            for (int k = 0; k < NC; ++k)
 #pragma unroll
-            for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KBC + pcB[j] * NC + pcC[k], kbc[j * NC + k]);
+                for (int l = 0; l < ND; ++l) d1[k * ND + l] = Dp(oc + pcC[k], od + pcD[l]);
 #pragma unroll
-            for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KBD + pcB[j] * ND + pcD[l], kbd[j * ND + l]);
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) d2[i * NB + j] = Dp(oa + pcA[i], ob + pcB[j]);
+            TC::digest0(out, d1, d2, x, y);
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) atomic_add_lds(tm + R_JAB + pcA[i] * NB + pcB[j], x[i * NB + j]);
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+#pragma unroll
+                for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_JCD + pcC[k] * ND + pcD[l], y[k * ND + l]);
+        }
+        {
+            double d1[NB * ND], d2[NA * NC], x[NA * NC], y[NB * ND];
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int l = 0; l < ND; ++l) d1[j * ND + l] = Dp(ob + pcB[j], od + pcD[l]);
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) d2[i * NC + k] = Dp(oa + pcA[i], oc + pcC[k]);
+            TC::digest1(out, d1, d2, x, y);
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KAC + pcA[i] * NC + pcC[k], x[i * NC + k]);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KBD + pcB[j] * ND + pcD[l], y[j * ND + l]);
+        }
+        {
+            double d1[NB * NC], d2[NA * ND], x[NA * ND], y[NB * NC];
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) d1[j * NC + k] = Dp(ob + pcB[j], oc + pcC[k]);
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int l = 0; l < ND; ++l) d2[i * ND + l] = Dp(oa + pcA[i], od + pcD[l]);
+            TC::digest2(out, d1, d2, x, y);
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KAD + pcA[i] * ND + pcD[l], x[i * ND + l]);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KBC + pcB[j] * NC + pcC[k], y[j * NC + k]);
+        }
         }
         wave_lds_sync();
         // J_ab by the wavefront and the K_bc / K_bd blocks of this bra pair by each team, then cleared

@@ -8,6 +8,7 @@ namespace uqc {
 constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kBlock = 256;            // threads per block of the quartet kernels (4 wavefronts)
 constexpr int kMaxK = 16;              // maximum contraction depth
+constexpr int kMaxNbf = 65535;         // maximum basis size (N x N matrices indexed with 32-bit offsets)
 constexpr int kBoysGridPerUnit = 8;    // Boys Taylor grid: T_g = g / 8 (exact in binary, same points in FP32/FP64)
 constexpr int kBoysTmax = 60;          // grid covers [0, 60); asymptotic form beyond
 constexpr int kBoysNg = kBoysTmax * kBoysGridPerUnit + 1;

@@ -107,43 +107,51 @@ def test_team_emulation_matches_oracle(c):
         env["src"] = comp_tab[ip]
         env["pidx"] = ip
         env["w"] = 1.0
-        env["fetch"] = None
-        rec = []
-        code = []
-        for line in t["hrr_digest"]:
-            m = re.match(r"\{ const double x = (.*);$", line)
-            if m:
-                code.append("_rec.append(%s)" % m.group(1))
-            elif line.startswith("  "):
-                continue
-            else:
-                line = re.sub(r"^const double ", "", line).rstrip(";")
-                line = re.sub(r"fetch\(acc\[(\d+)\], src\[(\d+)\]\)", r"_acc[src[\2]][\1]", line)
-                code.append(line)
-        env["_rec"] = rec
         env["_acc"] = accs
-        code = "\n".join(code).replace("? w : 0.0", "and w or 0.0").replace("(((", "((").replace(") & 1) and", ") & 1 and")
-        code = re.sub(r"\(\(\((\d+) >> pidx\) & 1\) \? w : 0\.0\)", r"(w if ((\1 >> pidx) & 1) else 0.0)", code)
-        exec(code, env)
-        assert len(rec) == len(t["out_reps"])
-        # map representative outputs to true components; owned ones only
+        env["out"] = np.zeros(len(t["out_reps"]))
+        code = []
+        for line in t["hrr"]:
+            line = re.sub(r"^const double ", "", line).rstrip(";")
+            line = re.sub(r"fetch\(acc\[(\d+)\], src\[(\d+)\]\)", r"_acc[src[\2]][\1]", line)
+            line = re.sub(r"\(\(\((\d+) >> pidx\) & 1\) \? w : 0\.0\)", r"(w if ((\1 >> pidx) & 1) else 0.0)", line)
+            code.append(line)
+        exec("\n".join(code), env)
+        rec = env["out"]
+        # map representative outputs to true components; owned ones only (a zero weight marks the others)
         pcs = [pc_tab[l][ip] for l in c]
         for n, (o, mask) in enumerate(zip(t["out_reps"], t["masks"])):
             if not (mask >> ip) & 1:
+                assert rec[n] == 0.0
                 continue
             idx = tuple(gen.comps(c[s]).index(gen.perm_q(o[s], p)) for s in range(4))
             covered[idx] += 1
             got[idx] = rec[n]
-            # digest in the lane's frame, added at true indices (mirrors the device reduction)
-            i, j, k, l = (gen.comps(c[s]).index(o[s]) for s in range(4))
-            I, Jx, K, Lx = (pcs[s][x] for s, x in zip(range(4), (i, j, k, l)))
-            x = rec[n]
-            true_dig["jab"][I * nb + Jx] += x * Dm[off[2] + K, off[3] + Lx]
-            true_dig["jcd"][K * nd + Lx] += x * Dm[off[0] + I, off[1] + Jx]
-            true_dig["kac"][I * nc + K] += x * Dm[off[1] + Jx, off[3] + Lx]
-            true_dig["kad"][I * nd + Lx] += x * Dm[off[1] + Jx, off[2] + K]
-            true_dig["kbc"][Jx * nc + K] += x * Dm[off[0] + I, off[3] + Lx]
-            true_dig["kbd"][Jx * nd + Lx] += x * Dm[off[0] + I, off[2] + K]
+        # the generated digest passes, in the lane's frame, with densities gathered at permuted indices; their
+        # partial blocks are added at the true indices (as the device does into LDS)
+        D1 = lambda r, cc: Dm[r, cc]
+        Pa, Pb, Pc, Pd = (lambda x: off[0] + pcs[0][x]), (lambda x: off[1] + pcs[1][x]), \
+            (lambda x: off[2] + pcs[2][x]), (lambda x: off[3] + pcs[3][x])
+        slices = [
+            (np.array([D1(Pc(k), Pd(l)) for k in range(nc) for l in range(nd)]),
+             np.array([D1(Pa(i), Pb(j)) for i in range(na) for j in range(nb)]),
+             ("jab", na, nb, 0, 1), ("jcd", nc, nd, 2, 3)),
+            (np.array([D1(Pb(j), Pd(l)) for j in range(nb) for l in range(nd)]),
+             np.array([D1(Pa(i), Pc(k)) for i in range(na) for k in range(nc)]),
+             ("kac", na, nc, 0, 2), ("kbd", nb, nd, 1, 3)),
+            (np.array([D1(Pb(j), Pc(k)) for j in range(nb) for k in range(nc)]),
+             np.array([D1(Pa(i), Pd(l)) for i in range(na) for l in range(nd)]),
+             ("kad", na, nd, 0, 3), ("kbc", nb, nc, 1, 2)),
+        ]
+        for P, (d1, d2, xs, ys) in enumerate(slices):
+            penv = {"fma": _fma, "out": rec, "d1": d1, "d2": d2, "x": np.full(xs[1] * xs[2], np.nan),
+                    "y": np.full(ys[1] * ys[2], np.nan)}
+            exec("\n".join(x.rstrip(";") for x in t["digest"][P]), penv)
+            assert not np.any(np.isnan(penv["x"])) and not np.any(np.isnan(penv["y"]))
+            for arr, (name, n1, n2, s1, s2) in ((penv["x"], xs), (penv["y"], ys)):
+                for u in range(n1):
+                    for v_ in range(n2):
+                        tu, tv = pcs[s1][u], pcs[s2][v_]
+                        true_dig[name][tu * n2 + tv] += arr[u * n2 + v_]
     assert np.all(covered == 1)
     assert np.max(np.abs(got - raw_ref)) <= 1e-12 * np.max(np.abs(raw_ref))
     # reference digest of the full true block
