@@ -55,18 +55,19 @@ __device__ __forceinline__ double rsqrt64(double x) {
 // The two halves of boys64: the table row for T (grid index clamped, so the row can be fetched ahead of the test
 // on T), then the evaluation from that row.
 template <int L>
-__device__ __forceinline__ void boys64_row(double T, const double* __restrict__ tab, double2* r) {
-    const double gd = fmin(T * (double)kBoysGridPerUnit + 0.5, (double)(kBoysNg - 1));
-    const int g = (int)gd;
-    const double2* row = reinterpret_cast<const double2*>(tab + ((size_t)L * kBoysNg + g) * kBoysRow);
+__device__ __forceinline__ int boys64_row(double T, const double* __restrict__ tab, double2* r) {
+    const int g = (int)fmin(T * (double)kBoysGridPerUnit + 0.5, (double)(kBoysNg - 1));
+    // uniform slice base + 32-bit byte offset of the row
+    const char* slice = reinterpret_cast<const char*>(tab + (size_t)L * kBoysNg * kBoysRow);
+    const double2* row = reinterpret_cast<const double2*>(slice + (unsigned)g * (unsigned)(kBoysRow * sizeof(double)));
 #pragma unroll
     for (int x = 0; x < kBoysRow / 2; ++x) r[x] = row[x];
+    return g;
 }
 
 template <int L>
-__device__ __forceinline__ void boys64_eval(double T, double pref, const double2* r, double* F) {
+__device__ __forceinline__ void boys64_eval(double T, int g, double pref, const double2* r, double* F) {
     if (T < (double)kBoysTmax) {
-        const int g = (int)(T * (double)kBoysGridPerUnit + 0.5);
         const double d = (double)g * (1.0 / kBoysGridPerUnit) - T;  // exact grid point
         double p = r[4].x;
         p = fma(p, d, r[3].y);
@@ -108,8 +109,8 @@ __device__ __forceinline__ void boys64_eval(double T, double pref, const double2
 template <int L>
 __device__ __forceinline__ void boys64(double T, double pref, const double* __restrict__ tab, double* F) {
     double2 r[kBoysRow / 2];
-    boys64_row<L>(T, tab, r);
-    boys64_eval<L>(T, pref, r, F);
+    const int g = boys64_row<L>(T, tab, r);
+    boys64_eval<L>(T, g, pref, r, F);
 }
 
 // FP32 variant (mixed mode, T <= 30 only): Taylor order 5 around the same grid points (truncation < 1e-10

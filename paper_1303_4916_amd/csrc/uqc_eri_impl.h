@@ -28,10 +28,71 @@ struct EriClass;
 // ------------------------------------------------------------------------------------- contracted quartet core
 // Sums the primitive quartets of (bra pair `bra` of bin B | ket pair `ket` of bin Kt) into the contracted
 // [e0|f0] accumulators of class C.
+// FP64 path: one loop over the primitive quartets (ket primitive outer, bra primitive inner).  The bra records are
+// wavefront-uniform scalar loads; the next one is requested before the current quartet is evaluated, which costs
+// scalar registers only.  Ket fields are read through 32-bit offsets from the bin's base.
+template <class C>
+__device__ __forceinline__ void accumulate64(const BinDev& B, int bra, const BinDev& Kt, int ket,
+                                             const double* __restrict__ boys64tab, double* __restrict__ acc) {
+    const unsigned npk = (unsigned)Kt.np, fsk = (unsigned)Kt.K * npk;
+    const cdptr kbase = as_const(Kt.prim);
+    const cdptr brec = as_const(B.rec) + (size_t)bra * B.K * kRec;  // wavefront-uniform: scalar loads
+    const int KB = B.K, NPQ = B.K * Kt.K;
+    double eta = 0, Qx = 0, Qy = 0, Qz = 0, QCx = 0, QCy = 0, QCz = 0, prefk = 0, o2e = 0;
+    double b[kNumFields];
+#pragma unroll
+    for (int f = 0; f < kNumFields; ++f) b[f] = brec[f];
+    int kb = 0, kk = 0;
+    for (int p = 0; p < NPQ; ++p) {
+        if (kb == 0) {  // wavefront-uniform: next ket primitive
+            const unsigned o = (unsigned)kk * npk + (unsigned)ket;
+            eta = kbase[o + F_Z * fsk];
+            Qx = kbase[o + F_PX * fsk];
+            Qy = kbase[o + F_PY * fsk];
+            Qz = kbase[o + F_PZ * fsk];
+            QCx = kbase[o + F_PAX * fsk];
+            QCy = kbase[o + F_PAY * fsk];
+            QCz = kbase[o + F_PAZ * fsk];
+            prefk = kbase[o + F_PREF * fsk];
+            o2e = kbase[o + F_O2Z * fsk];
+        }
+        const int kbn = kb + 1 == KB ? 0 : kb + 1;
+        double bn[kNumFields];
+        const cdptr bp = brec + kbn * kRec;
+#pragma unroll
+        for (int f = 0; f < kNumFields; ++f) bn[f] = bp[f];
+        const double zeta = b[F_Z];
+        const double ze = zeta + eta;
+        const double rz = rsqrt64(ze);
+        const double inv = rz * rz;
+        const double PQx = b[F_PX] - Qx, PQy = b[F_PY] - Qy, PQz = b[F_PZ] - Qz;
+        const double roz = eta * inv, roe = zeta * inv;
+        const double T = zeta * roz * (PQx * PQx + PQy * PQy + PQz * PQz);
+        const double pref = b[F_PREF] * prefk * rz;
+        PrimGeom<double> g;
+        g.PA[0] = b[F_PAX]; g.PA[1] = b[F_PAY]; g.PA[2] = b[F_PAZ];
+        g.WP[0] = -roz * PQx; g.WP[1] = -roz * PQy; g.WP[2] = -roz * PQz;
+        g.QC[0] = QCx; g.QC[1] = QCy; g.QC[2] = QCz;
+        g.WQ[0] = roe * PQx; g.WQ[1] = roe * PQy; g.WQ[2] = roe * PQz;
+        g.o2z = b[F_O2Z]; g.roz = roz; g.o2e = o2e; g.roe = roe; g.o2ze = 0.5 * inv;
+        double F[C::L + 1];
+        boys64<C::L>(T, pref, boys64tab, F);
+        C::template vrr<double>(F, g, acc);
+#pragma unroll
+        for (int f = 0; f < kNumFields; ++f) b[f] = bn[f];
+        kb = kbn;
+        if (kb == 0) ++kk;
+    }
+}
+
 template <class C, bool MIXED>
 __device__ __forceinline__ void accumulate(const BinDev& B, int bra, const BinDev& Kt, int ket,
                                            const double* __restrict__ boys64tab, const float* __restrict__ boys32tab,
                                            double* __restrict__ acc) {
+    if constexpr (!MIXED) {
+        accumulate64<C>(B, bra, Kt, ket, boys64tab, acc);
+        return;
+    }
     const size_t npk = (size_t)Kt.np;
     const size_t fsk = (size_t)Kt.K * npk;
     const cdptr brec = as_const(B.rec) + (size_t)bra * B.K * kRec;  // wavefront-uniform: scalar loads
