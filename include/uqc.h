@@ -51,6 +51,11 @@ typedef enum {
 
 typedef enum { UQC_FP64 = 0, UQC_MIXED = 1 } uqc_precision;
 
+/* Progress report of a Fock build: called on the calling thread after every class sub-launch has completed on the
+ * device (items_done of items_total work items of class class_id, encoded as in uqc_stats.class_id).  Setting it
+ * makes the build wait for each sub-launch; the work itself is unchanged. */
+typedef void (*uqc_progress_fn)(void* user, int class_id, long long items_done, long long items_total);
+
 /* Options of a Fock build.  Call uqc_fock_opts_default() first. */
 typedef struct {
     double schwarz_tau;   /* screening threshold tau (>= 0) */
@@ -59,6 +64,11 @@ typedef struct {
                              T > 30 (Boys function evaluated in FP64); J, K, G, E2 always accumulated in FP64 */
     double fp64_bound;    /* default 1e-8 */
     int timing;           /* 1: time every class launch with HIP events (reported in uqc_stats) */
+    uqc_progress_fn progress;   /* NULL (default) or a progress report, see uqc_progress_fn */
+    void* progress_user;        /* passed to progress */
+    long long max_items_per_launch;  /* > 0: cap on the work items of one class-kernel launch (longer classes are
+                                        split into several launches, which bounds the duration of each kernel);
+                                        0 (default): 2^20 */
 } uqc_fock_opts;
 
 #define UQC_MAX_CLASS_STATS 96
@@ -80,7 +90,8 @@ typedef struct {
     long long class_quartets[UQC_MAX_CLASS_STATS];
 } uqc_stats;
 
-/* Fills *o with: tau = 1e-12, precision = UQC_FP64, fp64_bound = 1e-8, timing = 0. */
+/* Fills *o with: tau = 1e-12, precision = UQC_FP64, fp64_bound = 1e-8, timing = 0, progress = NULL,
+ * max_items_per_launch = 0. */
 void uqc_fock_opts_default(uqc_fock_opts* o);
 
 /* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t the library launches on (NULL: the
@@ -153,7 +164,7 @@ typedef struct {
     int ncol;                   /* columns of R_t (>= 1) */
     double eps;                 /* perturbation weight in [0, 1] */
     unsigned long long seed;
-    uqc_fock_opts opts;
+    uqc_fock_opts opts;         /* its progress callback is not used by the server */
     double arrival_ms;          /* arrival time stamp on the caller's clock (reported back; informational) */
 } uqc_request;
 

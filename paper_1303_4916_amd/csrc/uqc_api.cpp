@@ -29,6 +29,9 @@ void uqc_fock_opts_default(uqc_fock_opts* o) {
     o->precision = UQC_FP64;
     o->fp64_bound = 1e-8;
     o->timing = 0;
+    o->progress = nullptr;
+    o->progress_user = nullptr;
+    o->max_items_per_launch = 0;
 }
 
 // ---------------------------------------------------------------------------------------------- Boys table
@@ -464,17 +467,42 @@ uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* n
         (void)hipFree(tmp);
         if (st != UQC_OK) { delete B; return st; }
     }
-    // sort each bin by bound (descending) and re-upload; record where every shell pair landed
+    // Morton code of every shell centre (10 bits per axis over the bounding box): pairs that differ only in their
+    // second shell are ordered along this curve, so neighbouring lanes hold nearby pairs
+    std::vector<uint32_t> morton(nshell);
+    {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int s = 0; s < nshell; ++s)
+            for (int x = 0; x < 3; ++x) {
+                lo[x] = std::min(lo[x], B->shells[s].A[x]);
+                hi[x] = std::max(hi[x], B->shells[s].A[x]);
+            }
+        for (int s = 0; s < nshell; ++s) {
+            uint32_t q[3];
+            for (int x = 0; x < 3; ++x) {
+                const double span = hi[x] > lo[x] ? hi[x] - lo[x] : 1.0;
+                q[x] = (uint32_t)std::min(1023.0, std::floor((B->shells[s].A[x] - lo[x]) / span * 1024.0));
+            }
+            uint32_t m = 0;
+            for (int bit = 0; bit < 10; ++bit)
+                for (int x = 0; x < 3; ++x) m |= ((q[x] >> bit) & 1u) << (3 * bit + x);
+            morton[s] = m;
+        }
+    }
+    // sort each bin and re-upload; record where every shell pair landed
     B->Qfull.assign((size_t)nshell * nshell, 0.0);
     for (size_t bi = 0; bi < B->bins.size(); ++bi) {
         Bin& bn = B->bins[bi];
         std::vector<int> perm(bn.np);
         std::iota(perm.begin(), perm.end(), 0);
-        // decade of the bound (descending), then first shell, then bound (descending)
+        // decade of the bound (descending), then first shell, then the second shell along the space-filling curve
+        // (then bound, descending)
         std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) {
             const int dx = decade(bn.Q[x]), dy = decade(bn.Q[y]);
             if (dx != dy) return dx > dy;
             if (bn.off_a[x] != bn.off_a[y]) return bn.off_a[x] < bn.off_a[y];
+            const uint32_t mx = morton[bn.sb[x]], my = morton[bn.sb[y]];
+            if (mx != my) return mx < my;
             return bn.Q[x] > bn.Q[y];
         });
         permute_bin(bn, perm);
@@ -924,6 +952,8 @@ uqc_status uqc_fock_build(uqc_basis* B, const double* D, double* J, double* K, d
     if (o.precision != UQC_FP64 && o.precision != UQC_MIXED)
         return uqc_fail(UQC_E_ARG, "uqc_fock_build: bad precision");
     if (o.precision == UQC_MIXED && !(o.fp64_bound >= 0)) return uqc_fail(UQC_E_ARG, "uqc_fock_build: bad fp64_bound");
+    if (o.max_items_per_launch < 0) return uqc_fail(UQC_E_ARG, "uqc_fock_build: negative max_items_per_launch");
+    const long long max_items = o.max_items_per_launch > 0 ? o.max_items_per_launch : kMaxItemsPerLaunch;
     uqc_ctx* ctx = B->ctx;
     UQC_HIP(hipSetDevice(ctx->device));
     const bool dev = is_device_ptr(D);
@@ -961,7 +991,17 @@ uqc_status uqc_fock_build(uqc_basis* B, const double* D, double* J, double* K, d
     size_t ev = 0;
     for (auto& g : plan->groups) {
         if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, ev++), s));
-        UQC_HIP(launch_digest(g.cls, g.mixed, g.d_tasks, g.d_begin, g.ntask, g.nitems, ctx->boys64, ctx->boys32, s));
+        int la, lb, lc, ld;
+        class_ls(g.cls, &la, &lb, &lc, &ld);
+        const int cid = la * 1000 + lb * 100 + lc * 10 + ld + (g.mixed ? 10000 : 0);
+        for (long long i0 = 0; i0 < g.nitems; i0 += max_items) {
+            const long long n = std::min(max_items, g.nitems - i0);
+            UQC_HIP(launch_digest(g.cls, g.mixed, g.d_tasks, g.d_begin, g.ntask, i0, n, ctx->boys64, ctx->boys32, s));
+            if (o.progress) {
+                UQC_HIP(hipStreamSynchronize(s));
+                o.progress(o.progress_user, cid, i0 + n, g.nitems);
+            }
+        }
         if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, ev++), s));
     }
     UQC_HIP(launch_finalize(Dd, B->d_J, B->d_K, B->d_f, Jd, Kd, Gd, B->d_scal, (int)N, s));

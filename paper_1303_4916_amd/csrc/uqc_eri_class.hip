@@ -16,7 +16,7 @@
 namespace uqc {
 
 static hipError_t launch_digest_cls(bool mixed, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
-                                    long long nitems, const double* b64, const float* b32,
+                                    long long item0, long long nitems, const double* b64, const float* b32,
                                     hipStream_t s) {
     const long long waves_per_block = kBlock / kWave;
     const long long nblocks = (nitems + waves_per_block - 1) / waves_per_block;
@@ -25,17 +25,17 @@ static hipError_t launch_digest_cls(bool mixed, const TaskDev* d_tasks, const lo
 #if UQC_TEAM
     if (mixed)
         hipLaunchKernelGGL((k_digest_team<UQC_LA, UQC_LB, UQC_LC, UQC_LD, true>), dim3((unsigned)nblocks),
-                           dim3(kBlock), 0, s, d_tasks, d_task_begin, ntask, nitems, b64, b32);
+                           dim3(kBlock), 0, s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32);
     else
         hipLaunchKernelGGL((k_digest_team<UQC_LA, UQC_LB, UQC_LC, UQC_LD, false>), dim3((unsigned)nblocks),
-                           dim3(kBlock), 0, s, d_tasks, d_task_begin, ntask, nitems, b64, b32);
+                           dim3(kBlock), 0, s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32);
 #else
     if (mixed)
         hipLaunchKernelGGL((k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, true>), dim3((unsigned)nblocks), dim3(kBlock), 0,
-                           s, d_tasks, d_task_begin, ntask, nitems, b64, b32);
+                           s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32);
     else
         hipLaunchKernelGGL((k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, false>), dim3((unsigned)nblocks), dim3(kBlock),
-                           0, s, d_tasks, d_task_begin, ntask, nitems, b64, b32);
+                           0, s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32);
 #endif
     return hipGetLastError();
 }

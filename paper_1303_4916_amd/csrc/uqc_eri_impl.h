@@ -247,7 +247,8 @@ constexpr bool kKacInLds = UQC_KAC_LDS != 0;
 template <int LA, int LB, int LC, int LD, bool MIXED>
 __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev* __restrict__ tasks,
                                                    const long long* __restrict__ task_begin, int ntask,
-                                                   long long nitems, const double* __restrict__ boys64tab,
+                                                   long long item0, long long nitems,
+                                                   const double* __restrict__ boys64tab,
                                                    const float* __restrict__ boys32tab) {
     using C = EriClass<LA, LB, LC, LD>;
     constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
@@ -260,8 +261,9 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
     constexpr bool KEEP_KAC = KAC_MODE != 0;
     constexpr int SLOTS = (KAD_MODE == 2 ? NA * ND : 0) + (KAC_MODE == 2 ? NA * NC : 0);
     __shared__ double slots[kBlock / kWave][SLOTS > 0 ? SLOTS * kWave : 1];
-    const long long item = wave_item();
-    if (item >= nitems) return;
+    const long long local = wave_item();
+    if (local >= nitems) return;
+    const long long item = item0 + local;
     const TaskDev& tk = tasks[find_task(task_begin, ntask, item)];
     const long long li = item - tk.item_begin;
     const int2 it = tk.items[li];

@@ -181,7 +181,8 @@ __device__ __forceinline__ void team_digest_stream(const double* acc, const int*
 template <int LA, int LB, int LC, int LD, bool MIXED>
 __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const TaskDev* __restrict__ tasks,
                                                         const long long* __restrict__ task_begin, int ntask,
-                                                        long long nitems, const double* __restrict__ boys64tab,
+                                                        long long item0, long long nitems,
+                                                   const double* __restrict__ boys64tab,
                                                         const float* __restrict__ boys32tab) {
     using TC = TeamClass<LA, LB, LC, LD>;
     constexpr int NA = TC::NA, NB = TC::NB, NC = TC::NC, ND = TC::ND;
@@ -195,8 +196,9 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
     constexpr int WAVE_LDS = (kTeamsPerWave + 1) * RS;
     __shared__ double lds[kBlock / kWave][WAVE_LDS];
 
-    const long long item = wave_item();
-    if (item >= nitems) return;
+    const long long local = wave_item();
+    if (local >= nitems) return;
+    const long long item = item0 + local;
     const int wid = (int)(threadIdx.x / kWave);
     const int lane = (int)(threadIdx.x % kWave);
     const TaskDev& tk = tasks[find_task(task_begin, ntask, item)];

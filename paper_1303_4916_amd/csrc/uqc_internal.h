@@ -25,6 +25,7 @@ constexpr int kTeamKets = 10;          // ket pairs per wavefront in the six-lan
 constexpr int kGroupBras = 8;          // bra pairs per work item (one wavefront), 64-ket kernels
 constexpr int kTeamGroupBras = 4;      // bra pairs per work item, team kernels
 constexpr int kXcds = 8;               // accelerator complex dies; workgroups are dealt to them round-robin
+constexpr long long kMaxItemsPerLaunch = 1LL << 20;  // work items per class-kernel launch (longer classes split)
 
 // Primitive-pair fields, stored field-major: prim[field][k][np] (consecutive pairs contiguous; the ket side, one
 // pair per lane), and again pair-major: rec[np][k][kRec] (the bra side, one pair per wavefront, scalar loads)
@@ -86,7 +87,8 @@ enum Mode { MODE_STORE = 0, MODE_SCHWARZ = 1 };
 // Host launchers of one angular-momentum class (defined in uqc_eri_class.hip, one object per class).
 struct ClassLaunchers {
     hipError_t (*digest)(bool mixed, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
-                         long long nitems, const double* boys64, const float* boys32, hipStream_t s);
+                         long long item0, long long nitems, const double* boys64, const float* boys32,
+                         hipStream_t s);
     hipError_t (*list)(bool mixed, int mode, const ListDev& list, const double* boys64, const float* boys32,
                        hipStream_t s);
 };
@@ -94,8 +96,10 @@ struct ClassLaunchers {
 // Host-side launchers (defined in uqc_kernels.hip).
 int class_index(int la, int lb, int lc, int ld);           // -1 if not canonical
 void class_ls(int idx, int* la, int* lb, int* lc, int* ld);
+// Work items [item0, item0 + nitems) of one (class, precision) launch group.
 hipError_t launch_digest(int cls, bool mixed, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
-                         long long nitems, const double* boys64, const float* boys32, hipStream_t s);
+                         long long item0, long long nitems, const double* boys64, const float* boys32,
+                         hipStream_t s);
 hipError_t launch_list(int cls, bool mixed, int mode, const ListDev& list, const double* boys64,
                        const float* boys32, hipStream_t s);
 hipError_t launch_prepare(const double* D, const double* f, double* Dp, int nbf, unsigned long long* maxbits,

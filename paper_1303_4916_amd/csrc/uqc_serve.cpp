@@ -212,9 +212,11 @@ bool uqc_server::step() {
     if (pos && hipMemcpyAsync(d_tasks, host.data(), pos, hipMemcpyHostToDevice, s) != hipSuccess)
         return fail_all("server: task upload failed");
     for (size_t gi = 0; gi < groups.size(); ++gi)
-        if (launch_digest(groups[gi].cls, groups[gi].mixed, ptrs[gi].first, ptrs[gi].second,
-                          (int)groups[gi].tasks.size(), groups[gi].items, ctx->boys64, ctx->boys32, s) != hipSuccess)
-            return fail_all("server: class launch failed");
+        for (long long i0 = 0; i0 < groups[gi].items; i0 += kMaxItemsPerLaunch)
+            if (launch_digest(groups[gi].cls, groups[gi].mixed, ptrs[gi].first, ptrs[gi].second,
+                              (int)groups[gi].tasks.size(), i0, std::min(kMaxItemsPerLaunch, groups[gi].items - i0),
+                              ctx->boys64, ctx->boys32, s) != hipSuccess)
+                return fail_all("server: class launch failed");
     std::vector<double> e2(act.size());
     for (size_t i = 0; i < act.size(); ++i) {
         uqc_basis* B = act[i]->basis;

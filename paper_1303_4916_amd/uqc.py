@@ -37,9 +37,13 @@ class UqcError(RuntimeError):
         self.status = status
 
 
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_longlong)
+
+
 class FockOpts(ctypes.Structure):
     _fields_ = [("schwarz_tau", ctypes.c_double), ("precision", ctypes.c_int), ("fp64_bound", ctypes.c_double),
-                ("timing", ctypes.c_int)]
+                ("timing", ctypes.c_int), ("progress", PROGRESS_FN), ("progress_user", ctypes.c_void_p),
+                ("max_items_per_launch", ctypes.c_longlong)]
 
 
 class Stats(ctypes.Structure):
@@ -152,13 +156,22 @@ def _ip(a: np.ndarray):
     return a.ctypes.data_as(_I)
 
 
-def default_opts(tau: float = 1e-12, precision: int = FP64, fp64_bound: float = 1e-8, timing: bool = False):
+def default_opts(tau: float = 1e-12, precision: int = FP64, fp64_bound: float = 1e-8, timing: bool = False,
+                 progress=None, max_items_per_launch: int = 0):
+    """Fock-build options.  progress: None or a callable(class_id, items_done, items_total) called after every
+    class sub-launch has completed on the device (the build then waits for each one).  max_items_per_launch: cap
+    on the work items of one class-kernel launch (0: the library default)."""
     o = FockOpts()
     load().uqc_fock_opts_default(ctypes.byref(o))
     o.schwarz_tau = float(tau)
     o.precision = int(precision)
     o.fp64_bound = float(fp64_bound)
     o.timing = 1 if timing else 0
+    o.max_items_per_launch = int(max_items_per_launch)
+    if progress is not None:
+        fn = PROGRESS_FN(lambda user, cid, done, total: progress(int(cid), int(done), int(total)))
+        o.progress = fn
+        o._progress_ref = fn  # keeps the C callback alive as long as the options object
     return o
 
 

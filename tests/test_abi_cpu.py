@@ -35,6 +35,7 @@ def test_library_has_gfx950_code_object():
 def test_default_options():
     o = uqc.default_opts()
     assert o.schwarz_tau == 1e-12 and o.precision == uqc.FP64 and o.fp64_bound == 1e-8 and o.timing == 0
+    assert not o.progress and o.max_items_per_launch == 0
 
 
 def test_null_arguments_rejected_before_device_use():
@@ -64,7 +65,8 @@ def test_init_without_device_reports_device_error():
 def test_struct_layouts_match_header(tmp_path):
     """The ctypes mirrors of the public structs have the C compiler's sizes and field offsets."""
     import subprocess
-    fields = {"uqc_fock_opts": (uqc.FockOpts, ["schwarz_tau", "precision", "fp64_bound", "timing"]),
+    fields = {"uqc_fock_opts": (uqc.FockOpts, ["schwarz_tau", "precision", "fp64_bound", "timing", "progress",
+                                                 "progress_user", "max_items_per_launch"]),
               "uqc_stats": (uqc.Stats, [f for f, _ in uqc.Stats._fields_]),
               "uqc_request": (uqc.Request, [f for f, _ in uqc.Request._fields_]),
               "uqc_result": (uqc.Result, [f for f, _ in uqc.Result._fields_])}

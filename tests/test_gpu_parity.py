@@ -134,6 +134,31 @@ def test_fock_device_pointers_match_host(ctx):
     assert abs(st.E2 - st2.E2) <= 1e-13 * abs(st.E2)
 
 
+def test_fock_split_launches_and_progress(ctx):
+    """Class launches split into many small ones (7 work items each, ragged ends) give the same J, K, G as single
+    launches; the progress report reaches every class's item total, in increasing steps."""
+    w = wl.lattice(9, seed=35, ndens=1, tau=1e-12)
+    B = uqc.Basis(ctx, w.shells)
+    O = oracle.Basis(w.shells)
+    D = w.densities[0]
+    J1, K1, G1, st1 = B.fock_build(D, uqc.default_opts(tau=1e-12))
+    seen = {}
+
+    def report(cid, done, total):
+        prev = seen.get(cid, (0, total))
+        assert prev[1] == total and done > prev[0] and done <= total
+        seen[cid] = (done, total)
+
+    J2, K2, G2, st2 = B.fock_build(D, uqc.default_opts(tau=1e-12, progress=report, max_items_per_launch=7))
+    assert seen and all(done == total for done, total in seen.values())
+    assert any(total > 7 for _, total in seen.values())
+    for a, b in [(J1, J2), (K1, K2), (G1, G2)]:
+        ok, err, m = close(b, a, tol=1e-13)
+        assert ok, (err, m)
+    assert st1.quartets == st2.quartets
+    _check_fock(B, O, D, 1e-12, J2, K2, G2, st2)
+
+
 def test_fock_zero_and_linear(ctx):
     w = wl.lattice(4, seed=33, ndens=2)
     B = uqc.Basis(ctx, w.shells)
