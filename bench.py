@@ -408,104 +408,6 @@ def bench_mixed(a):
     ctx.close()
 
 
-def _sample_quartets(nshell: int, n: int, seed: int) -> np.ndarray:
-    """Uniform sample of canonical shell quartets (a>=b, c>=d, ab>=cd)."""
-    rng = np.random.default_rng(seed)
-    npair = nshell * (nshell + 1) // 2
-    out = []
-    while len(out) < n:
-        p = rng.integers(0, npair, size=(4 * n, 2))
-        p.sort(axis=1)
-        for cd, ab in p:
-            a = int((np.sqrt(8 * ab + 1) - 1) // 2)
-            b = int(ab - a * (a + 1) // 2)
-            c = int((np.sqrt(8 * cd + 1) - 1) // 2)
-            d = int(cd - c * (c + 1) // 2)
-            out.append((a, b, c, d))
-            if len(out) == n:
-                break
-    return np.array(out, dtype=np.int32)
-
-
-def bench_mixed(a):
-    """Mixed precision (FP32 recursions, FP64 accumulation) vs the FP64 path on one system: full-build G and E2
-    errors, ERI-block errors of both precisions vs the oracle on a uniform sample of canonical quartets."""
-    import torch
-    from paper_1303_4916_amd import uqc
-    from paper_1303_4916_amd import workloads as wl
-    import oracle
-
-    if a.workload == "mixed150":
-        w = wl.mixed150(ndens=1)
-    else:
-        w = wl.large400(ndens=1, k_d=1 if a.workload == "large400kd1" else 3)
-    ctx = uqc.Context(0)
-    t = time.perf_counter()
-    B = uqc.Basis(ctx, w.shells)
-    plan_ms = (time.perf_counter() - t) * 1e3
-    N = B.nbf
-    D = torch.from_numpy(w.densities[0]).cuda()
-    J = torch.empty((N, N), dtype=torch.float64, device="cuda")
-    K = torch.empty_like(J)
-    G = torch.empty_like(J)
-    res = {}
-    print("%s: N=%d, plan %.0f ms" % (w.name, N, plan_ms), file=sys.stderr, flush=True)
-    def report(cid, done, total):
-        print("    class %s: %d of %d work items" % (class_name(cid), done, total), file=sys.stderr, flush=True)
-
-    legs = [("fp64", uqc.default_opts(tau=w.tau, timing=True, progress=report)),
-            ("mixed", uqc.default_opts(tau=w.tau, precision=uqc.MIXED, timing=True, progress=report))]
-    for name, opts in legs[:1] if a.fp64_only else legs:
-        times = []
-        for rep in range(max(1, a.steps)):
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            st = B.fock_build_ptr(D.data_ptr(), J.data_ptr(), K.data_ptr(), G.data_ptr(), opts)
-            times.append(time.perf_counter() - t)
-            print("  %s build %d: %.1f ms" % (name, rep, times[-1] * 1e3), file=sys.stderr, flush=True)
-        res[name] = {"ms": 1e3 * min(times), "E2": st.E2, "G": G.cpu().numpy().copy(), "quartets": st.quartets,
-                     "fp64_quartets": st.fp64_quartets, "flops": st.flops}
-    G64, Gm = res["fp64"]["G"], res["mixed"]["G"]
-    q = _sample_quartets(B.nshell, a.oracle_quartets, 31)
-    O = oracle.Basis(w.shells)
-    oracle.set_threads(min(os.cpu_count() or 1, 16))
-    e64 = em = ref_max = 0.0
-    b64 = B.eri_blocks(q, uqc.FP64)
-    bm = B.eri_blocks(q, uqc.MIXED)
-    for (qa, qb, qc, qd), x64, xm in zip(q, b64, bm):
-        r = O.eri(int(qa), int(qb), int(qc), int(qd))
-        e64 = max(e64, float(np.max(np.abs(x64 - r))))
-        em = max(em, float(np.max(np.abs(xm - r))))
-        ref_max = max(ref_max, float(np.max(np.abs(r))))
-    out = {
-        "metric": METRIC,
-        "value": res["mixed"]["quartets"] / (res["mixed"]["ms"] * 1e-3),
-        "unit": "shell quartets/s",
-        "n_gpus": 1, "steps": a.steps, "warmup": 0,
-        "ms_per_step": res["mixed"]["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 recursions + f64 accumulation", "data": "synthetic",
-        "config": {"workload": w.name + {"mixed150": ": 150 atoms, N=1650, first s K=6, tau=1e-12",
-                                         "large400": ": 400 atoms, N=4400, K=3 on every shell, tau=1e-11",
-                                         "large400kd1": ": 400 atoms, N=4400, K=3 on s and p, K=1 on d, "
-                                                        "tau=1e-11"}[a.workload],
-                   "nbf": N, "tau": w.tau, "fp64_bound": uqc.default_opts().fp64_bound},
-        "plan_ms": plan_ms,
-        "fp64_build_ms": res["fp64"]["ms"], "mixed_build_ms": res["mixed"]["ms"],
-        "mixed_speedup_vs_fp64": res["fp64"]["ms"] / res["mixed"]["ms"],
-        "quartets_per_build": res["fp64"]["quartets"],
-        "mixed_fp64_routed_quartets": res["mixed"]["fp64_quartets"],
-        "E2_fp64": res["fp64"]["E2"], "abs_E2_error_mixed_vs_fp64_Eh": abs(res["mixed"]["E2"] - res["fp64"]["E2"]),
-        "G_frobenius_rel_error_mixed_vs_fp64": float(np.linalg.norm(Gm - G64) / np.linalg.norm(G64)),
-        "G_max_abs_error_mixed_vs_fp64": float(np.max(np.abs(Gm - G64))),
-        "oracle_sample": {"quartets": int(len(q)), "max_abs_eri_error_fp64": e64, "max_abs_eri_error_mixed": em,
-                          "max_abs_eri": ref_max, "sample": "uniform over canonical shell quartets, seed 31"},
-        "fp64_tflops_algorithmic": res["fp64"]["flops"] / (res["fp64"]["ms"] * 1e-3) / 1e12,
-    }
-    print(json.dumps(out), flush=True)
-    B.close()
-    ctx.close()
-
-
 def bench_copy(a):
     """Reference for hardware traffic counters: a plain device-to-device copy of exactly 1 GiB, three times."""
     import torch
