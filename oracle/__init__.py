@@ -56,6 +56,7 @@ def lib():
                                               ctypes.c_int, _I]
             L.oracle_j_block.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int, _D]
             L.oracle_k_block.argtypes = [ctypes.c_void_p, _D, ctypes.c_double, ctypes.c_int, ctypes.c_int, _D]
+            L.oracle_one_electron.argtypes = [ctypes.c_void_p, ctypes.c_int, _D, _D, _D, _D, _D]
             L.oracle_num_threads.restype = ctypes.c_int
             L.oracle_set_num_threads.argtypes = [ctypes.c_int]
             _lib = L
@@ -169,6 +170,59 @@ class Basis:
         out = np.zeros((ncart(int(self.l[a])), ncart(int(self.l[d]))))
         lib().oracle_k_block(self.h, _dp(D), float(tau), a, d, _dp(out))
         return out
+
+
+def nuclear_repulsion(Z, R) -> float:
+    """E_nuc = sum_{A<B} Z_A Z_B / |R_A - R_B| (bohr, hartree)."""
+    Z = np.asarray(Z, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64).reshape(-1, 3)
+    e = 0.0
+    for a in range(len(Z)):
+        for b in range(a):
+            e += Z[a] * Z[b] / float(np.linalg.norm(R[a] - R[b]))
+    return e
+
+
+def one_electron(basis: "Basis", Z, R):
+    """Overlap S, kinetic T and nuclear attraction V matrices (Eq. (2)-(4)) for point nuclei Z at R."""
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1)
+    N = basis.nbf
+    S, T, V = (np.zeros((N, N)) for _ in range(3))
+    lib().oracle_one_electron(basis.h, int(Z.shape[0]), _dp(Z), _dp(R), _dp(S), _dp(T), _dp(V))
+    return S, T, V
+
+
+def rhf(shells, Z, R, nocc: int, tau: float = 0.0, max_iter: int = 200, e_conv: float = 1e-12,
+        d_conv: float = 1e-10):
+    """Restricted closed-shell Hartree-Fock by plain Roothaan iteration (Szabo-Ostlund Sec. 3.4.6): symmetric
+    orthogonalisation X = S^{-1/2}, core-Hamiltonian guess, P = 2 C_occ C_occ^T, F = H + J(P) - K(P)/2,
+    E = 1/2 tr P (H + F) + E_nuc.  No acceleration, no damping."""
+    O = Basis(shells)
+    S, T, V = one_electron(O, Z, R)
+    H = T + V
+    s, U = np.linalg.eigh(S)
+    X = U @ np.diag(s ** -0.5) @ U.T
+    N = O.nbf
+    P = np.zeros((N, N))
+    e_old = 0.0
+    for it in range(1, max_iter + 1):
+        J, K, _ = O.jk_symmetric([P], tau=tau)
+        F = H + J[0] - 0.5 * K[0]
+        e_el = 0.5 * float(np.sum(P * (H + F)))
+        eps, Cp = np.linalg.eigh(X.T @ F @ X)
+        C = X @ Cp
+        Pn = 2.0 * C[:, :nocc] @ C[:, :nocc].T
+        dP = float(np.max(np.abs(Pn - P)))
+        P = Pn
+        if it > 1 and abs(e_el - e_old) < e_conv and dP < d_conv:
+            break
+        e_old = e_el
+    else:
+        raise RuntimeError("oracle rhf: no convergence in %d iterations" % max_iter)
+    e_nuc = nuclear_repulsion(Z, R)
+    return {"E_elec": e_el, "E_nuc": e_nuc, "E_total": e_el + e_nuc, "P": P, "C": C, "eps": eps,
+            "iterations": it, "S": S, "T": T, "V": V}
 
 
 def fock_parts(J: np.ndarray, K: np.ndarray, D: np.ndarray):

@@ -9,7 +9,9 @@
 //   * electron-repulsion integrals (ij|kl), Eq. (5), evaluated exactly (the "analytic" route the paper attributes
 //     to Cook, here the McMurchie-Davidson Hermite expansion);
 //   * J_ij = sum_kl (ij|kl) D_kl and K_il = sum_jk (ij|kl) D_jk, Eq. (12), for a symmetric density D;
-//   * G = J - K/2 and E2 = 1/2 sum_ij D_ij G_ij (closed-shell convention of Szabo-Ostlund, which the paper follows).
+//   * G = J - K/2 and E2 = 1/2 sum_ij D_ij G_ij (closed-shell convention of Szabo-Ostlund, which the paper follows);
+//   * overlap, kinetic and nuclear-attraction integrals, Eq. (2)-(4), for the restricted Hartree-Fock reference
+//     (the SCF iteration itself is in the Python package, on top of these integrals and J/K).
 //
 // Readings of points the paper leaves open (each listed in the design notes):
 //   * one exponent per primitive, shared by every Cartesian component of a shell;
@@ -111,7 +113,7 @@ double same_centre_overlap(double a, double b, int lx, int ly, int lz) {
 //   E_t^{i,j+1} = E_{t-1}^{ij}/(2p) + X_PB E_t^{ij} + (t+1) E_{t+1}^{ij}
 // ---------------------------------------------------------------------------------------------------------------
 struct Ecoef {
-    double e[3][3][5];  // [i][j][t], i, j <= 2, t <= 4
+    double e[3][5][8];  // [i][j][t], i <= 2, j <= 4 (the kinetic integral raises the ket power by 2), t <= i + j
 };
 
 void hermite_E(int imax, int jmax, double p, double XPA, double XPB, double XAB, double mu, Ecoef& E) {
@@ -286,6 +288,70 @@ bool keep(const Basis& B, int a, int b, int c, int d, double tau) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------------------------------------------------------
+// One-electron integrals over the same basis (paper, Eq. (2)-(4)), McMurchie-Davidson form, per primitive pair
+// (a: alpha, A, powers i; b: beta, B, powers j), p = alpha + beta, P the product centre:
+//   overlap     S = E_0^{ix jx} E_0^{iy jy} E_0^{iz jz} (pi/p)^{3/2}
+//   kinetic     T = -1/2 <a|nabla^2|b> = sum over directions of t_x s_y s_z, with the one-dimensional pieces
+//                 s_{ij} = E_0^{ij} (pi/p)^{1/2}
+//                 t_{ij} = -2 beta^2 s_{i,j+2} + beta (2j+1) s_{ij} - j(j-1)/2 s_{i,j-2}
+//               (the second derivative of the ket factor x^j exp(-beta x^2))
+//   attraction  V = -sum_C Z_C (2 pi / p) sum_{tuv} E_t^x E_u^y E_v^z R_{tuv}(p, P - C)
+//               with R the Hermite Coulomb integrals of a point charge (exponent p, argument p |P - C|^2)
+// ---------------------------------------------------------------------------------------------------------------
+void one_electron_pair(const Basis& B, int ia, int ib, int natom, const double* Z, const double* Rn, double* S,
+                       double* T, double* V) {
+    const Shell &a = B.sh[ia], &b = B.sh[ib];
+    const int na = ncart(a.l), nb = ncart(b.l);
+    const double pi = 3.14159265358979323846;
+    int pa[6][3], pb[6][3];
+    for (int i = 0; i < na; ++i) cart_powers(a.l, i, pa[i][0], pa[i][1], pa[i][2]);
+    for (int j = 0; j < nb; ++j) cart_powers(b.l, j, pb[j][0], pb[j][1], pb[j][2]);
+    for (int x = 0; x < na * nb; ++x) S[x] = T[x] = V[x] = 0.0;
+    Ecoef E[3];
+    Rtab R;
+    for (int p1 = 0; p1 < a.K; ++p1)
+        for (int p2 = 0; p2 < b.K; ++p2) {
+            const double al = a.alpha[p1], be = b.alpha[p2];
+            const double p = al + be, mu = al * be / p;
+            double P[3];
+            for (int x = 0; x < 3; ++x) {
+                P[x] = (al * a.A[x] + be * b.A[x]) / p;
+                hermite_E(a.l, b.l + 2, p, P[x] - a.A[x], P[x] - b.A[x], a.A[x] - b.A[x], mu, E[x]);
+            }
+            const double r1 = std::sqrt(pi / p);
+            auto s1 = [&](int x, int i, int j) { return j < 0 ? 0.0 : E[x].e[i][j][0] * r1; };
+            auto t1 = [&](int x, int i, int j) {
+                return -2.0 * be * be * s1(x, i, j + 2) + be * (2 * j + 1) * s1(x, i, j) - 0.5 * j * (j - 1) * s1(x, i, j - 2);
+            };
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) {
+                    const double c = a.cc[i][p1] * b.cc[j][p2];
+                    const int *u = pa[i], *w = pb[j];
+                    const double sx = s1(0, u[0], w[0]), sy = s1(1, u[1], w[1]), sz = s1(2, u[2], w[2]);
+                    S[i * nb + j] += c * sx * sy * sz;
+                    T[i * nb + j] += c * (t1(0, u[0], w[0]) * sy * sz + sx * t1(1, u[1], w[1]) * sz +
+                                          sx * sy * t1(2, u[2], w[2]));
+                }
+            for (int n = 0; n < natom; ++n) {
+                const double PC[3] = {P[0] - Rn[3 * n], P[1] - Rn[3 * n + 1], P[2] - Rn[3 * n + 2]};
+                const double Tb = p * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
+                hermite_R(a.l + b.l, p, Tb, PC, R);
+                for (int i = 0; i < na; ++i)
+                    for (int j = 0; j < nb; ++j) {
+                        const int *u = pa[i], *w = pb[j];
+                        double sum = 0.0;
+                        for (int t = 0; t <= u[0] + w[0]; ++t)
+                            for (int v = 0; v <= u[1] + w[1]; ++v)
+                                for (int q = 0; q <= u[2] + w[2]; ++q)
+                                    sum += E[0].e[u[0]][w[0]][t] * E[1].e[u[1]][w[1]][v] * E[2].e[u[2]][w[2]][q] *
+                                           R.r[t][v][q];
+                        V[i * nb + j] -= a.cc[i][p1] * b.cc[j][p2] * Z[n] * (2.0 * pi / p) * sum;
+                    }
+            }
+        }
+}
 
 extern "C" {
 
@@ -562,6 +628,28 @@ void oracle_k_block(void* h, const double* D, double tau, int a, int d, double* 
     std::fill(Kblk, Kblk + na * nd, 0.0);
     for (int t = 0; t < nt; ++t)
         for (int x = 0; x < na * nd; ++x) Kblk[x] += acc[t][x];
+}
+
+// Overlap S, kinetic T and nuclear attraction V (point nuclei of charges Z at R, [natom][3] bohr) over the basis,
+// nbf x nbf row-major each (Eq. (2)-(4)).
+void oracle_one_electron(void* basis, int natom, const double* Z, const double* R, double* S, double* T, double* V) {
+    const Basis& B = *(const Basis*)basis;
+    const int ns = (int)B.sh.size(), N = B.nbf;
+#pragma omp parallel for schedule(dynamic) collapse(2)
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b) {
+            double s[36], t[36], v[36];
+            one_electron_pair(B, a, b, natom, Z, R, s, t, v);
+            const Shell &A = B.sh[a], &Bs = B.sh[b];
+            const int na = ncart(A.l), nb = ncart(Bs.l);
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) {
+                    const size_t x = (size_t)(A.off + i) * N + Bs.off + j;
+                    S[x] = s[i * nb + j];
+                    T[x] = t[i * nb + j];
+                    V[x] = v[i * nb + j];
+                }
+        }
 }
 
 int oracle_num_threads(void) { return omp_get_max_threads(); }
