@@ -138,6 +138,45 @@ uqc_status uqc_eri_blocks(uqc_basis* b, int n, const int* quartets, int precisio
 uqc_status uqc_fock_build(uqc_basis* b, const double* D, double* J, double* K, double* G, const uqc_fock_opts* opts,
                           uqc_stats* stats);
 
+/* One-electron integrals over the basis (paper, Eq. (2)-(4)): overlap S, kinetic T and attraction V to point nuclei
+ * of charges Z[natom] at R[natom][3] (bohr; host arrays, natom >= 0), each nbf*nbf row-major.  S, T, V are all
+ * device pointers or all host pointers; any may be NULL.  Same basis conventions as the ERIs.
+ * Errors: UQC_E_ARG, UQC_E_NOMEM, UQC_E_DEVICE. */
+uqc_status uqc_one_electron(uqc_basis* b, int natom, const double* Z, const double* R, double* S, double* T,
+                            double* V);
+
+/* Restricted closed-shell Hartree-Fock around the Fock build (the paper's HF method with Pulay DIIS acceleration,
+ * Sec. "Implementation details", and the closed-shell equations of Szabo-Ostlund it follows): symmetric
+ * orthogonalisation X = S^{-1/2}, core-Hamiltonian guess, F = H + J(P) - K(P)/2 with P = 2 C_occ C_occ^T,
+ * E = 1/2 tr P (H + F) + E_nuc.  Every matrix stays on the device; eigendecompositions use rocSOLVER. */
+typedef struct {
+    int max_iter;          /* default 100 */
+    double e_conv;         /* |E_k - E_(k-1)| in hartree, default 1e-10 */
+    double d_conv;         /* max |F P S - S P F|, default 1e-8 */
+    int diis_size;         /* DIIS subspace size (0: plain Roothaan iteration), default 8, at most 16 */
+    uqc_fock_opts fock;    /* options of every Fock build (its progress callback is not used) */
+} uqc_scf_opts;
+
+typedef struct {
+    double E_total, E_elec, E_nuc;
+    int iterations;        /* Fock builds performed */
+    int converged;         /* 1 if both criteria were met within max_iter */
+    double error;          /* final max |F P S - S P F| */
+    double ms;             /* wall time of the call */
+    double fock_ms;        /* of which in Fock builds */
+    long long quartets;    /* shell quartets of one Fock build */
+} uqc_scf_result;
+
+/* Fills *o with the defaults above and uqc_fock_opts_default() for the builds. */
+void uqc_scf_opts_default(uqc_scf_opts* o);
+
+/* Runs the SCF for nuclei Z[natom] at R[natom][3] (host arrays) with nocc doubly occupied orbitals (1 <= nocc <=
+ * nbf).  P (host, nbf*nbf) and eps (host, nbf: orbital energies, ascending) receive the final density and orbital
+ * energies if not NULL.  Not converging within max_iter is not an error (res->converged = 0).
+ * Errors: UQC_E_ARG, UQC_E_NOMEM, UQC_E_DEVICE (also when S is numerically singular). */
+uqc_status uqc_scf_rhf(uqc_basis* b, int natom, const double* Z, const double* R, int nocc, const uqc_scf_opts* o,
+                       double* P, double* eps, uqc_scf_result* res);
+
 /* Device Boys function, for verification: F_0..F_mmax (mmax <= 8) at n arguments T (host arrays; out is
  * n*(mmax+1), row-major).  precision UQC_FP64: tabulated Taylor grid + downward recursion (asymptotic form with
  * upward recursion beyond the grid); UQC_MIXED: the FP32 evaluation used for T <= 30 in mixed mode. */

@@ -58,7 +58,8 @@ def _units():
     headers = [os.path.join(CSRC, h) for h in ("uqc_internal.h", "uqc_device_common.h", "uqc_eri_impl.h",
                                                "uqc_api_internal.h")]
     headers += [os.path.join(GEN, "eri_classes.h"), os.path.join(GEN, "eri_flops.h"),
-                os.path.join(ROOT, "include", "uqc.h")]
+                os.path.join(ROOT, "include", "uqc.h"), os.path.join(CSRC, "uqc_one.h"),
+                os.path.join(GEN, "one_electron.h")]
     units = []
     team = _team_classes()
     headers = headers + [os.path.join(CSRC, "uqc_eri_team.h"), os.path.join(GEN, "eri_team.h")]
@@ -69,7 +70,7 @@ def _units():
                       (["-DUQC_WAVES_ATTR=__attribute__((amdgpu_waves_per_eu(2)))"]
                        if (la, lb, lc, ld) in TWO_WAVES else []) +
                       (["-DUQC_KAC_LDS=0"] if (la, lb, lc, ld) in KAC_NOT_IN_LDS else []), headers))
-    for src in ("uqc_kernels.hip", "uqc_api.cpp", "uqc_serve.cpp"):
+    for src in ("uqc_kernels.hip", "uqc_one.hip", "uqc_api.cpp", "uqc_serve.cpp", "uqc_scf.cpp"):
         units.append((os.path.join(CSRC, src), os.path.join(OBJ, os.path.splitext(src)[0] + ".o"), [], headers))
     # heaviest classes first so they start early
     units.sort(key=lambda u: -int(u[2][0].split("=")[1]) if u[2] else 0)
@@ -95,8 +96,8 @@ def _compile(unit):
 
 def build(incremental: bool = False, jobs: int = None, verbose: bool = True) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    gen = os.path.join(CSRC, "gen_eri.py")
-    subprocess.check_call([sys.executable, gen, GEN])
+    for gen in ("gen_eri.py", "gen_one.py"):
+        subprocess.check_call([sys.executable, os.path.join(CSRC, gen), GEN])
     units = _units()
     todo = [u for u in units if not incremental or _stale(u[1], [u[0]] + u[3])]
     jobs = jobs or min(16, os.cpu_count() or 4)
@@ -107,7 +108,8 @@ def build(incremental: bool = False, jobs: int = None, verbose: bool = True) -> 
                 print("  compiled %-22s %6.1f s" % (name, dt), flush=True)
     objs = [u[1] for u in units]
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + [
+        "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (r.stdout, r.stderr))

@@ -145,6 +145,7 @@ uqc_status uqc_finalize(uqc_ctx* c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto& e : c->events) (void)hipEventDestroy(e);
+    release_blas(c);
     if (c->boys64) (void)hipFree(c->boys64);
     if (c->boys32) (void)hipFree(c->boys32);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -175,6 +176,8 @@ uqc_basis::~uqc_basis() {
     }
     for (auto& kv : plans) free_plan(kv.second);
     if (d_work) (void)hipFree(d_work);
+    if (d_shells) (void)hipFree(d_shells);
+    if (d_nuc) (void)hipFree(d_nuc);
 }
 
 void uqc::free_plan(Plan& p) {
@@ -793,7 +796,7 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
 }
 
 // ---------------------------------------------------------------------------------------------- ERI blocks
-static bool is_device_ptr(const void* p) {
+bool uqc::is_device_ptr(const void* p) {
     if (!p) return false;
     hipPointerAttribute_t attr;
     if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
@@ -956,9 +959,9 @@ uqc_status uqc_fock_build(uqc_basis* B, const double* D, double* J, double* K, d
     const long long max_items = o.max_items_per_launch > 0 ? o.max_items_per_launch : kMaxItemsPerLaunch;
     uqc_ctx* ctx = B->ctx;
     UQC_HIP(hipSetDevice(ctx->device));
-    const bool dev = is_device_ptr(D);
+    const bool dev = uqc::is_device_ptr(D);
     for (const void* p : {(const void*)J, (const void*)K, (const void*)G})
-        if (p && is_device_ptr(p) != dev)
+        if (p && uqc::is_device_ptr(p) != dev)
             return uqc_fail(UQC_E_ARG, "uqc_fock_build: mix of host and device pointers");
     uqc_status st = UQC_OK;
     Plan* plan = get_plan(B, o.schwarz_tau, o.precision, o.fp64_bound, &st);

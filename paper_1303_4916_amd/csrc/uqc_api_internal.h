@@ -2,6 +2,7 @@
 #pragma once
 #include "uqc.h"
 #include "uqc_internal.h"
+#include "uqc_one.h"
 
 #include <list>
 #include <string>
@@ -24,7 +25,10 @@ struct uqc_ctx {
     double* boys64 = nullptr;
     float* boys32 = nullptr;
     std::vector<hipEvent_t> events;
+    void* blas = nullptr;  // rocblas_handle of the SCF driver, created on first use
 };
+
+void release_blas(uqc_ctx* c);  // destroys the rocBLAS handle if one was created
 
 hipEvent_t ctx_event(uqc_ctx* c, size_t i);
 
@@ -99,7 +103,18 @@ struct uqc_basis {
     void* d_work = nullptr;
     size_t work_bytes = 0;
     double *d_f = nullptr, *d_Dp = nullptr, *d_J = nullptr, *d_K = nullptr, *d_scal = nullptr, *d_io = nullptr;
+    // one-electron integrals: shell table and per-pair-class shell-pair lists (uploaded on first use), nuclei
+    void* d_shells = nullptr;
+    uqc::ShellsDev shells_dev{};
+    const int2* d_pairs[6] = {};
+    int npairs[6] = {};
+    double* d_nuc = nullptr;
+    size_t nuc_cap = 0;
     ~uqc_basis();
 };
 
 uqc::Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st);
+
+namespace uqc {
+bool is_device_ptr(const void* p);  // device or managed memory (false for host memory and null)
+}

@@ -105,6 +105,9 @@ hipError_t launch_list(int cls, bool mixed, int mode, const ListDev& list, const
 hipError_t launch_prepare(const double* D, const double* f, double* Dp, int nbf, unsigned long long* maxbits,
                           hipStream_t s);
 hipError_t launch_zero(double* p, size_t n, hipStream_t s);
+hipError_t launch_add(const double* A, const double* B, double* C, size_t n, hipStream_t s);   // C = A + B
+hipError_t launch_scale_cols(const double* U, const double* w, double* W, int N, hipStream_t s);  // W = U diag(w)
+hipError_t launch_antisym(const double* M, double* E, int N, hipStream_t s);                  // E = M - M^T
 hipError_t launch_finalize(const double* D, const double* Jacc, const double* Kacc, const double* f, double* J,
                            double* K, double* G, double* E2, int nbf, hipStream_t s);
 hipError_t launch_boys(int prec, int mmax, int n, const double* T, double* out, const double* boys64,

@@ -116,6 +116,30 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
     if ((threadIdx.x % kWave) == 0) atomic_add(E2, 0.5 * e);
 }
 
+// C = A + B (n elements)
+__global__ __launch_bounds__(kBlock) void k_add(const double* __restrict__ A, const double* __restrict__ B,
+                                                double* __restrict__ C, size_t n) {
+    for (size_t x = (size_t)blockIdx.x * kBlock + threadIdx.x; x < n; x += (size_t)gridDim.x * kBlock)
+        C[x] = A[x] + B[x];
+}
+
+// W = U diag(w) for a column-major N x N matrix U: column k of U scaled by w_k
+__global__ __launch_bounds__(kBlock) void k_scale_cols(const double* __restrict__ U, const double* __restrict__ w,
+                                                       double* __restrict__ W, int N) {
+    const size_t NN = (size_t)N * N;
+    for (size_t x = (size_t)blockIdx.x * kBlock + threadIdx.x; x < NN; x += (size_t)gridDim.x * kBlock)
+        W[x] = U[x] * w[x / N];
+}
+
+// E = M - M^T (N x N)
+__global__ __launch_bounds__(kBlock) void k_antisym(const double* __restrict__ M, double* __restrict__ E, int N) {
+    const size_t NN = (size_t)N * N;
+    for (size_t x = (size_t)blockIdx.x * kBlock + threadIdx.x; x < NN; x += (size_t)gridDim.x * kBlock) {
+        const size_t i = x / N, j = x % N;
+        E[x] = M[x] - M[j * N + i];
+    }
+}
+
 static unsigned grid_for(long long n) {
     long long b = (n + kBlock - 1) / kBlock;
     if (b > 4096) b = 4096;
@@ -126,6 +150,21 @@ static unsigned grid_for(long long n) {
 hipError_t launch_prepare(const double* D, const double* f, double* Dp, int nbf, unsigned long long* maxbits,
                           hipStream_t s) {
     hipLaunchKernelGGL(k_prepare, dim3(grid_for((long long)nbf * nbf)), dim3(kBlock), 0, s, D, f, Dp, nbf, maxbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(const double* A, const double* B, double* C, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_add, dim3(grid_for((long long)n)), dim3(kBlock), 0, s, A, B, C, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_cols(const double* U, const double* w, double* W, int N, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_cols, dim3(grid_for((long long)N * N)), dim3(kBlock), 0, s, U, w, W, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_antisym(const double* M, double* E, int N, hipStream_t s) {
+    hipLaunchKernelGGL(k_antisym, dim3(grid_for((long long)N * N)), dim3(kBlock), 0, s, M, E, N);
     return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ MAX_ITER = 64
 EXPORTED = ["uqc_fock_opts_default", "uqc_init", "uqc_finalize", "uqc_last_error", "uqc_basis_create",
             "uqc_basis_destroy", "uqc_basis_info", "uqc_schwarz", "uqc_eri_block", "uqc_eri_blocks",
             "uqc_fock_build", "uqc_boys", "uqc_server_create", "uqc_submit", "uqc_poll", "uqc_server_drain",
-            "uqc_server_destroy"]
+            "uqc_server_destroy", "uqc_one_electron", "uqc_scf_opts_default", "uqc_scf_rhf"]
 
 
 class UqcError(RuntimeError):
@@ -44,6 +44,17 @@ class FockOpts(ctypes.Structure):
     _fields_ = [("schwarz_tau", ctypes.c_double), ("precision", ctypes.c_int), ("fp64_bound", ctypes.c_double),
                 ("timing", ctypes.c_int), ("progress", PROGRESS_FN), ("progress_user", ctypes.c_void_p),
                 ("max_items_per_launch", ctypes.c_longlong)]
+
+
+class ScfOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("e_conv", ctypes.c_double), ("d_conv", ctypes.c_double),
+                ("diis_size", ctypes.c_int), ("fock", FockOpts)]
+
+
+class ScfResult(ctypes.Structure):
+    _fields_ = [("E_total", ctypes.c_double), ("E_elec", ctypes.c_double), ("E_nuc", ctypes.c_double),
+                ("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("error", ctypes.c_double),
+                ("ms", ctypes.c_double), ("fock_ms", ctypes.c_double), ("quartets", ctypes.c_longlong)]
 
 
 class Stats(ctypes.Structure):
@@ -135,8 +146,13 @@ def load(build_if_missing: bool = True):
         L.uqc_poll.argtypes = [vp, ctypes.c_longlong, ctypes.POINTER(Result)]
         L.uqc_server_drain.argtypes = [vp]
         L.uqc_server_destroy.argtypes = [vp]
+        L.uqc_one_electron.argtypes = [vp, ctypes.c_int, _D, _D, vp, vp, vp]
+        L.uqc_scf_opts_default.argtypes = [ctypes.POINTER(ScfOpts)]
+        L.uqc_scf_opts_default.restype = None
+        L.uqc_scf_rhf.argtypes = [vp, ctypes.c_int, _D, _D, ctypes.c_int, ctypes.POINTER(ScfOpts), _D, _D,
+                                  ctypes.POINTER(ScfResult)]
         for name in EXPORTED:
-            if name not in ("uqc_fock_opts_default", "uqc_last_error"):
+            if name not in ("uqc_fock_opts_default", "uqc_last_error", "uqc_scf_opts_default"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
         return L
@@ -154,6 +170,20 @@ def _dp(a: np.ndarray):
 
 def _ip(a: np.ndarray):
     return a.ctypes.data_as(_I)
+
+
+def scf_opts(max_iter: int = 100, e_conv: float = 1e-10, d_conv: float = 1e-8, diis_size: int = 8,
+             fock: FockOpts = None) -> ScfOpts:
+    """Options of uqc_scf_rhf (library defaults unless given)."""
+    o = ScfOpts()
+    load().uqc_scf_opts_default(ctypes.byref(o))
+    o.max_iter = int(max_iter)
+    o.e_conv = float(e_conv)
+    o.d_conv = float(d_conv)
+    o.diis_size = int(diis_size)
+    if fock is not None:
+        o.fock = fock
+    return o
 
 
 def default_opts(tau: float = 1e-12, precision: int = FP64, fp64_bound: float = 1e-8, timing: bool = False,
@@ -322,6 +352,39 @@ class Basis:
         ptr = lambda a: a.ctypes.data if a is not None else 0
         st = self.fock_build_ptr(D.ctypes.data, ptr(outs["J"]), ptr(outs["K"]), ptr(outs["G"]), opts)
         return outs["J"], outs["K"], outs["G"], st
+
+
+    def one_electron(self, Z, R, want=("S", "T", "V")):
+        """Overlap, kinetic and nuclear-attraction matrices for nuclei Z[natom] at R[natom][3] (host numpy arrays
+        out; None for those not requested)."""
+        Z = np.ascontiguousarray(Z, dtype=np.float64).reshape(-1)
+        R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1)
+        if R.shape[0] != 3 * Z.shape[0]:
+            raise ValueError("R must hold 3 coordinates per nucleus")
+        N = self.nbf
+        outs = {k: (np.zeros((N, N)) if k in want else None) for k in ("S", "T", "V")}
+        ptr = lambda a: ctypes.c_void_p(a.ctypes.data) if a is not None else None
+        _check(load().uqc_one_electron(self.h, int(Z.shape[0]), _dp(Z), _dp(R), ptr(outs["S"]), ptr(outs["T"]),
+                                       ptr(outs["V"])))
+        return outs["S"], outs["T"], outs["V"]
+
+    def scf_rhf(self, Z, R, nocc: int, opts: ScfOpts = None):
+        """Restricted closed-shell Hartree-Fock; returns a dict with the energies, iteration count, convergence
+        flag, final error, timings, the density P and the orbital energies."""
+        Z = np.ascontiguousarray(Z, dtype=np.float64).reshape(-1)
+        R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1)
+        if R.shape[0] != 3 * Z.shape[0]:
+            raise ValueError("R must hold 3 coordinates per nucleus")
+        N = self.nbf
+        P = np.zeros((N, N))
+        eps = np.zeros(N)
+        res = ScfResult()
+        o = opts if opts is not None else scf_opts()
+        _check(load().uqc_scf_rhf(self.h, int(Z.shape[0]), _dp(Z), _dp(R), int(nocc), ctypes.byref(o), _dp(P),
+                                  _dp(eps), ctypes.byref(res)))
+        return {"E_total": res.E_total, "E_elec": res.E_elec, "E_nuc": res.E_nuc, "iterations": res.iterations,
+                "converged": bool(res.converged), "error": res.error, "ms": res.ms, "fock_ms": res.fock_ms,
+                "quartets": res.quartets, "P": P, "eps": eps}
 
 
 class Server:

@@ -47,6 +47,11 @@ def test_null_arguments_rejected_before_device_use():
     assert L.uqc_eri_block(None, 0, 0, 0, 0, 0, None) == uqc.UQC_E_ARG
     assert L.uqc_poll(None, 1, None) == uqc.UQC_E_ARG
     assert L.uqc_server_destroy(None) == uqc.UQC_E_ARG
+    assert L.uqc_one_electron(None, 0, None, None, None, None, None) == uqc.UQC_E_ARG
+    assert L.uqc_scf_rhf(None, 0, None, None, 1, None, None, None, None) == uqc.UQC_E_ARG
+    o = uqc.scf_opts()
+    assert o.max_iter == 100 and o.e_conv == 1e-10 and o.d_conv == 1e-8 and o.diis_size == 8
+    assert o.fock.schwarz_tau == 1e-12 and o.fock.precision == uqc.FP64
 
 
 def test_init_without_device_reports_device_error():
@@ -68,6 +73,8 @@ def test_struct_layouts_match_header(tmp_path):
     fields = {"uqc_fock_opts": (uqc.FockOpts, ["schwarz_tau", "precision", "fp64_bound", "timing", "progress",
                                                  "progress_user", "max_items_per_launch"]),
               "uqc_stats": (uqc.Stats, [f for f, _ in uqc.Stats._fields_]),
+              "uqc_scf_opts": (uqc.ScfOpts, [f for f, _ in uqc.ScfOpts._fields_]),
+              "uqc_scf_result": (uqc.ScfResult, [f for f, _ in uqc.ScfResult._fields_]),
               "uqc_request": (uqc.Request, [f for f, _ in uqc.Request._fields_]),
               "uqc_result": (uqc.Result, [f for f, _ in uqc.Result._fields_])}
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "uqc.h"', "int main(void) {"]
