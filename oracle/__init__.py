@@ -225,6 +225,66 @@ def rhf(shells, Z, R, nocc: int, tau: float = 0.0, max_iter: int = 200, e_conv: 
             "iterations": it, "S": S, "T": T, "V": V}
 
 
+def mix_homo_lumo(C: np.ndarray, n: int, theta: float) -> np.ndarray:
+    """Rotates the highest occupied (index n-1) and lowest virtual (index n) columns of C by the angle theta:
+    c_h' = cos(theta) c_h + sin(theta) c_l, c_l' = -sin(theta) c_h + cos(theta) c_l (a guess that breaks the
+    spatial and spin symmetry of a closed-shell start; no change if theta = 0 or n is 0 or nbf)."""
+    C = C.copy()
+    if theta != 0.0 and 0 < n < C.shape[1]:
+        h, l = C[:, n - 1].copy(), C[:, n].copy()
+        C[:, n - 1] = np.cos(theta) * h + np.sin(theta) * l
+        C[:, n] = -np.sin(theta) * h + np.cos(theta) * l
+    return C
+
+
+def uhf(shells, Z, R, nalpha: int, nbeta: int, tau: float = 0.0, guess_mix: float = 0.0, max_iter: int = 500,
+        e_conv: float = 1e-12, d_conv: float = 1e-10):
+    """Unrestricted Hartree-Fock (the paper's URHF; Pople-Nesbet equations, Szabo-Ostlund Sec. 3.8) by plain
+    iteration: X = S^{-1/2}, core-Hamiltonian guess for both spins (the alpha guess optionally rotated by
+    mix_homo_lumo), P^s = C^s_occ C^s_occ^T, F^s = H + J(P^a + P^b) - K(P^s),
+    E = 1/2 tr[(P^a + P^b) H + P^a F^a + P^b F^b] + E_nuc.  No acceleration, no damping."""
+    O = Basis(shells)
+    S, T, V = one_electron(O, Z, R)
+    H = T + V
+    s, U = np.linalg.eigh(S)
+    X = U @ np.diag(s ** -0.5) @ U.T
+    _, Cp = np.linalg.eigh(X.T @ H @ X)
+    C0 = X @ Cp
+    Ca = mix_homo_lumo(C0, nalpha, guess_mix)
+    Cb = C0
+    Pa = Ca[:, :nalpha] @ Ca[:, :nalpha].T
+    Pb = Cb[:, :nbeta] @ Cb[:, :nbeta].T
+    e_old = 0.0
+    for it in range(1, max_iter + 1):
+        J, K, _ = O.jk_symmetric([Pa, Pb], tau=tau)
+        Jt = J[0] + J[1]
+        Fa, Fb = H + Jt - K[0], H + Jt - K[1]
+        e_el = 0.5 * float(np.sum((Pa + Pb) * H + Pa * Fa + Pb * Fb))
+        ea, Ca = np.linalg.eigh(X.T @ Fa @ X)
+        eb, Cb = np.linalg.eigh(X.T @ Fb @ X)
+        Ca, Cb = X @ Ca, X @ Cb
+        Pan = Ca[:, :nalpha] @ Ca[:, :nalpha].T
+        Pbn = Cb[:, :nbeta] @ Cb[:, :nbeta].T
+        dP = float(max(np.max(np.abs(Pan - Pa)), np.max(np.abs(Pbn - Pb))))
+        Pa, Pb = Pan, Pbn
+        if it > 1 and abs(e_el - e_old) < e_conv and dP < d_conv:
+            break
+        e_old = e_el
+    else:
+        raise RuntimeError("oracle uhf: no convergence in %d iterations" % max_iter)
+    e_nuc = nuclear_repulsion(Z, R)
+    s2 = spin_contamination(S, Pa, Pb, nalpha, nbeta)
+    return {"E_elec": e_el, "E_nuc": e_nuc, "E_total": e_el + e_nuc, "Pa": Pa, "Pb": Pb, "Ca": Ca, "Cb": Cb,
+            "eps_a": ea, "eps_b": eb, "iterations": it, "S": S, "H": H, "S2": s2}
+
+
+def spin_contamination(S, Pa, Pb, nalpha: int, nbeta: int) -> float:
+    """<S^2> of a single determinant of nalpha alpha and nbeta beta spin orbitals (Szabo-Ostlund Sec. 3.8):
+    S_z (S_z + 1) + nbeta - sum_ij |<i alpha|j beta>|^2, the overlap sum being tr(P^a S P^b S)."""
+    sz = 0.5 * (nalpha - nbeta)
+    return sz * (sz + 1.0) + nbeta - float(np.sum((Pa @ S) * (Pb @ S).T))
+
+
 def fock_parts(J: np.ndarray, K: np.ndarray, D: np.ndarray):
     """G = J - K/2 and E2 = 1/2 sum_ij D_ij G_ij."""
     G = J - 0.5 * K
