@@ -69,13 +69,17 @@ typedef struct {
     long long max_items_per_launch;  /* > 0: cap on the work items of one class-kernel launch (longer classes are
                                         split into several launches, which bounds the duration of each kernel);
                                         0 (default): 2^20 */
+    double exchange_scale;  /* x, the weight of exchange: G = J - (x/2) K (closed shell), G^s = J - x K^s (spin
+                               densities).  1 (default) is Hartree-Fock; the exact-exchange fraction a0 of a hybrid
+                               functional (Sec. "Implementation details", B3LYP) gives its scaled exchange, the
+                               exchange-correlation functional itself not being part of this library.  Finite. */
 } uqc_fock_opts;
 
 #define UQC_MAX_CLASS_STATS 96
 
 /* Per-build statistics.  Counts are of canonical shell quartets (a>=b, c>=d, ab>=cd). */
 typedef struct {
-    double E2;                      /* 1/2 sum D G */
+    double E2;                      /* 1/2 sum D G (spin densities: 1/2 sum (D^a G^a + D^b G^b)) */
     long long quartets;             /* shell quartets computed (after screening) */
     long long quartets_screened;    /* canonical shell quartets skipped by screening */
     long long prim_quartets;        /* primitive quartets computed */
@@ -91,7 +95,7 @@ typedef struct {
 } uqc_stats;
 
 /* Fills *o with: tau = 1e-12, precision = UQC_FP64, fp64_bound = 1e-8, timing = 0, progress = NULL,
- * max_items_per_launch = 0. */
+ * max_items_per_launch = 0, exchange_scale = 1. */
 void uqc_fock_opts_default(uqc_fock_opts* o);
 
 /* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t the library launches on (NULL: the
@@ -138,6 +142,16 @@ uqc_status uqc_eri_blocks(uqc_basis* b, int n, const int* quartets, int precisio
 uqc_status uqc_fock_build(uqc_basis* b, const double* D, double* J, double* K, double* G, const uqc_fock_opts* opts,
                           uqc_stats* stats);
 
+/* Unrestricted Fock build (the paper's URHF, for open shells: the Pople-Nesbet equations of Szabo-Ostlund Sec. 3.8,
+ * Eq. (12) applied per spin): for the spin densities Da, Db (nbf*nbf, row-major, symmetric; Da + Db is the total
+ * density), J = J(Da + Db), Ka = K(Da), Kb = K(Db), Ga = J - x Ka, Gb = J - x Kb (x = opts->exchange_scale) and
+ * stats->E2 = 1/2 sum (Da Ga + Db Gb).  Da and Db and the outputs
+ * are all device pointers or all host pointers, as for uqc_fock_build; any of J, Ka, Kb, Ga, Gb may be NULL.  With
+ * Da = Db = D/2 the result is that of uqc_fock_build for D (Ga = Gb = G).
+ * Errors: UQC_E_ARG, UQC_E_NOT_SYMMETRIC, UQC_E_NOMEM, UQC_E_DEVICE. */
+uqc_status uqc_fock_build_uhf(uqc_basis* b, const double* Da, const double* Db, double* J, double* Ka, double* Kb,
+                              double* Ga, double* Gb, const uqc_fock_opts* opts, uqc_stats* stats);
+
 /* One-electron integrals over the basis (paper, Eq. (2)-(4)): overlap S, kinetic T and attraction V to point nuclei
  * of charges Z[natom] at R[natom][3] (bohr; host arrays, natom >= 0), each nbf*nbf row-major.  S, T, V are all
  * device pointers or all host pointers; any may be NULL.  Same basis conventions as the ERIs.
@@ -155,6 +169,9 @@ typedef struct {
     double d_conv;         /* max |F P S - S P F|, default 1e-8 */
     int diis_size;         /* DIIS subspace size (0: plain Roothaan iteration), default 8, at most 16 */
     uqc_fock_opts fock;    /* options of every Fock build (its progress callback is not used) */
+    double guess_mix;      /* uqc_scf_uhf: angle theta (radians) by which the alpha core guess' highest occupied
+                              (h) and lowest virtual (l) orbitals are rotated, h' = cos h + sin l,
+                              l' = -sin h + cos l, to break the symmetry of a closed-shell start; default 0 */
 } uqc_scf_opts;
 
 typedef struct {
@@ -165,9 +182,10 @@ typedef struct {
     double ms;             /* wall time of the call */
     double fock_ms;        /* of which in Fock builds */
     long long quartets;    /* shell quartets of one Fock build */
+    double s2;             /* <S^2> of the final determinant (0 for uqc_scf_rhf) */
 } uqc_scf_result;
 
-/* Fills *o with the defaults above and uqc_fock_opts_default() for the builds. */
+/* Fills *o with the defaults above (guess_mix = 0) and uqc_fock_opts_default() for the builds. */
 void uqc_scf_opts_default(uqc_scf_opts* o);
 
 /* Runs the SCF for nuclei Z[natom] at R[natom][3] (host arrays) with nocc doubly occupied orbitals (1 <= nocc <=
@@ -176,6 +194,17 @@ void uqc_scf_opts_default(uqc_scf_opts* o);
  * Errors: UQC_E_ARG, UQC_E_NOMEM, UQC_E_DEVICE (also when S is numerically singular). */
 uqc_status uqc_scf_rhf(uqc_basis* b, int natom, const double* Z, const double* R, int nocc, const uqc_scf_opts* o,
                        double* P, double* eps, uqc_scf_result* res);
+
+/* Unrestricted Hartree-Fock (the paper's URHF; Pople-Nesbet equations, Szabo-Ostlund Sec. 3.8) with nalpha and
+ * nbeta electrons (0 <= n <= nbf, nalpha + nbeta >= 1): core-Hamiltonian guess for both spins (the alpha one
+ * rotated by opts->guess_mix), P^s = C^s_occ C^s_occ^T, F^s = H + G^s from uqc_fock_build_uhf,
+ * E = sum (P^a + P^b) H + E2 + E_nuc, DIIS over the pair of errors F^s P^s S - S P^s F^s with one set of
+ * coefficients for both spins; res->error is the larger spin's max |F P S - S P F| and res->s2 = <S^2>.
+ * Pa, Pb (host, nbf*nbf) and eps_a, eps_b (host, nbf) receive the final spin densities and orbital energies if not
+ * NULL.  Same options, stopping rule and errors as uqc_scf_rhf. */
+uqc_status uqc_scf_uhf(uqc_basis* b, int natom, const double* Z, const double* R, int nalpha, int nbeta,
+                       const uqc_scf_opts* o, double* Pa, double* Pb, double* eps_a, double* eps_b,
+                       uqc_scf_result* res);
 
 /* Device Boys function, for verification: F_0..F_mmax (mmax <= 8) at n arguments T (host arrays; out is
  * n*(mmax+1), row-major).  precision UQC_FP64: tabulated Taylor grid + downward recursion (asymptotic form with

@@ -32,6 +32,7 @@ void uqc_fock_opts_default(uqc_fock_opts* o) {
     o->progress = nullptr;
     o->progress_user = nullptr;
     o->max_items_per_launch = 0;
+    o->exchange_scale = 1.0;
 }
 
 // ---------------------------------------------------------------------------------------------- Boys table
@@ -176,6 +177,7 @@ uqc_basis::~uqc_basis() {
     }
     for (auto& kv : plans) free_plan(kv.second);
     if (d_work) (void)hipFree(d_work);
+    if (d_uio) (void)hipFree(d_uio);
     if (d_shells) (void)hipFree(d_shells);
     if (d_nuc) (void)hipFree(d_nuc);
 }
@@ -528,10 +530,11 @@ uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* n
         }
         for (int i = 0; i < bn.np; ++i) B->qmax = std::max(B->qmax, bn.Q[i]);
     }
-    // workspace: f[nbf], D', J, K accumulators, E2 + symmetry scalars, host-pointer staging for D, J, K, G
+    // workspace: f[nbf], D', J, K accumulators, E2 + symmetry scalars, host-pointer staging for D, J, K, G, and the
+    // second spin's D' and K accumulator
     {
         const size_t N = B->nbf, NN = N * N;
-        const size_t bytes = (N + 3 * NN + 8 + 4 * NN) * sizeof(double);
+        const size_t bytes = (N + 3 * NN + 8 + 4 * NN + 2 * NN) * sizeof(double);
         if (hipMalloc(&B->d_work, bytes) != hipSuccess) {
             delete B;
             return uqc_fail(UQC_E_NOMEM, "basis: workspace allocation failed");
@@ -543,6 +546,8 @@ uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* n
         B->d_K = B->d_J + NN;
         B->d_scal = B->d_K + NN;
         B->d_io = B->d_scal + 8;
+        B->d_Dp2 = B->d_io + 4 * NN;
+        B->d_K2 = B->d_Dp2 + NN;
         B->work_bytes = bytes;
         if (hipMemcpy(B->d_f, B->fcomp.data(), N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
             delete B;
@@ -944,80 +949,122 @@ uqc_status uqc_eri_block(uqc_basis* B, int a, int b, int c, int d, int precision
 }
 
 // ---------------------------------------------------------------------------------------------- Fock build
-uqc_status uqc_fock_build(uqc_basis* B, const double* D, double* J, double* K, double* G, const uqc_fock_opts* opts,
-                          uqc_stats* stats) {
+// Fock build for one density (nspin = 1: out = {J, K, G}) or a pair of spin densities (nspin = 2:
+// out = {J, Ka, Kb, Ga, Gb}).  The second spin runs the class launches a second time over its own density, with the
+// J accumulator shared (J(Da) + J(Db) = J(Da + Db)) and the first spin's K accumulator set aside.
+static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, double* const* out,
+                           const uqc_fock_opts* opts, uqc_stats* stats, const char* name) {
     const auto t0 = std::chrono::steady_clock::now();
-    if (!B || !D) return uqc_fail(UQC_E_ARG, "uqc_fock_build: NULL basis or density");
+    const std::string nm(name);
     uqc_fock_opts o;
     uqc_fock_opts_default(&o);
     if (opts) o = *opts;
-    if (!(o.schwarz_tau >= 0) || !std::isfinite(o.schwarz_tau)) return uqc_fail(UQC_E_ARG, "uqc_fock_build: bad tau");
-    if (o.precision != UQC_FP64 && o.precision != UQC_MIXED)
-        return uqc_fail(UQC_E_ARG, "uqc_fock_build: bad precision");
-    if (o.precision == UQC_MIXED && !(o.fp64_bound >= 0)) return uqc_fail(UQC_E_ARG, "uqc_fock_build: bad fp64_bound");
-    if (o.max_items_per_launch < 0) return uqc_fail(UQC_E_ARG, "uqc_fock_build: negative max_items_per_launch");
+    if (!(o.schwarz_tau >= 0) || !std::isfinite(o.schwarz_tau)) return uqc_fail(UQC_E_ARG, nm + ": bad tau");
+    if (o.precision != UQC_FP64 && o.precision != UQC_MIXED) return uqc_fail(UQC_E_ARG, nm + ": bad precision");
+    if (o.precision == UQC_MIXED && !(o.fp64_bound >= 0)) return uqc_fail(UQC_E_ARG, nm + ": bad fp64_bound");
+    if (o.max_items_per_launch < 0) return uqc_fail(UQC_E_ARG, nm + ": negative max_items_per_launch");
+    if (!std::isfinite(o.exchange_scale)) return uqc_fail(UQC_E_ARG, nm + ": exchange_scale is not finite");
     const long long max_items = o.max_items_per_launch > 0 ? o.max_items_per_launch : kMaxItemsPerLaunch;
+    const int nout = nspin == 1 ? 3 : 5;
     uqc_ctx* ctx = B->ctx;
     UQC_HIP(hipSetDevice(ctx->device));
-    const bool dev = uqc::is_device_ptr(D);
-    for (const void* p : {(const void*)J, (const void*)K, (const void*)G})
-        if (p && uqc::is_device_ptr(p) != dev)
-            return uqc_fail(UQC_E_ARG, "uqc_fock_build: mix of host and device pointers");
+    const bool dev = uqc::is_device_ptr(Din[0]);
+    if (nspin == 2 && uqc::is_device_ptr(Din[1]) != dev)
+        return uqc_fail(UQC_E_ARG, nm + ": mix of host and device pointers");
+    for (int i = 0; i < nout; ++i)
+        if (out[i] && uqc::is_device_ptr(out[i]) != dev)
+            return uqc_fail(UQC_E_ARG, nm + ": mix of host and device pointers");
     uqc_status st = UQC_OK;
     Plan* plan = get_plan(B, o.schwarz_tau, o.precision, o.fp64_bound, &st);
     if (!plan) return st;
     const size_t N = B->nbf, NN = N * N;
     hipStream_t s = ctx->stream;
-    const double* Dd = D;
-    double *Jd = J, *Kd = K, *Gd = G;
+    const double* Dd[2] = {Din[0], nspin == 2 ? Din[1] : nullptr};
+    double* Od[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    for (int i = 0; i < nout; ++i) Od[i] = out[i];
     if (!dev) {
+        // staging: the densities, then one slot per output
         double* io = B->d_io;
-        UQC_HIP(hipMemcpyAsync(io, D, NN * sizeof(double), hipMemcpyHostToDevice, s));
-        Dd = io;
-        Jd = J ? io + NN : nullptr;
-        Kd = K ? io + 2 * NN : nullptr;
-        Gd = G ? io + 3 * NN : nullptr;
+        if (nspin == 2) {
+            if (!B->d_uio && hipMalloc(&B->d_uio, 7 * NN * sizeof(double)) != hipSuccess) {
+                B->d_uio = nullptr;
+                return uqc_fail(UQC_E_NOMEM, nm + ": staging allocation failed");
+            }
+            io = B->d_uio;
+        }
+        for (int k = 0; k < nspin; ++k) {
+            UQC_HIP(hipMemcpyAsync(io + k * NN, Din[k], NN * sizeof(double), hipMemcpyHostToDevice, s));
+            Dd[k] = io + k * NN;
+        }
+        for (int i = 0; i < nout; ++i) Od[i] = out[i] ? io + (nspin + i) * NN : nullptr;
     }
     unsigned long long* maxbits = (unsigned long long*)(B->d_scal + 1);
     UQC_HIP(launch_zero(B->d_scal, 8, s));
-    UQC_HIP(launch_prepare(Dd, B->d_f, B->d_Dp, (int)N, maxbits, s));
-    unsigned long long hb[2] = {0, 0};
+    UQC_HIP(launch_prepare(Dd[0], B->d_f, B->d_Dp, (int)N, maxbits, s));
+    if (nspin == 2) UQC_HIP(launch_prepare(Dd[1], B->d_f, B->d_Dp2, (int)N, maxbits + 2, s));
+    unsigned long long hb[4] = {0, 0, 0, 0};
     UQC_HIP(hipMemcpyAsync(hb, maxbits, sizeof(hb), hipMemcpyDeviceToHost, s));
     UQC_HIP(hipStreamSynchronize(s));
-    double md, ma;
-    std::memcpy(&md, &hb[0], 8);
-    std::memcpy(&ma, &hb[1], 8);
-    if (!(md <= 1e-12 * ma)) return uqc_fail(UQC_E_NOT_SYMMETRIC, "uqc_fock_build: density is not symmetric (or not finite)");
+    for (int k = 0; k < nspin; ++k) {
+        double md, ma;
+        std::memcpy(&md, &hb[2 * k], 8);
+        std::memcpy(&ma, &hb[2 * k + 1], 8);
+        if (!(md <= 1e-12 * ma))
+            return uqc_fail(UQC_E_NOT_SYMMETRIC, nm + ": density is not symmetric (or not finite)");
+    }
     UQC_HIP(launch_zero(B->d_J, 2 * NN, s));
-    if (plan->ntasks) UQC_HIP(launch_zero((double*)plan->d_count, (size_t)plan->ntasks, s));
     const bool timing = o.timing != 0;
-    size_t ev = 0;
-    for (auto& g : plan->groups) {
-        if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, ev++), s));
-        int la, lb, lc, ld;
-        class_ls(g.cls, &la, &lb, &lc, &ld);
-        const int cid = la * 1000 + lb * 100 + lc * 10 + ld + (g.mixed ? 10000 : 0);
-        for (long long i0 = 0; i0 < g.nitems; i0 += max_items) {
-            const long long n = std::min(max_items, g.nitems - i0);
-            UQC_HIP(launch_digest(g.cls, g.mixed, g.d_tasks, g.d_begin, g.ntask, i0, n, ctx->boys64, ctx->boys32, s));
-            if (o.progress) {
-                UQC_HIP(hipStreamSynchronize(s));
-                o.progress(o.progress_user, cid, i0 + n, g.nitems);
+    std::vector<double> cls_ms(plan->groups.size(), 0.0);
+    auto pass = [&]() -> uqc_status {
+        if (plan->ntasks) UQC_HIP(launch_zero((double*)plan->d_count, (size_t)plan->ntasks, s));
+        size_t ev = 0;
+        for (auto& g : plan->groups) {
+            if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, ev++), s));
+            int la, lb, lc, ld;
+            class_ls(g.cls, &la, &lb, &lc, &ld);
+            const int cid = la * 1000 + lb * 100 + lc * 10 + ld + (g.mixed ? 10000 : 0);
+            for (long long i0 = 0; i0 < g.nitems; i0 += max_items) {
+                const long long n = std::min(max_items, g.nitems - i0);
+                UQC_HIP(launch_digest(g.cls, g.mixed, g.d_tasks, g.d_begin, g.ntask, i0, n, ctx->boys64, ctx->boys32,
+                                      s));
+                if (o.progress) {
+                    UQC_HIP(hipStreamSynchronize(s));
+                    o.progress(o.progress_user, cid, i0 + n, g.nitems);
+                }
+            }
+            if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, ev++), s));
+        }
+        if (timing) {
+            UQC_HIP(hipStreamSynchronize(s));
+            for (size_t gi = 0; gi < plan->groups.size(); ++gi) {
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, ctx->events[2 * gi], ctx->events[2 * gi + 1]);
+                cls_ms[gi] += ms;
             }
         }
-        if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, ev++), s));
+        return UQC_OK;
+    };
+    if ((st = pass()) != UQC_OK) return st;
+    if (nspin == 2) {
+        // first spin's K accumulator aside, second spin's density in place of the first
+        UQC_HIP(hipMemcpyAsync(B->d_K2, B->d_K, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+        UQC_HIP(hipMemcpyAsync(B->d_Dp, B->d_Dp2, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
+        UQC_HIP(launch_zero(B->d_K, NN, s));
+        if ((st = pass()) != UQC_OK) return st;
+        UQC_HIP(launch_finalize_uhf(Dd[0], Dd[1], B->d_J, B->d_K2, B->d_K, B->d_f, o.exchange_scale, Od[0], Od[1],
+                                    Od[2], Od[3], Od[4], B->d_scal, (int)N, s));
+    } else {
+        UQC_HIP(launch_finalize(Dd[0], B->d_J, B->d_K, B->d_f, Od[0], Od[1], Od[2], o.exchange_scale, B->d_scal,
+                                (int)N, s));
     }
-    UQC_HIP(launch_finalize(Dd, B->d_J, B->d_K, B->d_f, Jd, Kd, Gd, B->d_scal, (int)N, s));
     double E2 = 0.0;
     UQC_HIP(hipMemcpyAsync(&E2, B->d_scal, sizeof(double), hipMemcpyDeviceToHost, s));
     if (plan->ntasks)
         UQC_HIP(hipMemcpyAsync(plan->h_count.data(), plan->d_count, plan->ntasks * sizeof(unsigned long long),
                                hipMemcpyDeviceToHost, s));
-    if (!dev) {
-        if (J) UQC_HIP(hipMemcpyAsync(J, Jd, NN * sizeof(double), hipMemcpyDeviceToHost, s));
-        if (K) UQC_HIP(hipMemcpyAsync(K, Kd, NN * sizeof(double), hipMemcpyDeviceToHost, s));
-        if (G) UQC_HIP(hipMemcpyAsync(G, Gd, NN * sizeof(double), hipMemcpyDeviceToHost, s));
-    }
+    if (!dev)
+        for (int i = 0; i < nout; ++i)
+            if (out[i]) UQC_HIP(hipMemcpyAsync(out[i], Od[i], NN * sizeof(double), hipMemcpyDeviceToHost, s));
     UQC_HIP(hipStreamSynchronize(s));
     plan_account(*plan);
     if (stats) {
@@ -1029,18 +1076,15 @@ uqc_status uqc_fock_build(uqc_basis* B, const double* D, double* J, double* K, d
         stats->fp64_quartets = plan->fp64_quartets;
         stats->flops = plan->flops;
         if (timing) {
-            size_t e = 0;
             int nc = 0;
-            for (auto& g : plan->groups) {
-                float ms = 0.f;
-                (void)hipEventElapsedTime(&ms, ctx->events[e], ctx->events[e + 1]);
-                e += 2;
-                stats->eri_ms += ms;
+            for (size_t gi = 0; gi < plan->groups.size(); ++gi) {
+                const auto& g = plan->groups[gi];
+                stats->eri_ms += cls_ms[gi];
                 if (nc < UQC_MAX_CLASS_STATS) {
                     int la, lb, lc, ld;
                     class_ls(g.cls, &la, &lb, &lc, &ld);
                     stats->class_id[nc] = la * 1000 + lb * 100 + lc * 10 + ld + (g.mixed ? 10000 : 0);
-                    stats->class_ms[nc] = ms;
+                    stats->class_ms[nc] = cls_ms[gi];
                     stats->class_flops[nc] = g.flops;
                     stats->class_quartets[nc] = g.quartets;
                     ++nc;
@@ -1051,6 +1095,22 @@ uqc_status uqc_fock_build(uqc_basis* B, const double* D, double* J, double* K, d
         stats->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return UQC_OK;
+}
+
+uqc_status uqc_fock_build(uqc_basis* B, const double* D, double* J, double* K, double* G, const uqc_fock_opts* opts,
+                          uqc_stats* stats) {
+    if (!B || !D) return uqc_fail(UQC_E_ARG, "uqc_fock_build: NULL basis or density");
+    const double* Din[1] = {D};
+    double* out[3] = {J, K, G};
+    return fock_run(B, 1, Din, out, opts, stats, "uqc_fock_build");
+}
+
+uqc_status uqc_fock_build_uhf(uqc_basis* B, const double* Da, const double* Db, double* J, double* Ka, double* Kb,
+                              double* Ga, double* Gb, const uqc_fock_opts* opts, uqc_stats* stats) {
+    if (!B || !Da || !Db) return uqc_fail(UQC_E_ARG, "uqc_fock_build_uhf: NULL basis or density");
+    const double* Din[2] = {Da, Db};
+    double* out[5] = {J, Ka, Kb, Ga, Gb};
+    return fock_run(B, 2, Din, out, opts, stats, "uqc_fock_build_uhf");
 }
 
 // ---------------------------------------------------------------------------------------------- Boys check

@@ -103,6 +103,8 @@ struct uqc_basis {
     void* d_work = nullptr;
     size_t work_bytes = 0;
     double *d_f = nullptr, *d_Dp = nullptr, *d_J = nullptr, *d_K = nullptr, *d_scal = nullptr, *d_io = nullptr;
+    double *d_Dp2 = nullptr, *d_K2 = nullptr;  // second spin density D' and K accumulator (spin-density builds)
+    double* d_uio = nullptr;                     // host-pointer staging of spin-density builds (7 nbf^2, on first use)
     // one-electron integrals: shell table and per-pair-class shell-pair lists (uploaded on first use), nuclei
     void* d_shells = nullptr;
     uqc::ShellsDev shells_dev{};

@@ -109,7 +109,12 @@ hipError_t launch_add(const double* A, const double* B, double* C, size_t n, hip
 hipError_t launch_scale_cols(const double* U, const double* w, double* W, int N, hipStream_t s);  // W = U diag(w)
 hipError_t launch_antisym(const double* M, double* E, int N, hipStream_t s);                  // E = M - M^T
 hipError_t launch_finalize(const double* D, const double* Jacc, const double* Kacc, const double* f, double* J,
-                           double* K, double* G, double* E2, int nbf, hipStream_t s);
+                           double* K, double* G, double xs, double* E2, int nbf, hipStream_t s);
+// Spin densities: J = sym(Jacc), K^s = sym(K^s acc), G^s = J - xs K^s, E2 += 1/2 sum (Da Ga + Db Gb); any output
+// may be null.
+hipError_t launch_finalize_uhf(const double* Da, const double* Db, const double* Jacc, const double* Kaacc,
+                               const double* Kbacc, const double* f, double xs, double* J, double* Ka, double* Kb,
+                               double* Ga, double* Gb, double* E2, int nbf, hipStream_t s);
 hipError_t launch_boys(int prec, int mmax, int n, const double* T, double* out, const double* boys64,
                        const float* boys32, hipStream_t s);
 hipError_t launch_perturb(double* D, const double* R, int nbf, int ncol, double eps, double trace0, double* work,

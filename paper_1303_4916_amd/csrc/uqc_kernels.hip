@@ -93,12 +93,14 @@ __global__ __launch_bounds__(kBlock) void k_zero(double* __restrict__ p, size_t 
     for (size_t x = (size_t)blockIdx.x * kBlock + threadIdx.x; x < n; x += (size_t)gridDim.x * kBlock) p[x] = 0.0;
 }
 
-// J = f_i f_j (Jacc_ij + Jacc_ji), K likewise, G = J - K/2, E2 = 1/2 sum D_ij G_ij.
+// J = f_i f_j (Jacc_ij + Jacc_ji), K likewise, G = J - (xs/2) K, E2 = 1/2 sum D_ij G_ij.
 __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ D, const double* __restrict__ Jacc,
                                                      const double* __restrict__ Kacc, const double* __restrict__ f,
                                                      double* __restrict__ J, double* __restrict__ K,
-                                                     double* __restrict__ G, double* __restrict__ E2, int N) {
+                                                     double* __restrict__ G, double xs, double* __restrict__ E2,
+                                                     int N) {
     const long long NN = (long long)N * N;
+    const double hx = 0.5 * xs;
     double e = 0.0;
     for (long long x = (long long)blockIdx.x * kBlock + threadIdx.x; x < NN; x += (long long)gridDim.x * kBlock) {
         const int i = (int)(x / N), j = (int)(x % N);
@@ -106,11 +108,42 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
         const double ff = f[i] * f[j];
         const double jv = ff * (Jacc[x] + Jacc[t]);
         const double kv = ff * (Kacc[x] + Kacc[t]);
-        const double gv = jv - 0.5 * kv;
+        const double gv = jv - hx * kv;
         if (J) J[x] = jv;
         if (K) K[x] = kv;
         if (G) G[x] = gv;
         e = fma(D[x], gv, e);
+    }
+    e = wave_sum(e);
+    if ((threadIdx.x % kWave) == 0) atomic_add(E2, 0.5 * e);
+}
+
+// Spin densities: J from the shared accumulator, K^a and K^b from their own, G^s = J - xs K^s,
+// E2 = 1/2 sum (Da_ij Ga_ij + Db_ij Gb_ij).
+__global__ __launch_bounds__(kBlock) void k_finalize_uhf(const double* __restrict__ Da, const double* __restrict__ Db,
+                                                         const double* __restrict__ Jacc,
+                                                         const double* __restrict__ Kaacc,
+                                                         const double* __restrict__ Kbacc,
+                                                         const double* __restrict__ f, double xs,
+                                                         double* __restrict__ J, double* __restrict__ Ka,
+                                                         double* __restrict__ Kb, double* __restrict__ Ga,
+                                                         double* __restrict__ Gb, double* __restrict__ E2, int N) {
+    const long long NN = (long long)N * N;
+    double e = 0.0;
+    for (long long x = (long long)blockIdx.x * kBlock + threadIdx.x; x < NN; x += (long long)gridDim.x * kBlock) {
+        const int i = (int)(x / N), j = (int)(x % N);
+        const size_t t = (size_t)j * N + i;
+        const double ff = f[i] * f[j];
+        const double jv = ff * (Jacc[x] + Jacc[t]);
+        const double ka = ff * (Kaacc[x] + Kaacc[t]);
+        const double kb = ff * (Kbacc[x] + Kbacc[t]);
+        const double ga = jv - xs * ka, gb = jv - xs * kb;
+        if (J) J[x] = jv;
+        if (Ka) Ka[x] = ka;
+        if (Kb) Kb[x] = kb;
+        if (Ga) Ga[x] = ga;
+        if (Gb) Gb[x] = gb;
+        e = fma(Da[x], ga, fma(Db[x], gb, e));
     }
     e = wave_sum(e);
     if ((threadIdx.x % kWave) == 0) atomic_add(E2, 0.5 * e);
@@ -174,9 +207,17 @@ hipError_t launch_zero(double* p, size_t n, hipStream_t s) {
 }
 
 hipError_t launch_finalize(const double* D, const double* Jacc, const double* Kacc, const double* f, double* J,
-                           double* K, double* G, double* E2, int nbf, hipStream_t s) {
+                           double* K, double* G, double xs, double* E2, int nbf, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(grid_for((long long)nbf * nbf)), dim3(kBlock), 0, s, D, Jacc, Kacc, f, J, K,
-                       G, E2, nbf);
+                       G, xs, E2, nbf);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_uhf(const double* Da, const double* Db, const double* Jacc, const double* Kaacc,
+                               const double* Kbacc, const double* f, double xs, double* J, double* Ka, double* Kb,
+                               double* Ga, double* Gb, double* E2, int nbf, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_uhf, dim3(grid_for((long long)nbf * nbf)), dim3(kBlock), 0, s, Da, Db, Jacc, Kaacc,
+                       Kbacc, f, xs, J, Ka, Kb, Ga, Gb, E2, nbf);
     return hipGetLastError();
 }
 

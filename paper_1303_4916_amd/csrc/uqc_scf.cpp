@@ -1,10 +1,13 @@
-// One-electron integrals (Eq. (2)-(4)) and the restricted closed-shell Hartree-Fock driver around the Fock build.
+// One-electron integrals (Eq. (2)-(4)) and the Hartree-Fock drivers around the Fock build: restricted closed shell
+// and unrestricted (the paper's RHF and URHF).
 //
-// SCF (Szabo-Ostlund closed-shell equations, which the paper states it follows; Pulay DIIS as in the paper's SCF):
+// SCF (Szabo-Ostlund closed-shell and Pople-Nesbet equations, which the paper states it follows; Pulay DIIS as in
+// the paper's SCF):
 //   X = S^{-1/2} (symmetric orthogonalisation), core-Hamiltonian guess F_0 = H = T + V;
-//   per iteration: F' = X F X, F' C' = C' eps, C = X C', P = 2 C_occ C_occ^T, F = H + G(P) with G from
-//   uqc_fock_build, E = sum P H + E2 (= 1/2 tr P (H + F)), error e = F P S - S P F;
-//   DIIS: F_extrapolated = sum_i c_i F_i with sum_i c_i = 1 minimising |sum_i c_i e_i|.
+//   per iteration: F' = X F X, F' C' = C' eps, C = X C', closed shell P = 2 C_occ C_occ^T and F = H + G(P) from
+//   uqc_fock_build; unrestricted P^s = C^s_occ C^s_occ^T and F^s = H + G^s from uqc_fock_build_uhf;
+//   E = sum_s P^s H + E2, error e^s = F^s P^s S - S P^s F^s;
+//   DIIS: F^s_extrapolated = sum_i c_i F^s_i with sum_i c_i = 1 minimising sum_s |sum_i c_i e^s_i|^2.
 // Matrices live on the device; products and eigendecompositions use rocBLAS / rocSOLVER (column-major; every
 // matrix handed to them is symmetric except the eigenvector blocks, which stay internal).
 #include "uqc_api_internal.h"
@@ -165,6 +168,7 @@ void uqc_scf_opts_default(uqc_scf_opts* o) {
     o->d_conv = 1e-8;
     o->diis_size = 8;
     uqc_fock_opts_default(&o->fock);
+    o->guess_mix = 0.0;
 }
 
 // Solves the (m+1) x (m+1) DIIS system [B -1; -1 0] [c; lambda] = [0; -1] by Gaussian elimination with partial
@@ -202,18 +206,21 @@ static bool diis_solve(const std::vector<double>& Bm, int m, std::vector<double>
     return true;
 }
 
-uqc_status uqc_scf_rhf(uqc_basis* B, int natom, const double* Z, const double* R, int nocc, const uqc_scf_opts* opts,
-                       double* Pout, double* eps_out, uqc_scf_result* res) {
+// Closed shell (nspin = 1: one density P = 2 C_occ C_occ^T, G from uqc_fock_build) or spin-unrestricted (nspin = 2:
+// P^s = C^s_occ C^s_occ^T, G^s from uqc_fock_build_uhf).  nocc[s] occupied orbitals per spin.
+static uqc_status scf_run(uqc_basis* B, int natom, const double* Z, const double* R, int nspin, const int* nocc,
+                          const uqc_scf_opts* opts, double* const* Pout, double* const* eps_out, uqc_scf_result* res,
+                          const char* name) {
     const auto t0 = std::chrono::steady_clock::now();
-    if (!B) return uqc_fail(UQC_E_ARG, "uqc_scf_rhf: NULL basis");
+    const std::string nm(name);
     const int N = B->nbf;
-    if (nocc < 1 || nocc > N) return uqc_fail(UQC_E_ARG, "uqc_scf_rhf: nocc outside 1..nbf");
-    if (natom < 0 || (natom > 0 && (!Z || !R))) return uqc_fail(UQC_E_ARG, "uqc_scf_rhf: bad nuclei");
+    if (natom < 0 || (natom > 0 && (!Z || !R))) return uqc_fail(UQC_E_ARG, nm + ": bad nuclei");
     uqc_scf_opts o;
     uqc_scf_opts_default(&o);
     if (opts) o = *opts;
-    if (o.max_iter < 1 || o.diis_size < 0 || o.diis_size > 16 || !(o.e_conv > 0) || !(o.d_conv > 0))
-        return uqc_fail(UQC_E_ARG, "uqc_scf_rhf: bad options");
+    if (o.max_iter < 1 || o.diis_size < 0 || o.diis_size > 16 || !(o.e_conv > 0) || !(o.d_conv > 0) ||
+        !std::isfinite(o.guess_mix))
+        return uqc_fail(UQC_E_ARG, nm + ": bad options");
     o.fock.progress = nullptr;
     o.fock.timing = 0;
     uqc_ctx* ctx = B->ctx;
@@ -230,27 +237,32 @@ uqc_status uqc_scf_rhf(uqc_basis* B, int natom, const double* Z, const double* R
 
     const size_t NN = (size_t)N * N;
     const int m_max = o.diis_size;
-    // S H X P F G T1 M E Fx C | DIIS F_i, e_i | w eig D E info
-    const size_t nmat = 11 + 2 * (size_t)m_max;
+    // shared: S H X T1 M | per spin: P F G E Fx C | DIIS per slot and spin: F_i, e_i | w, work, info
+    const size_t nmat = 5 + 6 * (size_t)nspin + 2 * (size_t)nspin * m_max;
     double* mem = nullptr;
     if (hipMalloc(&mem, (nmat * NN + 3 * (size_t)N + 8) * sizeof(double)) != hipSuccess)
-        return uqc_fail(UQC_E_NOMEM, "uqc_scf_rhf: workspace allocation failed");
+        return uqc_fail(UQC_E_NOMEM, nm + ": workspace allocation failed");
     struct Free {
         double* p;
         ~Free() { if (p) (void)hipFree(p); }
     } guard{mem};
-    double *S = mem, *H = S + NN, *X = H + NN, *P = X + NN, *F = P + NN, *G = F + NN, *T1 = G + NN, *M = T1 + NN,
-           *E = M + NN, *Fx = E + NN, *C = Fx + NN;
-    double* Fs = C + NN;                 // DIIS Fock matrices [m_max]
-    double* Es = Fs + (size_t)m_max * NN;  // DIIS error matrices [m_max]
-    double* w = Es + (size_t)m_max * NN;  // eigenvalues [N]
-    double* offd = w + N;                  // work [N]
+    double *S = mem, *H = S + NN, *X = H + NN, *T1 = X + NN, *M = T1 + NN;
+    double *P[2], *F[2], *G[2], *E[2], *Fx[2], *C[2];
+    double* q = M + NN;
+    for (int sp = 0; sp < nspin; ++sp) {
+        P[sp] = q; F[sp] = q + NN; G[sp] = q + 2 * NN; E[sp] = q + 3 * NN; Fx[sp] = q + 4 * NN; C[sp] = q + 5 * NN;
+        q += 6 * NN;
+    }
+    auto Fs = [&](int slot, int sp) { return q + ((size_t)slot * nspin + sp) * NN; };                 // DIIS Fock
+    auto Es = [&](int slot, int sp) { return q + ((size_t)(m_max + slot) * nspin + sp) * NN; };      // DIIS error
+    double* w = q + 2 * (size_t)m_max * nspin * NN;  // eigenvalues [N]
+    double* offd = w + N;                            // work [N]
     rocblas_int* info = (rocblas_int*)(offd + N);
 
-    // one-electron part: S, H = T + V (T in M, V in E as scratch)
-    uqc_status st = one_electron_device(B, natom, Z, R, S, M, E);
+    // one-electron part: S, H = T + V (T in M, V in T1 as scratch)
+    uqc_status st = one_electron_device(B, natom, Z, R, S, M, T1);
     if (st != UQC_OK) return st;
-    UQC_HIP(launch_add(M, E, H, NN, s));
+    UQC_HIP(launch_add(M, T1, H, NN, s));
     double E_nuc = 0.0;
     for (int a = 0; a < natom; ++a)
         for (int b = 0; b < a; ++b) {
@@ -263,10 +275,11 @@ uqc_status uqc_scf_rhf(uqc_basis* B, int natom, const double* Z, const double* R
         rocblas_int hinfo = 0;
         UQC_HIP(hipMemcpyAsync(&hinfo, info, sizeof(hinfo), hipMemcpyDeviceToHost, s));
         UQC_HIP(hipStreamSynchronize(s));
-        if (hinfo != 0) return uqc_fail(UQC_E_DEVICE, "uqc_scf_rhf: eigendecomposition did not converge");
+        if (hinfo != 0) return uqc_fail(UQC_E_DEVICE, nm + ": eigendecomposition did not converge");
         return UQC_OK;
     };
-    const double one = 1.0, zero = 0.0, two = 2.0;
+    const double one = 1.0, zero = 0.0;
+    const double occ = nspin == 1 ? 2.0 : 1.0;
 
     // X = U diag(s^-1/2) U^T
     UQC_HIP(hipMemcpyAsync(T1, S, NN * 8, hipMemcpyDeviceToDevice, s));
@@ -274,29 +287,45 @@ uqc_status uqc_scf_rhf(uqc_basis* B, int natom, const double* Z, const double* R
     std::vector<double> hw(N);
     UQC_HIP(hipMemcpyAsync(hw.data(), w, N * 8, hipMemcpyDeviceToHost, s));
     UQC_HIP(hipStreamSynchronize(s));
-    if (!(hw[0] > 1e-10 * hw[N - 1])) return uqc_fail(UQC_E_DEVICE, "uqc_scf_rhf: overlap matrix is numerically singular");
+    if (!(hw[0] > 1e-10 * hw[N - 1])) return uqc_fail(UQC_E_DEVICE, nm + ": overlap matrix is numerically singular");
     for (int i = 0; i < N; ++i) hw[i] = 1.0 / std::sqrt(hw[i]);
     UQC_HIP(hipMemcpyAsync(w, hw.data(), N * 8, hipMemcpyHostToDevice, s));
     UQC_HIP(launch_scale_cols(T1, w, M, N, s));
     UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, N, N, N, &one, M, N, T1, N, &zero, X,
                            N));
 
-    // density from a Fock matrix Fin: P = 2 C_occ C_occ^T, C = X C', X Fin X C' = C' eps
-    auto density = [&](const double* Fin) -> uqc_status {
+    // orbitals of Fin in C (X Fin X C' = C' eps, C = X C'; eigenvalues in w)
+    auto orbitals = [&](const double* Fin, double* Cout) -> uqc_status {
         UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &one, Fin, N, X, N, &zero, T1,
                                N));
         UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &one, X, N, T1, N, &zero, M,
                                N));
         uqc_status s2 = eig(M);
         if (s2 != UQC_OK) return s2;
-        UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &one, X, N, M, N, &zero, C,
+        UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &one, X, N, M, N, &zero, Cout,
                                N));
-        UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, N, N, nocc, &two, C, N, C, N,
-                               &zero, P, N));
+        return UQC_OK;
+    };
+    // density of spin sp from its orbitals: P = occ C_occ C_occ^T
+    auto density = [&](int sp) -> uqc_status {
+        if (nocc[sp] == 0) {
+            UQC_HIP(launch_zero(P[sp], NN, s));
+            return UQC_OK;
+        }
+        UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, N, N, nocc[sp], &occ, C[sp], N,
+                               C[sp], N, &zero, P[sp], N));
         return UQC_OK;
     };
 
-    if ((st = density(H)) != UQC_OK) return st;
+    // core-Hamiltonian guess; for spin densities the alpha highest occupied / lowest virtual pair is rotated
+    for (int sp = 0; sp < nspin; ++sp) {
+        if ((st = orbitals(H, C[sp])) != UQC_OK) return st;
+        if (nspin == 2 && sp == 0 && o.guess_mix != 0.0 && nocc[0] > 0 && nocc[0] < N) {
+            const double c = std::cos(o.guess_mix), sn = std::sin(o.guess_mix);
+            UQC_BLAS(rocblas_drot(h, N, C[0] + (size_t)(nocc[0] - 1) * N, 1, C[0] + (size_t)nocc[0] * N, 1, &c, &sn));
+        }
+        if ((st = density(sp)) != UQC_OK) return st;
+    }
     double e_prev = 0.0, E_elec = 0.0, err = 0.0, fock_ms = 0.0;
     int it = 0, nstore = 0, head = 0;
     bool converged = false;
@@ -306,41 +335,56 @@ uqc_status uqc_scf_rhf(uqc_basis* B, int natom, const double* Z, const double* R
         ++it;
         uqc_stats fs;
         const auto tf = std::chrono::steady_clock::now();
-        if ((st = uqc_fock_build(B, P, nullptr, nullptr, G, &o.fock, &fs)) != UQC_OK) return st;
+        if (nspin == 1)
+            st = uqc_fock_build(B, P[0], nullptr, nullptr, G[0], &o.fock, &fs);
+        else
+            st = uqc_fock_build_uhf(B, P[0], P[1], nullptr, nullptr, nullptr, G[0], G[1], &o.fock, &fs);
+        if (st != UQC_OK) return st;
         fock_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
         quartets = fs.quartets;
-        UQC_HIP(launch_add(H, G, F, NN, s));
-        double ph = 0.0;
-        UQC_BLAS(rocblas_ddot(h, (rocblas_int)NN, P, 1, H, 1, &ph));
-        E_elec = ph + fs.E2;
-        // error F P S - S P F
-        UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &one, F, N, P, N, &zero, T1,
-                               N));
-        UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &one, T1, N, S, N, &zero, M,
-                               N));
-        UQC_HIP(launch_antisym(M, E, N, s));
-        rocblas_int imax = 1;
-        UQC_BLAS(rocblas_idamax(h, (rocblas_int)NN, E, 1, &imax));
-        UQC_HIP(hipMemcpyAsync(&err, E + (imax - 1), 8, hipMemcpyDeviceToHost, s));
-        UQC_HIP(hipStreamSynchronize(s));
-        err = std::fabs(err);
+        E_elec = fs.E2;
+        err = 0.0;
+        for (int sp = 0; sp < nspin; ++sp) {
+            UQC_HIP(launch_add(H, G[sp], F[sp], NN, s));
+            double ph = 0.0;
+            UQC_BLAS(rocblas_ddot(h, (rocblas_int)NN, P[sp], 1, H, 1, &ph));
+            E_elec += ph;
+            // error F P S - S P F
+            UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &one, F[sp], N, P[sp], N,
+                                   &zero, T1, N));
+            UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &one, T1, N, S, N, &zero,
+                                   M, N));
+            UQC_HIP(launch_antisym(M, E[sp], N, s));
+            rocblas_int imax = 1;
+            UQC_BLAS(rocblas_idamax(h, (rocblas_int)NN, E[sp], 1, &imax));
+            double e1 = 0.0;
+            UQC_HIP(hipMemcpyAsync(&e1, E[sp] + (imax - 1), 8, hipMemcpyDeviceToHost, s));
+            UQC_HIP(hipStreamSynchronize(s));
+            err = std::max(err, std::fabs(e1));
+        }
         if (it > 1 && std::fabs(E_elec - e_prev) < o.e_conv && err < o.d_conv) {
             converged = true;
             break;
         }
         if (it == o.max_iter) break;  // P, F and E stay those of the last build
         e_prev = E_elec;
-        const double* Fnext = F;
+        const double* Fnext[2] = {F[0], nspin == 2 ? F[1] : nullptr};
         if (m_max > 0) {
-            // store (F, e) in the ring, update the error overlaps, extrapolate
+            // store (F, e) of every spin in the ring, update the error overlaps, extrapolate with one set of weights
             const int slot = head;
             head = (head + 1) % m_max;
             nstore = std::min(nstore + 1, m_max);
-            UQC_HIP(hipMemcpyAsync(Fs + (size_t)slot * NN, F, NN * 8, hipMemcpyDeviceToDevice, s));
-            UQC_HIP(hipMemcpyAsync(Es + (size_t)slot * NN, E, NN * 8, hipMemcpyDeviceToDevice, s));
+            for (int sp = 0; sp < nspin; ++sp) {
+                UQC_HIP(hipMemcpyAsync(Fs(slot, sp), F[sp], NN * 8, hipMemcpyDeviceToDevice, s));
+                UQC_HIP(hipMemcpyAsync(Es(slot, sp), E[sp], NN * 8, hipMemcpyDeviceToDevice, s));
+            }
             for (int j = 0; j < nstore; ++j) {
                 double d = 0.0;
-                UQC_BLAS(rocblas_ddot(h, (rocblas_int)NN, Es + (size_t)slot * NN, 1, Es + (size_t)j * NN, 1, &d));
+                for (int sp = 0; sp < nspin; ++sp) {
+                    double d1 = 0.0;
+                    UQC_BLAS(rocblas_ddot(h, (rocblas_int)NN, Es(slot, sp), 1, Es(j, sp), 1, &d1));
+                    d += d1;
+                }
                 Bm[slot * m_max + j] = Bm[j * m_max + slot] = d;
             }
             if (nstore >= 2) {
@@ -348,27 +392,40 @@ uqc_status uqc_scf_rhf(uqc_basis* B, int natom, const double* Z, const double* R
                 for (int i = 0; i < nstore; ++i)
                     for (int j = 0; j < nstore; ++j) Bs[i * nstore + j] = Bm[i * m_max + j];
                 if (diis_solve(Bs, nstore, cvec)) {
-                    UQC_HIP(launch_zero(Fx, NN, s));
-                    for (int i = 0; i < nstore; ++i)
-                        UQC_BLAS(rocblas_daxpy(h, (rocblas_int)NN, &cvec[i], Fs + (size_t)i * NN, 1, Fx, 1));
-                    Fnext = Fx;
+                    for (int sp = 0; sp < nspin; ++sp) {
+                        UQC_HIP(launch_zero(Fx[sp], NN, s));
+                        for (int i = 0; i < nstore; ++i)
+                            UQC_BLAS(rocblas_daxpy(h, (rocblas_int)NN, &cvec[i], Fs(i, sp), 1, Fx[sp], 1));
+                        Fnext[sp] = Fx[sp];
+                    }
                 }
             }
         }
-        if ((st = density(Fnext)) != UQC_OK) return st;
+        for (int sp = 0; sp < nspin; ++sp) {
+            if ((st = orbitals(Fnext[sp], C[sp])) != UQC_OK) return st;
+            if ((st = density(sp)) != UQC_OK) return st;
+        }
     }
     UQC_HIP(hipStreamSynchronize(s));
-    if (Pout) {
-        UQC_HIP(hipMemcpyAsync(Pout, P, NN * 8, hipMemcpyDeviceToHost, s));
+    double s2 = 0.0;
+    if (nspin == 2) {
+        // <S^2> = S_z (S_z + 1) + n_beta - tr(P^a S P^b S); T1 = P^a S and M = S P^b, column-major
+        UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &one, P[0], N, S, N, &zero,
+                               T1, N));
+        UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &one, S, N, P[1], N, &zero,
+                               M, N));
+        double tr = 0.0;
+        UQC_BLAS(rocblas_ddot(h, (rocblas_int)NN, T1, 1, M, 1, &tr));
+        const double sz = 0.5 * (nocc[0] - nocc[1]);
+        s2 = sz * (sz + 1.0) + nocc[1] - tr;
     }
-    if (eps_out) {
-        // orbital energies of the final Fock matrix
-        UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &one, F, N, X, N, &zero, T1,
-                               N));
-        UQC_BLAS(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, N, N, N, &one, X, N, T1, N, &zero, M,
-                               N));
-        if ((st = eig(M)) != UQC_OK) return st;
-        UQC_HIP(hipMemcpyAsync(eps_out, w, N * 8, hipMemcpyDeviceToHost, s));
+    for (int sp = 0; sp < nspin; ++sp) {
+        if (Pout[sp]) UQC_HIP(hipMemcpyAsync(Pout[sp], P[sp], NN * 8, hipMemcpyDeviceToHost, s));
+        if (eps_out[sp]) {
+            // orbital energies of the final Fock matrix
+            if ((st = orbitals(F[sp], E[sp])) != UQC_OK) return st;  // E[sp]: scratch for the orbitals
+            UQC_HIP(hipMemcpyAsync(eps_out[sp], w, N * 8, hipMemcpyDeviceToHost, s));
+        }
     }
     UQC_HIP(hipStreamSynchronize(s));
     if (res) {
@@ -381,7 +438,30 @@ uqc_status uqc_scf_rhf(uqc_basis* B, int natom, const double* Z, const double* R
         res->error = err;
         res->fock_ms = fock_ms;
         res->quartets = quartets;
+        res->s2 = s2;
         res->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return UQC_OK;
+}
+
+uqc_status uqc_scf_rhf(uqc_basis* B, int natom, const double* Z, const double* R, int nocc, const uqc_scf_opts* opts,
+                       double* Pout, double* eps_out, uqc_scf_result* res) {
+    if (!B) return uqc_fail(UQC_E_ARG, "uqc_scf_rhf: NULL basis");
+    if (nocc < 1 || nocc > B->nbf) return uqc_fail(UQC_E_ARG, "uqc_scf_rhf: nocc outside 1..nbf");
+    const int n[1] = {nocc};
+    double* P[1] = {Pout};
+    double* e[1] = {eps_out};
+    return scf_run(B, natom, Z, R, 1, n, opts, P, e, res, "uqc_scf_rhf");
+}
+
+uqc_status uqc_scf_uhf(uqc_basis* B, int natom, const double* Z, const double* R, int nalpha, int nbeta,
+                       const uqc_scf_opts* opts, double* Pa, double* Pb, double* eps_a, double* eps_b,
+                       uqc_scf_result* res) {
+    if (!B) return uqc_fail(UQC_E_ARG, "uqc_scf_uhf: NULL basis");
+    if (nalpha < 0 || nbeta < 0 || nalpha > B->nbf || nbeta > B->nbf || nalpha + nbeta < 1)
+        return uqc_fail(UQC_E_ARG, "uqc_scf_uhf: electron counts outside 0..nbf (or none)");
+    const int n[2] = {nalpha, nbeta};
+    double* P[2] = {Pa, Pb};
+    double* e[2] = {eps_a, eps_b};
+    return scf_run(B, natom, Z, R, 2, n, opts, P, e, res, "uqc_scf_uhf");
 }

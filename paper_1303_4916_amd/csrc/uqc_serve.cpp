@@ -62,7 +62,7 @@ size_t estimate_footprint(const Req& r) {
             prim_pairs += (size_t)r.nprim[a] * r.nprim[b];
             ++pairs;
         }
-    size_t bytes = (N + 8 + 7 * NN) * sizeof(double);            // basis workspace
+    size_t bytes = (N + 8 + 9 * NN) * sizeof(double);            // basis workspace
     bytes += NN * sizeof(double) + N * r.ncol * sizeof(double);  // density + perturbation
     bytes += prim_pairs * kNumFields * sizeof(double) + pairs * (4 * sizeof(double) + 2 * sizeof(int));
     bytes += pairs * 2 * (2 * sizeof(int) + sizeof(long long)) + 64 * 1024;  // screened work lists (both precisions)
@@ -222,7 +222,7 @@ bool uqc_server::step() {
         uqc_basis* B = act[i]->basis;
         const size_t NN = (size_t)B->nbf * B->nbf;
         if (launch_finalize(act[i]->d_D, B->d_J, B->d_K, B->d_f, B->d_io + NN, B->d_io + 2 * NN, B->d_io + 3 * NN,
-                            B->d_scal, B->nbf, s) != hipSuccess ||
+                            act[i]->opts.exchange_scale, B->d_scal, B->nbf, s) != hipSuccess ||
             hipMemcpyAsync(&e2[i], B->d_scal, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
             (act[i]->plan->ntasks &&
              hipMemcpyAsync(act[i]->plan->h_count.data(), act[i]->plan->d_count,
@@ -351,6 +351,10 @@ uqc_status uqc_submit(uqc_server* s, const uqc_request* q, long long* ticket) {
     r->eps = q->eps;
     r->seed = q->seed;
     r->opts = q->opts;
+    if (!std::isfinite(r->opts.exchange_scale)) {
+        delete r;
+        return uqc_fail(UQC_E_ARG, "uqc_submit: exchange_scale is not finite");
+    }
     r->footprint = estimate_footprint(*r);
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) {

@@ -28,7 +28,8 @@ MAX_ITER = 64
 EXPORTED = ["uqc_fock_opts_default", "uqc_init", "uqc_finalize", "uqc_last_error", "uqc_basis_create",
             "uqc_basis_destroy", "uqc_basis_info", "uqc_schwarz", "uqc_eri_block", "uqc_eri_blocks",
             "uqc_fock_build", "uqc_boys", "uqc_server_create", "uqc_submit", "uqc_poll", "uqc_server_drain",
-            "uqc_server_destroy", "uqc_one_electron", "uqc_scf_opts_default", "uqc_scf_rhf"]
+            "uqc_server_destroy", "uqc_one_electron", "uqc_scf_opts_default", "uqc_scf_rhf", "uqc_fock_build_uhf",
+            "uqc_scf_uhf"]
 
 
 class UqcError(RuntimeError):
@@ -43,18 +44,19 @@ PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int, ctypes.c_lon
 class FockOpts(ctypes.Structure):
     _fields_ = [("schwarz_tau", ctypes.c_double), ("precision", ctypes.c_int), ("fp64_bound", ctypes.c_double),
                 ("timing", ctypes.c_int), ("progress", PROGRESS_FN), ("progress_user", ctypes.c_void_p),
-                ("max_items_per_launch", ctypes.c_longlong)]
+                ("max_items_per_launch", ctypes.c_longlong), ("exchange_scale", ctypes.c_double)]
 
 
 class ScfOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("e_conv", ctypes.c_double), ("d_conv", ctypes.c_double),
-                ("diis_size", ctypes.c_int), ("fock", FockOpts)]
+                ("diis_size", ctypes.c_int), ("fock", FockOpts), ("guess_mix", ctypes.c_double)]
 
 
 class ScfResult(ctypes.Structure):
     _fields_ = [("E_total", ctypes.c_double), ("E_elec", ctypes.c_double), ("E_nuc", ctypes.c_double),
                 ("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("error", ctypes.c_double),
-                ("ms", ctypes.c_double), ("fock_ms", ctypes.c_double), ("quartets", ctypes.c_longlong)]
+                ("ms", ctypes.c_double), ("fock_ms", ctypes.c_double), ("quartets", ctypes.c_longlong),
+                ("s2", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -151,6 +153,10 @@ def load(build_if_missing: bool = True):
         L.uqc_scf_opts_default.restype = None
         L.uqc_scf_rhf.argtypes = [vp, ctypes.c_int, _D, _D, ctypes.c_int, ctypes.POINTER(ScfOpts), _D, _D,
                                   ctypes.POINTER(ScfResult)]
+        L.uqc_fock_build_uhf.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(FockOpts),
+                                         ctypes.POINTER(Stats)]
+        L.uqc_scf_uhf.argtypes = [vp, ctypes.c_int, _D, _D, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ScfOpts), _D,
+                                  _D, _D, _D, ctypes.POINTER(ScfResult)]
         for name in EXPORTED:
             if name not in ("uqc_fock_opts_default", "uqc_last_error", "uqc_scf_opts_default"):
                 getattr(L, name).restype = ctypes.c_int
@@ -173,24 +179,26 @@ def _ip(a: np.ndarray):
 
 
 def scf_opts(max_iter: int = 100, e_conv: float = 1e-10, d_conv: float = 1e-8, diis_size: int = 8,
-             fock: FockOpts = None) -> ScfOpts:
-    """Options of uqc_scf_rhf (library defaults unless given)."""
+             fock: FockOpts = None, guess_mix: float = 0.0) -> ScfOpts:
+    """Options of uqc_scf_rhf / uqc_scf_uhf (library defaults unless given)."""
     o = ScfOpts()
     load().uqc_scf_opts_default(ctypes.byref(o))
     o.max_iter = int(max_iter)
     o.e_conv = float(e_conv)
     o.d_conv = float(d_conv)
     o.diis_size = int(diis_size)
+    o.guess_mix = float(guess_mix)
     if fock is not None:
         o.fock = fock
     return o
 
 
 def default_opts(tau: float = 1e-12, precision: int = FP64, fp64_bound: float = 1e-8, timing: bool = False,
-                 progress=None, max_items_per_launch: int = 0):
+                 progress=None, max_items_per_launch: int = 0, exchange_scale: float = 1.0):
     """Fock-build options.  progress: None or a callable(class_id, items_done, items_total) called after every
     class sub-launch has completed on the device (the build then waits for each one).  max_items_per_launch: cap
-    on the work items of one class-kernel launch (0: the library default)."""
+    on the work items of one class-kernel launch (0: the library default).  exchange_scale: weight x of exchange
+    (G = J - (x/2) K; spin densities G^s = J - x K^s)."""
     o = FockOpts()
     load().uqc_fock_opts_default(ctypes.byref(o))
     o.schwarz_tau = float(tau)
@@ -198,6 +206,7 @@ def default_opts(tau: float = 1e-12, precision: int = FP64, fp64_bound: float = 
     o.fp64_bound = float(fp64_bound)
     o.timing = 1 if timing else 0
     o.max_items_per_launch = int(max_items_per_launch)
+    o.exchange_scale = float(exchange_scale)
     if progress is not None:
         fn = PROGRESS_FN(lambda user, cid, done, total: progress(int(cid), int(done), int(total)))
         o.progress = fn
@@ -353,6 +362,38 @@ class Basis:
         st = self.fock_build_ptr(D.ctypes.data, ptr(outs["J"]), ptr(outs["K"]), ptr(outs["G"]), opts)
         return outs["J"], outs["K"], outs["G"], st
 
+    def fock_build_uhf(self, Da, Db, opts: FockOpts = None, want=("J", "Ka", "Kb", "Ga", "Gb")):
+        """Spin-density build: Da, Db numpy arrays (host path) or torch tensors on the device (device path).  Returns
+        a dict with J, Ka, Kb, Ga, Gb (outputs of the same kind as the inputs; None for those not requested) and
+        "stats"."""
+        N = self.nbf
+        names = ("J", "Ka", "Kb", "Ga", "Gb")
+        try:
+            import torch
+            is_t = isinstance(Da, torch.Tensor)
+        except Exception:
+            is_t = False
+        if is_t:
+            for D in (Da, Db):
+                if D.dtype != torch.float64 or not D.is_contiguous() or tuple(D.shape) != (N, N):
+                    raise ValueError("densities must be contiguous float64 %dx%d tensors" % (N, N))
+            outs = {k: (torch.empty((N, N), dtype=torch.float64, device=Da.device) if k in want else None)
+                    for k in names}
+            ptr = lambda t: ctypes.c_void_p(int(t.data_ptr())) if t is not None else None
+        else:
+            Da = np.ascontiguousarray(Da, dtype=np.float64)
+            Db = np.ascontiguousarray(Db, dtype=np.float64)
+            if Da.shape != (N, N) or Db.shape != (N, N):
+                raise ValueError("densities must be %dx%d" % (N, N))
+            outs = {k: (np.zeros((N, N)) if k in want else None) for k in names}
+            ptr = lambda a: ctypes.c_void_p(a.ctypes.data) if a is not None else None
+        st = Stats()
+        o = opts if opts is not None else default_opts()
+        _check(load().uqc_fock_build_uhf(self.h, ptr(Da), ptr(Db), *[ptr(outs[k]) for k in names], ctypes.byref(o),
+                                         ctypes.byref(st)))
+        outs["stats"] = st
+        return outs
+
 
     def one_electron(self, Z, R, want=("S", "T", "V")):
         """Overlap, kinetic and nuclear-attraction matrices for nuclei Z[natom] at R[natom][3] (host numpy arrays
@@ -385,6 +426,24 @@ class Basis:
         return {"E_total": res.E_total, "E_elec": res.E_elec, "E_nuc": res.E_nuc, "iterations": res.iterations,
                 "converged": bool(res.converged), "error": res.error, "ms": res.ms, "fock_ms": res.fock_ms,
                 "quartets": res.quartets, "P": P, "eps": eps}
+
+    def scf_uhf(self, Z, R, nalpha: int, nbeta: int, opts: ScfOpts = None):
+        """Unrestricted Hartree-Fock; returns a dict with the energies, iteration count, convergence flag, final
+        error, <S^2>, timings, the spin densities Pa, Pb and the orbital energies eps_a, eps_b."""
+        Z = np.ascontiguousarray(Z, dtype=np.float64).reshape(-1)
+        R = np.ascontiguousarray(R, dtype=np.float64).reshape(-1)
+        if R.shape[0] != 3 * Z.shape[0]:
+            raise ValueError("R must hold 3 coordinates per nucleus")
+        N = self.nbf
+        Pa, Pb = np.zeros((N, N)), np.zeros((N, N))
+        ea, eb = np.zeros(N), np.zeros(N)
+        res = ScfResult()
+        o = opts if opts is not None else scf_opts()
+        _check(load().uqc_scf_uhf(self.h, int(Z.shape[0]), _dp(Z), _dp(R), int(nalpha), int(nbeta), ctypes.byref(o),
+                                  _dp(Pa), _dp(Pb), _dp(ea), _dp(eb), ctypes.byref(res)))
+        return {"E_total": res.E_total, "E_elec": res.E_elec, "E_nuc": res.E_nuc, "iterations": res.iterations,
+                "converged": bool(res.converged), "error": res.error, "s2": res.s2, "ms": res.ms,
+                "fock_ms": res.fock_ms, "quartets": res.quartets, "Pa": Pa, "Pb": Pb, "eps_a": ea, "eps_b": eb}
 
 
 class Server:

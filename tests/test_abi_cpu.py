@@ -35,7 +35,7 @@ def test_library_has_gfx950_code_object():
 def test_default_options():
     o = uqc.default_opts()
     assert o.schwarz_tau == 1e-12 and o.precision == uqc.FP64 and o.fp64_bound == 1e-8 and o.timing == 0
-    assert not o.progress and o.max_items_per_launch == 0
+    assert not o.progress and o.max_items_per_launch == 0 and o.exchange_scale == 1.0
 
 
 def test_null_arguments_rejected_before_device_use():
@@ -49,8 +49,11 @@ def test_null_arguments_rejected_before_device_use():
     assert L.uqc_server_destroy(None) == uqc.UQC_E_ARG
     assert L.uqc_one_electron(None, 0, None, None, None, None, None) == uqc.UQC_E_ARG
     assert L.uqc_scf_rhf(None, 0, None, None, 1, None, None, None, None) == uqc.UQC_E_ARG
+    assert L.uqc_fock_build_uhf(None, None, None, None, None, None, None, None, None, None) == uqc.UQC_E_ARG
+    assert L.uqc_scf_uhf(None, 0, None, None, 1, 0, None, None, None, None, None, None) == uqc.UQC_E_ARG
     o = uqc.scf_opts()
     assert o.max_iter == 100 and o.e_conv == 1e-10 and o.d_conv == 1e-8 and o.diis_size == 8
+    assert o.guess_mix == 0.0
     assert o.fock.schwarz_tau == 1e-12 and o.fock.precision == uqc.FP64
 
 
@@ -71,7 +74,7 @@ def test_struct_layouts_match_header(tmp_path):
     """The ctypes mirrors of the public structs have the C compiler's sizes and field offsets."""
     import subprocess
     fields = {"uqc_fock_opts": (uqc.FockOpts, ["schwarz_tau", "precision", "fp64_bound", "timing", "progress",
-                                                 "progress_user", "max_items_per_launch"]),
+                                                 "progress_user", "max_items_per_launch", "exchange_scale"]),
               "uqc_stats": (uqc.Stats, [f for f, _ in uqc.Stats._fields_]),
               "uqc_scf_opts": (uqc.ScfOpts, [f for f, _ in uqc.ScfOpts._fields_]),
               "uqc_scf_result": (uqc.ScfResult, [f for f, _ in uqc.ScfResult._fields_]),
