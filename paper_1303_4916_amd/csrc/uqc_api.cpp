@@ -6,7 +6,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <numeric>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -193,7 +195,7 @@ static uqc_status upload_bin(Bin& b) {
     const size_t np = b.np, K = b.K;
     const size_t n_prim = kNumFields * K * np, n_rec = np * K * kRec, n_hdr = np * kHdr;
     const size_t nd = n_prim + 3 * np + 2 * np + n_rec + n_hdr;
-    const size_t bytes = nd * sizeof(double) + 2 * np * sizeof(int);
+    const size_t bytes = nd * sizeof(double) + 3 * np * sizeof(int);
     if (!b.d_mem) {
         if (hipMalloc(&b.d_mem, bytes) != hipSuccess) return uqc_fail(UQC_E_NOMEM, "basis: bin allocation failed");
     }
@@ -221,6 +223,7 @@ static uqc_status upload_bin(Bin& b) {
     int* hi = (int*)(hd + nd);
     std::memcpy(hi, b.off_a.data(), np * sizeof(int));
     std::memcpy(hi + np, b.off_b.data(), np * sizeof(int));
+    for (size_t i = 0; i < np; ++i) hi[2 * np + i] = b.kp.empty() ? (int)K : b.kp[i];
     UQC_HIP(hipMemcpy(b.d_mem, host.data(), bytes, hipMemcpyHostToDevice));
     double* dd = (double*)b.d_mem;
     int* di = (int*)(dd + nd);
@@ -232,6 +235,7 @@ static uqc_status upload_bin(Bin& b) {
     b.dev.hdr = b.dev.rec + n_rec;
     b.dev.off_a = di;
     b.dev.off_b = di + np;
+    b.dev.kp = di + 2 * np;
     b.dev.np = (int)np;
     b.dev.K = (int)K;
     return UQC_OK;
@@ -258,9 +262,10 @@ int Bin::first_at_or_below(int dec) const {
 static void permute_bin(Bin& b, const std::vector<int>& perm) {
     const size_t np = b.np, K = b.K;
     std::vector<double> prim(b.prim.size()), AB(b.AB.size()), sdeg(np), Q(np);
-    std::vector<int> oa(np), ob(np), sa(np), sb(np);
+    std::vector<int> oa(np), ob(np), sa(np), sb(np), kp(np);
     for (size_t i = 0; i < np; ++i) {
         const size_t o = perm[i];
+        kp[i] = b.kp[o];
         for (size_t f = 0; f < (size_t)kNumFields; ++f)
             for (size_t k = 0; k < K; ++k) prim[(f * K + k) * np + i] = b.prim[(f * K + k) * np + o];
         for (int x = 0; x < 3; ++x) AB[x * np + i] = b.AB[x * np + o];
@@ -279,6 +284,73 @@ static void permute_bin(Bin& b, const std::vector<int>& perm) {
     b.off_b.swap(ob);
     b.sa.swap(sa);
     b.sb.swap(sb);
+    b.kp.swap(kp);
+}
+
+// Bounds Q_e = sqrt(max_ij (e|e)_ij) of every primitive pair e of a bin (entry e = k * np + i for primitive pair k
+// of pair i), from the bin viewed as K = 1: its field-major primitive array [field][k][i] is already laid out as
+// [field][e].  didx holds 0..n-1 and dq room for n values, n >= K * np.
+static uqc_status prim_schwarz(uqc_ctx* ctx, const Bin& bn, const int* didx, double* dq, std::vector<double>& qp) {
+    const size_t np = bn.np, K = bn.K, nv = np * K;
+    Bin v;
+    v.la = bn.la;
+    v.lb = bn.lb;
+    v.K = 1;
+    v.np = (int)nv;
+    v.prim = bn.prim;
+    v.AB.resize(3 * nv);
+    v.sdeg.assign(nv, 1.0);
+    v.Q.assign(nv, 0.0);
+    v.off_a.resize(nv);
+    v.off_b.resize(nv);
+    for (size_t k = 0; k < K; ++k)
+        for (size_t i = 0; i < np; ++i) {
+            const size_t e = k * np + i;
+            for (int x = 0; x < 3; ++x) v.AB[x * nv + e] = bn.AB[x * np + i];
+            v.off_a[e] = bn.off_a[i];
+            v.off_b[e] = bn.off_b[i];
+        }
+    uqc_status st = upload_bin(v);
+    if (st != UQC_OK) return st;
+    ListDev L;
+    L.bra = v.dev;
+    L.ket = v.dev;
+    L.bra_idx = didx;
+    L.ket_idx = didx;
+    L.n = (int)nv;
+    L.out = dq;
+    qp.assign(nv, 0.0);
+    const int cls = class_index(bn.la, bn.lb, bn.la, bn.lb);
+    if (launch_list(cls, false, MODE_SCHWARZ, L, ctx->boys64, ctx->boys32, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(qp.data(), dq, nv * sizeof(double), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        st = uqc_fail(UQC_E_DEVICE, "basis: primitive Schwarz kernel failed");
+    (void)hipFree(v.d_mem);
+    return st;
+}
+
+// Orders the primitive pairs of every shell pair by decreasing bound and sets kp to the number with
+// Q_e * qmax > kPrimEps (at least 1).  qp[b] holds the primitive bounds of bins[b].  Re-uploaded later.
+static void order_primitives(std::vector<Bin>& bins, const std::vector<std::vector<double>>& qp, double qmax) {
+    for (size_t b = 0; b < bins.size(); ++b) {
+        Bin& bn = bins[b];
+        const size_t np = bn.np, K = bn.K;
+        std::vector<int> ord(K);
+        std::vector<double> rec(kNumFields * K);
+        for (size_t i = 0; i < np; ++i) {
+            std::iota(ord.begin(), ord.end(), 0);
+            std::stable_sort(ord.begin(), ord.end(),
+                             [&](int x, int y) { return qp[b][(size_t)x * np + i] > qp[b][(size_t)y * np + i]; });
+            int keep = 0;
+            for (size_t k = 0; k < K; ++k)
+                if (qp[b][(size_t)ord[k] * np + i] * qmax > kPrimEps) ++keep;
+            bn.kp[i] = std::max(keep, 1);
+            for (size_t f = 0; f < (size_t)kNumFields; ++f)
+                for (size_t k = 0; k < K; ++k) rec[f * K + k] = bn.prim[(f * K + ord[k]) * np + i];
+            for (size_t f = 0; f < (size_t)kNumFields; ++f)
+                for (size_t k = 0; k < K; ++k) bn.prim[(f * K + k) * np + i] = rec[f * K + k];
+        }
+    }
 }
 
 uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* nprim, const double* center,
@@ -399,6 +471,7 @@ uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* n
         bn.off_b.resize(np);
         bn.sa.resize(np);
         bn.sb.resize(np);
+        bn.kp.assign(np, (int)K);
         for (size_t i = 0; i < np; ++i) {
             const ShellH& A = B->shells[mem[i].first];
             const ShellH& Bs = B->shells[mem[i].second];
@@ -471,6 +544,34 @@ uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* n
         }
         (void)hipFree(tmp);
         if (st != UQC_OK) { delete B; return st; }
+    }
+    // primitive-pair screening: bounds of every primitive pair on the GPU, then each pair's primitive pairs ordered
+    // by bound with the count above kPrimEps recorded
+    {
+        double qmax = 0.0;
+        size_t maxn = 0;
+        for (auto& bn : B->bins) {
+            for (int i = 0; i < bn.np; ++i) qmax = std::max(qmax, bn.Q[i]);
+            maxn = std::max(maxn, (size_t)bn.np * bn.K);
+        }
+        void* tmp = nullptr;
+        if (hipMalloc(&tmp, (maxn + 1) * (sizeof(int) + sizeof(double))) != hipSuccess) {
+            delete B;
+            return uqc_fail(UQC_E_NOMEM, "basis: primitive Schwarz scratch allocation failed");
+        }
+        std::vector<int> idx(maxn);
+        std::iota(idx.begin(), idx.end(), 0);
+        int* didx = (int*)tmp;
+        double* dq = (double*)(didx + maxn + (maxn & 1));
+        uqc_status st = UQC_OK;
+        if (hipMemcpy(didx, idx.data(), maxn * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+            st = uqc_fail(UQC_E_DEVICE, "basis: upload failed");
+        std::vector<std::vector<double>> qp(B->bins.size());
+        for (size_t bi = 0; bi < B->bins.size() && st == UQC_OK; ++bi)
+            st = prim_schwarz(ctx, B->bins[bi], didx, dq, qp[bi]);
+        (void)hipFree(tmp);
+        if (st != UQC_OK) { delete B; return st; }
+        order_primitives(B->bins, qp, qmax);
     }
     // Morton code of every shell centre (10 bits per axis over the bounding box): pairs that differ only in their
     // second shell are ordered along this curve, so neighbouring lanes hold nearby pairs
@@ -594,9 +695,10 @@ void uqc::plan_account(Plan& p) {
         g.flops = 0;
         for (int t = 0; t < g.ntask; ++t) {
             const long long q = (long long)p.h_count[g.task0 + t];
+            const long long pq = (long long)p.h_count[p.ntasks + g.task0 + t];
             g.quartets += q;
-            g.prim_quartets += q * g.task_K[t];
-            g.flops += (double)q * ((double)g.task_K[t] * class_flops_prim(g.cls) + class_flops_contr(g.cls));
+            g.prim_quartets += pq;
+            g.flops += (double)q * class_flops_contr(g.cls) + (double)pq * class_flops_prim(g.cls);
         }
         p.quartets += g.quartets;
         p.prim_quartets += g.prim_quartets;
@@ -708,7 +810,7 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
     // device memory: counters, per task lo/hi/off, per group TaskDev array + task_begin
     size_t bytes = 0;
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    bytes += align(tasks.size() * sizeof(unsigned long long));
+    bytes += align(2 * tasks.size() * sizeof(unsigned long long));
     for (auto& t : tasks) {
         const size_t n = B->bins[t.X].np;
         bytes += align(n * sizeof(int)) * 2 + align(t.blist.size() * sizeof(int)) + align(t.items.size() * sizeof(int));
@@ -721,9 +823,9 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
     }
     char* dbase = (char*)plan.d_mem;
     size_t pos = 0;
-    plan.d_count = (unsigned long long*)dbase;
-    plan.h_count.assign(tasks.size(), 0);
-    pos += align(tasks.size() * sizeof(unsigned long long));
+    plan.d_count = (unsigned long long*)dbase;  // [ntasks] quartets, then [ntasks] primitive quartets
+    plan.h_count.assign(2 * tasks.size(), 0);
+    pos += align(2 * tasks.size() * sizeof(unsigned long long));
     std::vector<TaskDev> tdev(tasks.size());
     for (size_t oi = 0; oi < order.size(); ++oi) {
         const int ti = order[oi];
@@ -754,6 +856,7 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
         d.lo_excl = t.lo_excl;
         d.hi_incl = t.hi_incl;
         d.count = plan.d_count + oi;
+        d.pcount = plan.d_count + tasks.size() + oi;
         d.nbra = (int)n;
         d.same = t.same;
         d.D = B->d_Dp;
@@ -776,7 +879,6 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
             begin.push_back(items);
             items += d.nitems;
             gt.push_back(d);
-            G.task_K.push_back(B->bins[tasks[order[oi]].X].K * B->bins[tasks[order[oi]].Y].K);
             ++oi;
         }
         G.ntask = (int)gt.size();
@@ -1016,7 +1118,7 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
     const bool timing = o.timing != 0;
     std::vector<double> cls_ms(plan->groups.size(), 0.0);
     auto pass = [&]() -> uqc_status {
-        if (plan->ntasks) UQC_HIP(launch_zero((double*)plan->d_count, (size_t)plan->ntasks, s));
+        if (plan->ntasks) UQC_HIP(launch_zero((double*)plan->d_count, 2 * (size_t)plan->ntasks, s));
         size_t ev = 0;
         for (auto& g : plan->groups) {
             if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, ev++), s));
@@ -1060,7 +1162,7 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
     double E2 = 0.0;
     UQC_HIP(hipMemcpyAsync(&E2, B->d_scal, sizeof(double), hipMemcpyDeviceToHost, s));
     if (plan->ntasks)
-        UQC_HIP(hipMemcpyAsync(plan->h_count.data(), plan->d_count, plan->ntasks * sizeof(unsigned long long),
+        UQC_HIP(hipMemcpyAsync(plan->h_count.data(), plan->d_count, 2 * plan->ntasks * sizeof(unsigned long long),
                                hipMemcpyDeviceToHost, s));
     if (!dev)
         for (int i = 0; i < nout; ++i)

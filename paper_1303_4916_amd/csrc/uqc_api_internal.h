@@ -44,6 +44,7 @@ struct Bin {
     int la = 0, lb = 0, Ka = 0, Kb = 0, K = 0, np = 0;
     std::vector<double> prim, AB, sdeg, Q;
     std::vector<int> off_a, off_b, sa, sb;
+    std::vector<int> kp;                       // [np] leading primitive pairs above the primitive bound
     std::vector<int> bucket;                   // [np] decade of Q (floor(log10 Q)), non-increasing along the bin
     std::vector<std::pair<int, int>> bstart;   // (decade, first index) for every decade present, in bin order
     int first_below(int dec) const;            // first index whose decade is < dec (np if none)
@@ -59,7 +60,6 @@ struct LaunchGroup {
     int task0 = 0;                     // index of the group's first task counter in the plan's counter array
     long long nitems = 0, quartets = 0, prim_quartets = 0;  // counts of the last build
     double flops = 0;
-    std::vector<int> task_K;           // primitive quartets per shell quartet of every task (K_bra * K_ket)
     const TaskDev* d_tasks = nullptr;
     const long long* d_begin = nullptr;
     std::vector<TaskDev> host_tasks;   // copies (device pointers inside), used to batch several bases
@@ -78,7 +78,7 @@ struct Plan {
     long long quartets = 0, screened = 0, prim_quartets = 0, fp64_quartets = 0;  // counts of the last build
     double flops = 0;
     int ntasks = 0;
-    unsigned long long* d_count = nullptr;         // [ntasks] per-task quartet counters (device)
+    unsigned long long* d_count = nullptr;         // [2 ntasks] per-task quartet, then primitive-quartet counters
     std::vector<unsigned long long> h_count;
     void* d_mem = nullptr;
 };

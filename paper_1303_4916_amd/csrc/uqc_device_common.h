@@ -155,6 +155,13 @@ __device__ __forceinline__ double wave_sum(double x) {
     return x;
 }
 
+// Largest x over the wavefront (every lane active), as a wavefront-uniform value.
+__device__ __forceinline__ int wave_max_int(int x) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, kWave));
+    return __builtin_amdgcn_readfirstlane(x);
+}
+
 __device__ __forceinline__ void atomic_add(double* p, double v) { (void)unsafeAtomicAdd(p, v); }
 
 __device__ __forceinline__ void atomic_add_lds(double* p, double v) {

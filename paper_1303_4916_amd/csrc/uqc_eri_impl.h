@@ -27,17 +27,18 @@ struct EriClass;
 
 // ------------------------------------------------------------------------------------- contracted quartet core
 // Sums the primitive quartets of (bra pair `bra` of bin B | ket pair `ket` of bin Kt) into the contracted
-// [e0|f0] accumulators of class C.
+// [e0|f0] accumulators of class C: the leading kbn primitive pairs of the bra times the leading kkn of the ket
+// (all of them: kbn = B.K, kkn = Kt.K).
 // FP64 path: one loop over the primitive quartets (ket primitive outer, bra primitive inner).  The bra records are
 // wavefront-uniform scalar loads; the next one is requested before the current quartet is evaluated, which costs
 // scalar registers only.  Ket fields are read through 32-bit offsets from the bin's base.
 template <class C>
-__device__ __forceinline__ void accumulate64(const BinDev& B, int bra, const BinDev& Kt, int ket,
+__device__ __forceinline__ void accumulate64(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
                                              const double* __restrict__ boys64tab, double* __restrict__ acc) {
     const unsigned npk = (unsigned)Kt.np, fsk = (unsigned)Kt.K * npk;
     const cdptr kbase = as_const(Kt.prim);
     const cdptr brec = as_const(B.rec) + (size_t)bra * B.K * kRec;  // wavefront-uniform: scalar loads
-    const int KB = B.K, NPQ = B.K * Kt.K;
+    const int KB = kbn, NPQ = kbn * kkn;
     double eta = 0, Qx = 0, Qy = 0, Qz = 0, QCx = 0, QCy = 0, QCz = 0, prefk = 0, o2e = 0;
     double b[kNumFields];
 #pragma unroll
@@ -86,24 +87,24 @@ __device__ __forceinline__ void accumulate64(const BinDev& B, int bra, const Bin
 }
 
 template <class C, bool MIXED>
-__device__ __forceinline__ void accumulate(const BinDev& B, int bra, const BinDev& Kt, int ket,
+__device__ __forceinline__ void accumulate(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
                                            const double* __restrict__ boys64tab, const float* __restrict__ boys32tab,
                                            double* __restrict__ acc) {
     if constexpr (!MIXED) {
-        accumulate64<C>(B, bra, Kt, ket, boys64tab, acc);
+        accumulate64<C>(B, bra, kbn, Kt, ket, kkn, boys64tab, acc);
         return;
     }
     const size_t npk = (size_t)Kt.np;
     const size_t fsk = (size_t)Kt.K * npk;
     const cdptr brec = as_const(B.rec) + (size_t)bra * B.K * kRec;  // wavefront-uniform: scalar loads
-    for (int kk = 0; kk < Kt.K; ++kk) {
+    for (int kk = 0; kk < kkn; ++kk) {
         const double* kp = Kt.prim + (size_t)kk * npk + ket;
         const double eta = kp[F_Z * fsk];
         const double Qx = kp[F_PX * fsk], Qy = kp[F_PY * fsk], Qz = kp[F_PZ * fsk];
         const double QCx = kp[F_PAX * fsk], QCy = kp[F_PAY * fsk], QCz = kp[F_PAZ * fsk];
         const double prefk = kp[F_PREF * fsk];
         const double o2e = kp[F_O2Z * fsk];
-        for (int kb = 0; kb < B.K; ++kb) {
+        for (int kb = 0; kb < kbn; ++kb) {
             const cdptr bp = brec + kb * kRec;
             const double zeta = bp[F_Z];
             const double Px = bp[F_PX], Py = bp[F_PY], Pz = bp[F_PZ];
@@ -275,6 +276,8 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
     const bool ket_ok = ket < Kt.np;
     const int kc = ket_ok ? ket : Kt.np - 1;
     const double qk = Kt.Q[kc];
+    // ket primitive pairs evaluated: the most any lane's ket needs (the kets stay for the whole item)
+    const int kkn = wave_max_int(ket_ok ? Kt.kp[kc] : 1);
     const double* __restrict__ D = tk.D;
     // D is read-only while the kernel runs: read through the constant address space with 32-bit offsets (N < 2^16)
     const cdptr Dc = as_const(D);
@@ -350,7 +353,7 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
                 }
         }
     };
-    unsigned long long cnt = 0;
+    unsigned long long cnt = 0, pcnt = 0;
     for (int e = it.x; e < gend; ++e) {
         const int bra = __builtin_amdgcn_readfirstlane(as_const(tk.blist)[e]);  // wavefront-uniform
         const cdptr bh = as_const(B.hdr) + (size_t)bra * kHdr;  // AB, sdeg, Q, offsets of the bra pair
@@ -359,7 +362,9 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
                          q > tk.lo_excl && q <= tk.hi_incl;
         const unsigned long long live = __ballot(act);
         if (live == 0ULL) continue;  // uniform: no quartet of this bra pair survives in the chunk
+        const int kbn = as_const(B.kp)[bra];
         cnt += (unsigned long long)__popcll(live);
+        pcnt += (unsigned long long)__popcll(live) * (unsigned long long)(kbn * kkn);
         const int oa = ((ciptr)(bh + 5))[0], ob = ((ciptr)(bh + 5))[1];
         if (oa != cur_a) {
             if (cur_a >= 0) flush_a();
@@ -371,7 +376,7 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
             double acc[C::NACC];
 #pragma unroll
             for (int x = 0; x < C::NACC; ++x) acc[x] = 0.0;
-            accumulate<C, MIXED>(B, bra, Kt, kl, boys64tab, boys32tab, acc);
+            accumulate<C, MIXED>(B, bra, kbn, Kt, kl, kkn, boys64tab, boys32tab, acc);
             C::hrr(acc, bh[0], bh[1], bh[2], Kt.AB[kl], Kt.AB[Kt.np + kl],
                    Kt.AB[2 * Kt.np + kl], out);
         }
@@ -473,7 +478,10 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
                 if (s != 0.0) atomic_add(J + (size_t)(oc + k) * N + od + l, s);
             }
     }
-    if (lane == 0 && cnt) atomicAdd(tk.count, cnt);
+    if (lane == 0 && cnt) {
+        atomicAdd(tk.count, cnt);
+        atomicAdd(tk.pcount, pcnt);
+    }
 }
 
 template <int LA, int LB, int LC, int LD, bool MIXED, int MODE>
@@ -486,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void k_list(ListDev L, const double* __rest
     double acc[C::NACC];
 #pragma unroll
     for (int x = 0; x < C::NACC; ++x) acc[x] = 0.0;
-    accumulate<C, MIXED>(L.bra, bra, L.ket, ket, boys64tab, boys32tab, acc);
+    accumulate<C, MIXED>(L.bra, bra, L.bra.K, L.ket, ket, L.ket.K, boys64tab, boys32tab, acc);
     constexpr int NOUT = C::NA * C::NB * C::NC * C::ND;
     double out[NOUT];
     C::hrr(acc, L.bra.AB[bra], L.bra.AB[L.bra.np + bra], L.bra.AB[2 * L.bra.np + bra], L.ket.AB[ket],

@@ -32,13 +32,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Contracted representative accumulators of one lane: the recursion of class TC with the geometry relabelled by
 // the axis permutation (q0, q1, q2).
 template <class TC, bool MIXED>
-__device__ __forceinline__ void team_accumulate(const BinDev& B, int bra, const BinDev& Kt, int ket, int q0, int q1,
-                                                int q2, const double* __restrict__ boys64tab,
+__device__ __forceinline__ void team_accumulate(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
+                                                int q0, int q1, int q2, const double* __restrict__ boys64tab,
                                                 const float* __restrict__ boys32tab, double* __restrict__ acc) {
     const size_t npk = (size_t)Kt.np;
     const size_t fsk = (size_t)Kt.K * npk;
     const cdptr brec = as_const(B.rec) + (size_t)bra * B.K * kRec;  // wavefront-uniform: scalar loads
-    for (int kk = 0; kk < Kt.K; ++kk) {
+    for (int kk = 0; kk < kkn; ++kk) {
         const double* kp = Kt.prim + (size_t)kk * npk + ket;
         const double eta = kp[F_Z * fsk];
         const double Qx = kp[F_PX * fsk], Qy = kp[F_PY * fsk], Qz = kp[F_PZ * fsk];
@@ -46,7 +46,7 @@ __device__ __forceinline__ void team_accumulate(const BinDev& B, int bra, const 
         const double QCx = sel3(QC0, QC1, QC2, q0), QCy = sel3(QC0, QC1, QC2, q1), QCz = sel3(QC0, QC1, QC2, q2);
         const double prefk = kp[F_PREF * fsk];
         const double o2e = kp[F_O2Z * fsk];
-        for (int kb = 0; kb < B.K; ++kb) {
+        for (int kb = 0; kb < kbn; ++kb) {
             const cdptr bp = brec + kb * kRec;
             const double zeta = bp[F_Z];
             const double Px = bp[F_PX], Py = bp[F_PY], Pz = bp[F_PZ];
@@ -212,6 +212,8 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
     const bool ket_ok = team < kTeamsPerWave && ket < Kt.np;
     const int kc = ket_ok ? ket : Kt.np - 1;  // idle teams compute a valid quartet with weight 0
     const double qk = Kt.Q[kc];
+    // ket primitive pairs evaluated: the most any team's ket needs (the kets stay for the whole item)
+    const int kkn = wave_max_int(ket_ok ? Kt.kp[kc] : 1);
     const double* __restrict__ D = tk.D;
     // D is read-only while the kernel runs: read through the constant address space with 32-bit offsets (N < 2^16)
     const cdptr Dc = as_const(D);
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
         }
     };
     int cur_a = -1;  // wavefront-uniform: first shell of the bra pairs whose K_ac / K_ad sums are held in LDS
-    unsigned long long cnt = 0;
+    unsigned long long cnt = 0, pcnt = 0;
     for (int e = it.x; e < gend; ++e) {
         const int bra = __builtin_amdgcn_readfirstlane(as_const(tk.blist)[e]);  // wavefront-uniform
         const cdptr bh = as_const(B.hdr) + (size_t)bra * kHdr;  // AB, sdeg, Q, offsets of the bra pair
@@ -257,7 +259,9 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
                          q > tk.lo_excl && q <= tk.hi_incl;
         const unsigned long long live = __ballot(act);
         if (live == 0ULL) continue;
+        const int kbn = as_const(B.kp)[bra];
         cnt += (unsigned long long)(__popcll(live) / kTeam);
+        pcnt += (unsigned long long)(__popcll(live) / kTeam) * (unsigned long long)(kbn * kkn);
         const int oa = ((ciptr)(bh + 5))[0], ob = ((ciptr)(bh + 5))[1];
         if (oa != cur_a) {
             if (cur_a >= 0) {
@@ -272,7 +276,7 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
         double acc[TC::NREP];
 #pragma unroll
         for (int x = 0; x < TC::NREP; ++x) acc[x] = 0.0;
-        team_accumulate<TC, MIXED>(B, bra, Kt, kl, q0, q1, q2, boys64tab, boys32tab, acc);
+        team_accumulate<TC, MIXED>(B, bra, kbn, Kt, kl, kkn, q0, q1, q2, boys64tab, boys32tab, acc);
 
         int src[kTeam];
 #pragma unroll
@@ -383,7 +387,10 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
         wave_lds_sync();
     }
     if (cur_a >= 0) flush(R_JCD, R_KBC, cur_a, 0);
-    if (lane == 0 && cnt) atomicAdd(tk.count, cnt);
+    if (lane == 0 && cnt) {
+        atomicAdd(tk.count, cnt);
+        atomicAdd(tk.pcount, pcnt);
+    }
 }
 
 }  // namespace uqc

@@ -8,6 +8,10 @@ namespace uqc {
 constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kBlock = 256;            // threads per block of the quartet kernels (4 wavefronts)
 constexpr int kMaxK = 16;              // maximum contraction depth
+// A primitive pair e of a shell pair is dropped when Q_e * Q_max <= kPrimEps, where Q_e = sqrt(max (e|e)) over its
+// Cartesian components and Q_max is the largest contracted pair bound of the basis.  By the Cauchy-Schwarz
+// inequality every integral then changes by at most (dropped primitive pairs of bra and ket) * kPrimEps.
+constexpr double kPrimEps = 1e-15;
 constexpr int kMaxNbf = 65535;         // maximum basis size (N x N matrices indexed with 32-bit offsets)
 constexpr int kBoysGridPerUnit = 8;    // Boys Taylor grid: T_g = g / 8 (exact in binary, same points in FP32/FP64)
 constexpr int kBoysTmax = 60;          // grid covers [0, 60); asymptotic form beyond
@@ -45,6 +49,8 @@ struct BinDev {
     const int* off_b;     // [np]
     const double* sdeg;   // [np] 0.5 if a == b else 1
     const double* Q;      // [np] Schwarz bound of the pair
+    const int* kp;        // [np] primitive pairs evaluated by the Fock build: the leading kp of the pair's K, which
+                          // are ordered by decreasing bound (the rest fall under kPrimEps)
     int np;
     int K;                // primitive pairs per shell pair (K_a * K_b)
 };
@@ -65,6 +71,7 @@ struct TaskDev {
     double tau;                // a quartet in the range is computed iff Q_ab Q_cd >= tau
     double lo_excl, hi_incl;   //   and lo_excl < Q_ab Q_cd <= hi_incl (precision routing)
     unsigned long long* count; // quartets computed by this task (one atomic per wavefront)
+    unsigned long long* pcount;  // primitive quartets computed by this task
     int nbra;
     int same;                  // bra bin == ket bin: the diagonal quartet (bra == ket) gets an extra 1/2
     const double* D;           // scaled density D' = f D f (nbf x nbf)

@@ -154,7 +154,7 @@ bool uqc_server::step() {
     for (Req* r : act) {
         uqc_basis* B = r->basis;
         const size_t NN = (size_t)B->nbf * B->nbf;
-        if ((r->plan->ntasks && launch_zero((double*)r->plan->d_count, (size_t)r->plan->ntasks, s) != hipSuccess) ||
+        if ((r->plan->ntasks && launch_zero((double*)r->plan->d_count, 2 * (size_t)r->plan->ntasks, s) != hipSuccess) ||
             launch_zero(B->d_scal, 8, s) != hipSuccess ||
             launch_prepare(r->d_D, B->d_f, B->d_Dp, B->nbf, (unsigned long long*)(B->d_scal + 1), s) != hipSuccess ||
             launch_zero(B->d_J, 2 * NN, s) != hipSuccess)
@@ -226,7 +226,8 @@ bool uqc_server::step() {
             hipMemcpyAsync(&e2[i], B->d_scal, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
             (act[i]->plan->ntasks &&
              hipMemcpyAsync(act[i]->plan->h_count.data(), act[i]->plan->d_count,
-                            act[i]->plan->ntasks * sizeof(unsigned long long), hipMemcpyDeviceToHost, s) != hipSuccess))
+                            2 * act[i]->plan->ntasks * sizeof(unsigned long long), hipMemcpyDeviceToHost, s) !=
+                                hipSuccess))
             return fail_all("server: finalize failed");
     }
     if (hipStreamSynchronize(s) != hipSuccess) return fail_all("server: step failed on the device");
