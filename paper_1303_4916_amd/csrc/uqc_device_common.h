@@ -45,13 +45,14 @@ __device__ __forceinline__ double rsqrt64(double x) {
 
 // ------------------------------------------------------------------------------------------------ Boys function
 // F_m(T) = int_0^1 t^{2m} exp(-T t^2) dt, returned multiplied by `pref` (`tab`: the per-order FP64 slices).
-// For T < 60: Taylor series of order 8 around the nearest grid point T_g = g/8 (|d| = |T_g - T| <= 1/16,
-// truncation error < 1e-16 relative), using dF_m/dT = -F_{m+1}, for the highest order needed (the table holds
-// the coefficients F_{L+k}(T_g)/k!); exp(-T) = exp(-T_g) exp(d) with exp(-T_g) tabulated and exp(d) from its
+// For T < T_L (L the highest order needed): Taylor series of order 8 around the nearest grid point T_g = g/8
+// (|d| = |T_g - T| <= 1/16, truncation error < 1e-16 relative), using dF_m/dT = -F_{m+1}, for order L (the table
+// holds the coefficients F_{L+k}(T_g)/k!); exp(-T) = exp(-T_g) exp(d) with exp(-T_g) tabulated and exp(d) from its
 // Taylor series to order 9 (truncation < 3e-19); then the downward recursion F_m = (2T F_{m+1} + exp(-T)) / (2m+1).
-// For T >= 60: F_0 = sqrt(pi/T)/2 (erf(sqrt(T)) = 1 to double precision) and the upward recursion
-// F_{m+1} = (2m+1) F_m / (2T); the exp(-T) term the exact recursion subtracts is below 1e-26 and changes no F_m,
-// m <= 8, by more than 2e-17 of its value.
+// For T >= T_L: F_0 = sqrt(pi/T)/2 and the upward recursion F_{m+1} = (2m+1) F_m / (2T), i.e.
+// F_m = Gamma(m+1/2) / (2 T^{m+1/2}); the exact value is this times the regularised lower incomplete gamma
+// P(m+1/2, T), so the relative error is Q(m+1/2, T) <= Q(L+1/2, T), which the cut-offs
+// T_L = 37, 41, 44, 47, 50, 53, 55, 58, 60 (L = 0..8) keep below 2e-17 (the grid covers [0, 60) for every L).
 // The two halves of boys64: the table row for T (grid index clamped, so the row can be fetched ahead of the test
 // on T), then the evaluation from that row.
 template <int L>
@@ -65,9 +66,13 @@ __device__ __forceinline__ int boys64_row(double T, const double* __restrict__ t
     return g;
 }
 
+// T_L of the comment above: the smallest integer T with Q(L+1/2, T) <= 2e-17
+__device__ constexpr double kBoysAsymT[9] = {37, 41, 44, 47, 50, 53, 55, 58, 60};
+
 template <int L>
 __device__ __forceinline__ void boys64_eval(double T, int g, double pref, const double2* r, double* F) {
-    if (T < (double)kBoysTmax) {
+    static_assert(L >= 0 && L <= 8 && kBoysTmax >= 60, "Boys orders 0..8 with the grid covering [0, 60)");
+    if (T < kBoysAsymT[L]) {
         const double d = (double)g * (1.0 / kBoysGridPerUnit) - T;  // exact grid point
         double p = r[4].x;
         p = fma(p, d, r[3].y);

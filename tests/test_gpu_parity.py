@@ -45,6 +45,17 @@ def test_boys_fp64_matches_oracle(ctx):
     assert rel <= 5e-14, rel
 
 
+@pytest.mark.parametrize("mmax", range(9))
+def test_boys_fp64_every_order_around_its_asymptotic_cut(ctx, mmax):
+    # the order-L evaluation switches to the asymptotic form at T_L = 37, 41, ..., 60 (L = 0..8)
+    cut = [37, 41, 44, 47, 50, 53, 55, 58, 60][mmax]
+    T = np.concatenate([np.linspace(0, 70, 1401), cut + np.array([-1e-9, -1e-6, -0.01, 0.0, 1e-9, 1e-6, 0.01, 0.5])])
+    got = ctx.boys(T, mmax, uqc.FP64)
+    ref = np.array([oracle.boys(mmax, t) for t in T])
+    rel = np.max(np.abs(got - ref) / ref)
+    assert rel <= 5e-14, rel
+
+
 def test_boys_fp32_matches_oracle(ctx):
     T = np.linspace(0, 30, 3001)
     got = ctx.boys(T, 8, uqc.MIXED)
