@@ -285,6 +285,33 @@ def spin_contamination(S, Pa, Pb, nalpha: int, nbeta: int) -> float:
     return sz * (sz + 1.0) + nbeta - float(np.sum((Pa @ S) * (Pb @ S).T))
 
 
+def mo_integrals_ovov(eri: np.ndarray, C: np.ndarray, nocc: int, nfrozen: int = 0) -> np.ndarray:
+    """(ia|jb) = sum_{mu nu lam sig} C_mu,i C_nu,a (mu nu|lam sig) C_lam,j C_sig,b for active occupied i, j
+    (nfrozen <= i < nocc) and virtual a, b (>= nocc): the four-index transformation written out, one index at a
+    time, from the AO tensor eri[mu, nu, lam, sig]."""
+    Co = C[:, nfrozen:nocc]
+    Cv = C[:, nocc:]
+    t = np.einsum("mi,mnls->inls", Co, eri, optimize=False)
+    t = np.einsum("na,inls->ials", Cv, t, optimize=False)
+    t = np.einsum("lj,ials->iajs", Co, t, optimize=False)
+    return np.einsum("sb,iajs->iajb", Cv, t, optimize=False)
+
+
+def mp2_closed_shell(ovov: np.ndarray, eps: np.ndarray, nocc: int, nfrozen: int = 0):
+    """Closed-shell second-order Moller-Plesset energy from canonical orbitals (Szabo-Ostlund Sec. 6.5, the
+    spin-adapted form the paper's MP2 follows): E2 = sum_{ijab} (ia|jb) [2 (ia|jb) - (ib|ja)] / D_ijab with
+    D_ijab = e_i + e_j - e_a - e_b.  Returns (E2, E_os, E_ss): E_os = sum (ia|jb)^2 / D (opposite spins),
+    E_ss = sum (ia|jb) [(ia|jb) - (ib|ja)] / D (same spins), E2 = E_os + E_ss."""
+    eo = eps[nfrozen:nocc]
+    ev = eps[nocc:]
+    D = eo[:, None, None, None] - ev[None, :, None, None] + eo[None, None, :, None] - ev[None, None, None, :]
+    V = ovov
+    Vx = V.transpose(0, 3, 2, 1)  # (ib|ja) at [i, a, j, b]
+    e_os = float(np.sum(V * V / D))
+    e_ss = float(np.sum(V * (V - Vx) / D))
+    return e_os + e_ss, e_os, e_ss
+
+
 def fock_parts(J: np.ndarray, K: np.ndarray, D: np.ndarray):
     """G = J - K/2 and E2 = 1/2 sum_ij D_ij G_ij."""
     G = J - 0.5 * K
