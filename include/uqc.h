@@ -206,6 +206,27 @@ uqc_status uqc_scf_uhf(uqc_basis* b, int natom, const double* Z, const double* R
                        const uqc_scf_opts* o, double* Pa, double* Pb, double* eps_a, double* eps_b,
                        uqc_scf_result* res);
 
+/* Closed-shell second-order Moller-Plesset correlation energy (the paper's MP2; spin-adapted form of Szabo-Ostlund
+ * Sec. 6.5) for canonical orbitals C (host, nbf*nbf row-major: C[mu*nbf + p] is the coefficient of basis function
+ * mu in orbital p) with energies eps (host, nbf, virtual ones above the occupied ones), nocc doubly occupied
+ * orbitals of which the first nfrozen are left out (frozen core, 0 <= nfrozen < nocc <= nbf):
+ *   E2 = sum_{ijab} (ia|jb) [2 (ia|jb) - (ib|ja)] / (e_i + e_j - e_a - e_b),
+ * i, j active occupied, a, b virtual.  The AO integrals are computed on the GPU (shell quartets with
+ * Q_ab Q_cd >= tau; tau = 0: all) into an nbf^4 tensor in device memory and transformed to (ia|jb) by four GEMMs;
+ * the call needs about 8 (nbf^4 + o nbf^3 + o v nbf^2) bytes of free device memory (o active occupied, v virtual
+ * orbitals; e.g. 19 GB at nbf = 220) and fails with UQC_E_NOMEM otherwise.  `res` may be NULL.
+ * Errors: UQC_E_ARG, UQC_E_NOMEM, UQC_E_DEVICE. */
+typedef struct {
+    double e2;               /* correlation energy (hartree) */
+    double e_os, e_ss;       /* opposite-spin part sum (ia|jb)^2 / D and same-spin part, e2 = e_os + e_ss */
+    long long quartets;      /* canonical shell quartets computed for the AO tensor */
+    double ao_ms, transform_ms, energy_ms, ms;   /* wall time of the stages and of the call */
+    double transform_flops;  /* 2 (o nbf^4 + o v nbf^3 + o v^2 nbf^2 + o^2 v^2 nbf) */
+} uqc_mp2_result;
+
+uqc_status uqc_mp2(uqc_basis* b, const double* C, const double* eps, int nocc, int nfrozen, double tau,
+                   uqc_mp2_result* res);
+
 /* Device Boys function, for verification: F_0..F_mmax (mmax <= 8) at n arguments T (host arrays; out is
  * n*(mmax+1), row-major).  precision UQC_FP64: tabulated Taylor grid + downward recursion (asymptotic form with
  * upward recursion beyond the grid); UQC_MIXED: the FP32 evaluation used for T <= 30 in mixed mode. */

@@ -117,6 +117,10 @@ struct uqc_basis {
 
 uqc::Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st);
 
+typedef struct _rocblas_handle* rocblas_handle;
+
 namespace uqc {
 bool is_device_ptr(const void* p);  // device or managed memory (false for host memory and null)
+// The context's rocBLAS handle (created on first use), bound to the context's stream, host pointer mode.
+uqc_status ensure_blas(uqc_ctx* ctx, rocblas_handle* out);
 }

@@ -47,6 +47,9 @@ static hipError_t launch_list_cls(bool mixed, int mode, const ListDev& L, const 
     if (mode == MODE_SCHWARZ)
         hipLaunchKernelGGL((k_list<UQC_LA, UQC_LB, UQC_LC, UQC_LD, false, MODE_SCHWARZ>), dim3(nblocks),
                            dim3(kBlock), 0, s, L, b64, b32);
+    else if (mode == MODE_SCATTER)
+        hipLaunchKernelGGL((k_list<UQC_LA, UQC_LB, UQC_LC, UQC_LD, false, MODE_SCATTER>), dim3(nblocks),
+                           dim3(kBlock), 0, s, L, b64, b32);
     else if (mixed)
         hipLaunchKernelGGL((k_list<UQC_LA, UQC_LB, UQC_LC, UQC_LD, true, MODE_STORE>), dim3(nblocks), dim3(kBlock), 0,
                            s, L, b64, b32);

@@ -499,7 +499,32 @@ __global__ __launch_bounds__(kBlock) void k_list(ListDev L, const double* __rest
     double out[NOUT];
     C::hrr(acc, L.bra.AB[bra], L.bra.AB[L.bra.np + bra], L.bra.AB[2 * L.bra.np + bra], L.ket.AB[ket],
            L.ket.AB[L.ket.np + ket], L.ket.AB[2 * L.ket.np + ket], out);
-    if constexpr (MODE == MODE_STORE) {
+    if constexpr (MODE == MODE_SCATTER) {
+        const size_t N = (size_t)L.nbf;
+        const size_t oa = L.bra.off_a[bra], ob = L.bra.off_b[bra], oc = L.ket.off_a[ket], od = L.ket.off_b[ket];
+        double* T = L.out;
+#pragma unroll
+        for (int i = 0; i < C::NA; ++i)
+#pragma unroll
+            for (int j = 0; j < C::NB; ++j)
+#pragma unroll
+                for (int k = 0; k < C::NC; ++k)
+#pragma unroll
+                    for (int l = 0; l < C::ND; ++l) {
+                        const int x = ((i * C::NB + j) * C::NC + k) * C::ND + l;
+                        const double v = out[x] * (comp_factor(LA, i) * comp_factor(LB, j) * comp_factor(LC, k) *
+                                                   comp_factor(LD, l));
+                        const size_t a = oa + i, b = ob + j, c = oc + k, d = od + l;
+                        T[((a * N + b) * N + c) * N + d] = v;
+                        T[((b * N + a) * N + c) * N + d] = v;
+                        T[((a * N + b) * N + d) * N + c] = v;
+                        T[((b * N + a) * N + d) * N + c] = v;
+                        T[((c * N + d) * N + a) * N + b] = v;
+                        T[((d * N + c) * N + a) * N + b] = v;
+                        T[((c * N + d) * N + b) * N + a] = v;
+                        T[((d * N + c) * N + b) * N + a] = v;
+                    }
+    } else if constexpr (MODE == MODE_STORE) {
         double* o = L.out + (size_t)q * NOUT;
 #pragma unroll
         for (int i = 0; i < C::NA; ++i)

@@ -86,10 +86,13 @@ struct ListDev {
     const int* bra_idx;
     const int* ket_idx;
     int n;
-    double* out;               // STORE: [n][NA*NB*NC*ND]; SCHWARZ: [n]
+    double* out;               // STORE: [n][NA*NB*NC*ND]; SCHWARZ: [n]; SCATTER: the nbf^4 tensor (see Mode)
+    int nbf;                   // SCATTER only
 };
 
-enum Mode { MODE_STORE = 0, MODE_SCHWARZ = 1 };
+// STORE: each quartet's block; SCHWARZ: sqrt of the largest diagonal element; SCATTER: every element of the block
+// written to the dense tensor out[((i nbf + j) nbf + k) nbf + l] at its eight permutationally equivalent places.
+enum Mode { MODE_STORE = 0, MODE_SCHWARZ = 1, MODE_SCATTER = 2 };
 
 // Host launchers of one angular-momentum class (defined in uqc_eri_class.hip, one object per class).
 struct ClassLaunchers {

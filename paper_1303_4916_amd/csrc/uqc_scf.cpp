@@ -30,6 +30,21 @@ void release_blas(uqc_ctx* c) {
     }
 }
 
+uqc_status uqc::ensure_blas(uqc_ctx* ctx, rocblas_handle* out) {
+    if (!ctx->blas) {
+        rocblas_handle h;
+        if (rocblas_create_handle(&h) != rocblas_status_success)
+            return uqc_fail(UQC_E_DEVICE, "rocblas_create_handle failed");
+        ctx->blas = h;
+    }
+    rocblas_handle h = (rocblas_handle)ctx->blas;
+    if (rocblas_set_stream(h, ctx->stream) != rocblas_status_success ||
+        rocblas_set_pointer_mode(h, rocblas_pointer_mode_host) != rocblas_status_success)
+        return uqc_fail(UQC_E_DEVICE, "rocBLAS stream or pointer mode could not be set");
+    *out = h;
+    return UQC_OK;
+}
+
 #define UQC_BLAS(expr)                                                                                   \
     do {                                                                                                 \
         rocblas_status b_ = (expr);                                                                      \
@@ -226,14 +241,11 @@ static uqc_status scf_run(uqc_basis* B, int natom, const double* Z, const double
     uqc_ctx* ctx = B->ctx;
     UQC_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
-    if (!ctx->blas) {
-        rocblas_handle h;
-        UQC_BLAS(rocblas_create_handle(&h));
-        ctx->blas = h;
+    rocblas_handle h = nullptr;
+    {
+        const uqc_status sb = ensure_blas(ctx, &h);
+        if (sb != UQC_OK) return sb;
     }
-    rocblas_handle h = (rocblas_handle)ctx->blas;
-    UQC_BLAS(rocblas_set_stream(h, s));
-    UQC_BLAS(rocblas_set_pointer_mode(h, rocblas_pointer_mode_host));
 
     const size_t NN = (size_t)N * N;
     const int m_max = o.diis_size;

@@ -51,6 +51,7 @@ def test_null_arguments_rejected_before_device_use():
     assert L.uqc_scf_rhf(None, 0, None, None, 1, None, None, None, None) == uqc.UQC_E_ARG
     assert L.uqc_fock_build_uhf(None, None, None, None, None, None, None, None, None, None) == uqc.UQC_E_ARG
     assert L.uqc_scf_uhf(None, 0, None, None, 1, 0, None, None, None, None, None, None) == uqc.UQC_E_ARG
+    assert L.uqc_mp2(None, None, None, 1, 0, 0.0, None) == uqc.UQC_E_ARG
     o = uqc.scf_opts()
     assert o.max_iter == 100 and o.e_conv == 1e-10 and o.d_conv == 1e-8 and o.diis_size == 8
     assert o.guess_mix == 0.0
@@ -78,6 +79,7 @@ def test_struct_layouts_match_header(tmp_path):
               "uqc_stats": (uqc.Stats, [f for f, _ in uqc.Stats._fields_]),
               "uqc_scf_opts": (uqc.ScfOpts, [f for f, _ in uqc.ScfOpts._fields_]),
               "uqc_scf_result": (uqc.ScfResult, [f for f, _ in uqc.ScfResult._fields_]),
+              "uqc_mp2_result": (uqc.Mp2Result, [f for f, _ in uqc.Mp2Result._fields_]),
               "uqc_request": (uqc.Request, [f for f, _ in uqc.Request._fields_]),
               "uqc_result": (uqc.Result, [f for f, _ in uqc.Result._fields_])}
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "uqc.h"', "int main(void) {"]
