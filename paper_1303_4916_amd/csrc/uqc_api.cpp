@@ -631,11 +631,11 @@ uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* n
         }
         for (int i = 0; i < bn.np; ++i) B->qmax = std::max(B->qmax, bn.Q[i]);
     }
-    // workspace: f[nbf], D', J, K accumulators, E2 + symmetry scalars, host-pointer staging for D, J, K, G, and the
-    // second spin's D' and K accumulator
+    // workspace: f[nbf], D', J, K accumulators, E2 + symmetry scalars, host-pointer staging for D, J, K, G, and for
+    // spin-density builds the second spin's D' and K accumulator and the total D' of the J pass
     {
         const size_t N = B->nbf, NN = N * N;
-        const size_t bytes = (N + 3 * NN + 8 + 4 * NN + 2 * NN) * sizeof(double);
+        const size_t bytes = (N + 3 * NN + 8 + 4 * NN + 3 * NN) * sizeof(double);
         if (hipMalloc(&B->d_work, bytes) != hipSuccess) {
             delete B;
             return uqc_fail(UQC_E_NOMEM, "basis: workspace allocation failed");
@@ -649,6 +649,7 @@ uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* n
         B->d_io = B->d_scal + 8;
         B->d_Dp2 = B->d_io + 4 * NN;
         B->d_K2 = B->d_Dp2 + NN;
+        B->d_Dp3 = B->d_K2 + NN;
         B->work_bytes = bytes;
         if (hipMemcpy(B->d_f, B->fcomp.data(), N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
             delete B;
@@ -862,6 +863,9 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
         d.D = B->d_Dp;
         d.J = B->d_J;
         d.K = B->d_K;
+        d.DJ = B->d_Dp3;
+        d.D2 = B->d_Dp2;
+        d.K2 = B->d_K2;
         d.nbf = B->nbf;
     }
     size_t oi = 0;
@@ -1052,8 +1056,8 @@ uqc_status uqc_eri_block(uqc_basis* B, int a, int b, int c, int d, int precision
 
 // ---------------------------------------------------------------------------------------------- Fock build
 // Fock build for one density (nspin = 1: out = {J, K, G}) or a pair of spin densities (nspin = 2:
-// out = {J, Ka, Kb, Ga, Gb}).  The second spin runs the class launches a second time over its own density, with the
-// J accumulator shared (J(Da) + J(Db) = J(Da + Db)) and the first spin's K accumulator set aside.
+// out = {J, Ka, Kb, Ga, Gb}).  With spin densities the class kernels evaluate every integral once and contract it
+// with the total density for J and with each spin density for its own K.
 static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, double* const* out,
                            const uqc_fock_opts* opts, uqc_stats* stats, const char* name) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -1115,6 +1119,10 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
             return uqc_fail(UQC_E_NOT_SYMMETRIC, nm + ": density is not symmetric (or not finite)");
     }
     UQC_HIP(launch_zero(B->d_J, 2 * NN, s));
+    if (nspin == 2) {
+        UQC_HIP(launch_zero(B->d_K2, NN, s));
+        UQC_HIP(launch_add(B->d_Dp, B->d_Dp2, B->d_Dp3, NN, s));
+    }
     const bool timing = o.timing != 0;
     std::vector<double> cls_ms(plan->groups.size(), 0.0);
     auto pass = [&]() -> uqc_status {
@@ -1127,8 +1135,8 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
             const int cid = la * 1000 + lb * 100 + lc * 10 + ld + (g.mixed ? 10000 : 0);
             for (long long i0 = 0; i0 < g.nitems; i0 += max_items) {
                 const long long n = std::min(max_items, g.nitems - i0);
-                UQC_HIP(launch_digest(g.cls, g.mixed, g.d_tasks, g.d_begin, g.ntask, i0, n, ctx->boys64, ctx->boys32,
-                                      s));
+                UQC_HIP(launch_digest(g.cls, g.mixed, nspin, g.d_tasks, g.d_begin, g.ntask, i0, n, ctx->boys64,
+                                      ctx->boys32, s));
                 if (o.progress) {
                     UQC_HIP(hipStreamSynchronize(s));
                     o.progress(o.progress_user, cid, i0 + n, g.nitems);
@@ -1148,12 +1156,7 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
     };
     if ((st = pass()) != UQC_OK) return st;
     if (nspin == 2) {
-        // first spin's K accumulator aside, second spin's density in place of the first
-        UQC_HIP(hipMemcpyAsync(B->d_K2, B->d_K, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
-        UQC_HIP(hipMemcpyAsync(B->d_Dp, B->d_Dp2, NN * sizeof(double), hipMemcpyDeviceToDevice, s));
-        UQC_HIP(launch_zero(B->d_K, NN, s));
-        if ((st = pass()) != UQC_OK) return st;
-        UQC_HIP(launch_finalize_uhf(Dd[0], Dd[1], B->d_J, B->d_K2, B->d_K, B->d_f, o.exchange_scale, Od[0], Od[1],
+        UQC_HIP(launch_finalize_uhf(Dd[0], Dd[1], B->d_J, B->d_K, B->d_K2, B->d_f, o.exchange_scale, Od[0], Od[1],
                                     Od[2], Od[3], Od[4], B->d_scal, (int)N, s));
     } else {
         UQC_HIP(launch_finalize(Dd[0], B->d_J, B->d_K, B->d_f, Od[0], Od[1], Od[2], o.exchange_scale, B->d_scal,

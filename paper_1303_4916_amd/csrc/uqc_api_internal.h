@@ -104,6 +104,7 @@ struct uqc_basis {
     size_t work_bytes = 0;
     double *d_f = nullptr, *d_Dp = nullptr, *d_J = nullptr, *d_K = nullptr, *d_scal = nullptr, *d_io = nullptr;
     double *d_Dp2 = nullptr, *d_K2 = nullptr;  // second spin density D' and K accumulator (spin-density builds)
+    double* d_Dp3 = nullptr;                     // spin-density builds: D'a + D'b, the density of the J pass
     double* d_uio = nullptr;                     // host-pointer staging of spin-density builds (7 nbf^2, on first use)
     // one-electron integrals: shell table and per-pair-class shell-pair lists (uploaded on first use), nuclei
     void* d_shells = nullptr;

@@ -15,28 +15,33 @@
 
 namespace uqc {
 
-static hipError_t launch_digest_cls(bool mixed, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
-                                    long long item0, long long nitems, const double* b64, const float* b32,
+template <bool MIXED, int NSPIN>
+static void launch_digest_one(unsigned nblocks, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
+                              long long item0, long long nitems, const double* b64, const float* b32, hipStream_t s) {
+#if UQC_TEAM
+    hipLaunchKernelGGL((k_digest_team<UQC_LA, UQC_LB, UQC_LC, UQC_LD, MIXED, NSPIN>), dim3(nblocks), dim3(kBlock), 0,
+                       s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32);
+#else
+    hipLaunchKernelGGL((k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, MIXED, NSPIN>), dim3(nblocks), dim3(kBlock), 0, s,
+                       d_tasks, d_task_begin, ntask, item0, nitems, b64, b32);
+#endif
+}
+
+static hipError_t launch_digest_cls(bool mixed, int nspin, const TaskDev* d_tasks, const long long* d_task_begin,
+                                    int ntask, long long item0, long long nitems, const double* b64, const float* b32,
                                     hipStream_t s) {
     const long long waves_per_block = kBlock / kWave;
     const long long nblocks = (nitems + waves_per_block - 1) / waves_per_block;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
-#if UQC_TEAM
-    if (mixed)
-        hipLaunchKernelGGL((k_digest_team<UQC_LA, UQC_LB, UQC_LC, UQC_LD, true>), dim3((unsigned)nblocks),
-                           dim3(kBlock), 0, s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32);
-    else
-        hipLaunchKernelGGL((k_digest_team<UQC_LA, UQC_LB, UQC_LC, UQC_LD, false>), dim3((unsigned)nblocks),
-                           dim3(kBlock), 0, s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32);
-#else
-    if (mixed)
-        hipLaunchKernelGGL((k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, true>), dim3((unsigned)nblocks), dim3(kBlock), 0,
-                           s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32);
-    else
-        hipLaunchKernelGGL((k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, false>), dim3((unsigned)nblocks), dim3(kBlock),
-                           0, s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32);
-#endif
+    const unsigned nb = (unsigned)nblocks;
+    if (nspin == 2) {
+        if (mixed) launch_digest_one<true, 2>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, s);
+        else launch_digest_one<false, 2>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, s);
+    } else {
+        if (mixed) launch_digest_one<true, 1>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, s);
+        else launch_digest_one<false, 1>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, s);
+    }
     return hipGetLastError();
 }
 

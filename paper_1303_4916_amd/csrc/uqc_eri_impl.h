@@ -245,7 +245,9 @@ constexpr bool kKacInLds = UQC_KAC_LDS != 0;
 // primitive sums, horizontal recursion, partial J/K sums.  Reductions: J_ab (one bra pair for all lanes) over the
 // wavefront, then one atomic add; K_ac and K_bc over each run of adjacent lanes sharing the first ket shell c,
 // then one atomic add per run; J_cd, K_ad (and K_bd) per lane.  Idle lanes compute a valid quartet with weight 0.
-template <int LA, int LB, int LC, int LD, bool MIXED>
+// NSPIN = 2 (spin densities): J from the total density, the K passes once per spin density into its own
+// accumulator, the integrals evaluated once.
+template <int LA, int LB, int LC, int LD, bool MIXED, int NSPIN>
 __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev* __restrict__ tasks,
                                                    const long long* __restrict__ task_begin, int ntask,
                                                    long long item0, long long nitems,
@@ -256,11 +258,13 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
     constexpr int NAB = NA * NB, NCD = NC * ND;
     // where the K_ad and K_ac sums of a same-a run are kept: 1 = registers, 2 = the lane's private LDS slots,
     // 0 = not kept (summed over the lanes of each c-run and added per bra pair)
-    constexpr int KAD_MODE = NCD + NA * ND <= kKeepLimit ? 1 : 2;
-    constexpr int KAC_MODE = (KAD_MODE == 1 && NCD + NA * ND + NA * NC <= kKeepLimit) ? 1 : (kKacInLds ? 2 : 0);
+    constexpr int KAD_MODE = NCD + NSPIN * NA * ND <= kKeepLimit ? 1 : 2;
+    constexpr int KAC_MODE =
+        (KAD_MODE == 1 && NCD + NSPIN * (NA * ND + NA * NC) <= kKeepLimit) ? 1 : (kKacInLds ? 2 : 0);
     constexpr bool KEEP_KAD = KAD_MODE != 0;
     constexpr bool KEEP_KAC = KAC_MODE != 0;
-    constexpr int SLOTS = (KAD_MODE == 2 ? NA * ND : 0) + (KAC_MODE == 2 ? NA * NC : 0);
+    constexpr int SLOTS1 = (KAD_MODE == 2 ? NA * ND : 0) + (KAC_MODE == 2 ? NA * NC : 0);  // per spin
+    constexpr int SLOTS = NSPIN * SLOTS1;
     __shared__ double slots[kBlock / kWave][SLOTS > 0 ? SLOTS * kWave : 1];
     const long long local = wave_item();
     if (local >= nitems) return;
@@ -281,9 +285,11 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
     const double* __restrict__ D = tk.D;
     // D is read-only while the kernel runs: read through the constant address space with 32-bit offsets (N < 2^16)
     const cdptr Dc = as_const(D);
+    const cdptr Dj = NSPIN == 2 ? as_const(tk.DJ) : Dc;  // density of the J pass
     double* __restrict__ J = tk.J;
-    double* __restrict__ K = tk.K;
     const int N = tk.nbf;
+    auto Dk = [&](int sp) { return sp == 0 ? Dc : as_const(tk.D2); };  // density of spin sp's K passes
+    auto Kp = [&](int sp) { return sp == 0 ? tk.K : tk.K2; };           // its accumulator
     // Only the ket index, its bound and the kept sums live across the loop; everything else about the ket is
     // re-read (from cache) through an index the compiler cannot see through, which keeps register use low.
     auto opaque = [](int x) {
@@ -306,51 +312,59 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
         run_last = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ULL);
     };
 
-    double jcd_s[NCD], kad_s[KAD_MODE == 1 ? NA * ND : 1], kac_s[KAC_MODE == 1 ? NA * NC : 1];
+    double jcd_s[NCD], kad_s[NSPIN][KAD_MODE == 1 ? NA * ND : 1], kac_s[NSPIN][KAC_MODE == 1 ? NA * NC : 1];
 #pragma unroll
     for (int x = 0; x < NCD; ++x) jcd_s[x] = 0.0;
 #pragma unroll
-    for (int x = 0; x < (KAD_MODE == 1 ? NA * ND : 1); ++x) kad_s[x] = 0.0;
+    for (int sp = 0; sp < NSPIN; ++sp) {
 #pragma unroll
-    for (int x = 0; x < (KAC_MODE == 1 ? NA * NC : 1); ++x) kac_s[x] = 0.0;
-    // LDS slots of this lane: slot x at kept[x * kWave] (lane-contiguous, no bank conflicts, private to the lane)
-    double* kept_ad = &slots[threadIdx.x / kWave][lane];
-    double* kept_ac = kept_ad + (KAD_MODE == 2 ? NA * ND * kWave : 0);
+        for (int x = 0; x < (KAD_MODE == 1 ? NA * ND : 1); ++x) kad_s[sp][x] = 0.0;
 #pragma unroll
-    for (int x = 0; x < SLOTS; ++x) kept_ad[x * kWave] = 0.0;
-    auto kad_get = [&](int x) -> double& {
-        if constexpr (KAD_MODE == 2) return kept_ad[x * kWave]; else return kad_s[x];
+        for (int x = 0; x < (KAC_MODE == 1 ? NA * NC : 1); ++x) kac_s[sp][x] = 0.0;
+    }
+    // LDS slots of this lane: slot x at kept[x * kWave] (lane-contiguous, no bank conflicts, private to the lane),
+    // spin sp's slots after those of the spins before it
+    double* kept0 = &slots[threadIdx.x / kWave][lane];
+#pragma unroll
+    for (int x = 0; x < SLOTS; ++x) kept0[x * kWave] = 0.0;
+    auto kad_get = [&](int sp, int x) -> double& {
+        if constexpr (KAD_MODE == 2) return kept0[(sp * SLOTS1 + x) * kWave]; else return kad_s[sp][x];
     };
-    auto kac_get = [&](int x) -> double& {
-        if constexpr (KAC_MODE == 2) return kept_ac[x * kWave]; else return kac_s[x];
+    auto kac_get = [&](int sp, int x) -> double& {
+        if constexpr (KAC_MODE == 2) return kept0[(sp * SLOTS1 + (KAD_MODE == 2 ? NA * ND : 0) + x) * kWave];
+        else return kac_s[sp][x];
     };
     int cur_a = -1;  // wavefront-uniform: first shell of the bra pairs whose K_ad / K_ac sums are held
     auto flush_a = [&]() {
         const int kl = opaque(kc);
         const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
-        if constexpr (KEEP_KAD) {
+        bool inseg[6], run_last;
+        if constexpr (KEEP_KAC) runs(oc, inseg, run_last);
 #pragma unroll
-            for (int i = 0; i < NA; ++i)
+        for (int sp = 0; sp < NSPIN; ++sp) {
+            double* __restrict__ K = Kp(sp);
+            if constexpr (KEEP_KAD) {
 #pragma unroll
-                for (int l = 0; l < ND; ++l) {
-                    double& r = kad_get(i * ND + l);
-                    const double s = r;
-                    r = 0.0;
-                    if (s != 0.0) atomic_add(K + (size_t)(cur_a + i) * N + od + l, s);
-                }
-        }
-        if constexpr (KEEP_KAC) {
-            bool inseg[6], run_last;
-            runs(oc, inseg, run_last);
+                for (int i = 0; i < NA; ++i)
 #pragma unroll
-            for (int i = 0; i < NA; ++i)
+                    for (int l = 0; l < ND; ++l) {
+                        double& r = kad_get(sp, i * ND + l);
+                        const double s = r;
+                        r = 0.0;
+                        if (s != 0.0) atomic_add(K + (size_t)(cur_a + i) * N + od + l, s);
+                    }
+            }
+            if constexpr (KEEP_KAC) {
 #pragma unroll
-                for (int k = 0; k < NC; ++k) {
-                    double& r = kac_get(i * NC + k);
-                    const double s = seg_scan(r, inseg);
-                    r = 0.0;
-                    if (run_last && s != 0.0) atomic_add(K + (size_t)(cur_a + i) * N + oc + k, s);
-                }
+                for (int i = 0; i < NA; ++i)
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+                        double& r = kac_get(sp, i * NC + k);
+                        const double s = seg_scan(r, inseg);
+                        r = 0.0;
+                        if (run_last && s != 0.0) atomic_add(K + (size_t)(cur_a + i) * N + oc + k, s);
+                    }
+            }
         }
     };
     unsigned long long cnt = 0, pcnt = 0;
@@ -391,11 +405,11 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
 #pragma unroll
             for (int i = 0; i < NA; ++i)
 #pragma unroll
-                for (int j = 0; j < NB; ++j) dab[i * NB + j] = Dc[(unsigned)(oa + i) * (unsigned)N + (unsigned)(ob + j)];
+                for (int j = 0; j < NB; ++j) dab[i * NB + j] = Dj[(unsigned)(oa + i) * (unsigned)N + (unsigned)(ob + j)];
 #pragma unroll
             for (int k = 0; k < NC; ++k)
 #pragma unroll
-                for (int l = 0; l < ND; ++l) dcd[k * ND + l] = Dc[(unsigned)(oc + k) * (unsigned)N + (unsigned)(od + l)];
+                for (int l = 0; l < ND; ++l) dcd[k * ND + l] = Dj[(unsigned)(oc + k) * (unsigned)N + (unsigned)(od + l)];
             contract_pair<NA, NB, NC, ND, 0>(out, dcd, dab, jab, jcd);
 #pragma unroll
             for (int x = 0; x < NAB; ++x) {
@@ -407,64 +421,69 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
         }
         bool inseg[6], run_last;
         runs(oc, inseg, run_last);
-        {
-            double dbd[NB * ND], dac[NA * NC], kac[NA * NC], kbd[NB * ND];
 #pragma unroll
-            for (int j = 0; j < NB; ++j)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) dbd[j * ND + l] = Dc[(unsigned)(ob + j) * (unsigned)N + (unsigned)(od + l)];
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int k = 0; k < NC; ++k) dac[i * NC + k] = Dc[(unsigned)(oa + i) * (unsigned)N + (unsigned)(oc + k)];
-            contract_pair<NA, NB, NC, ND, 1>(out, dbd, dac, kac, kbd);
-            if constexpr (KEEP_KAC) {
-#pragma unroll
-                for (int x = 0; x < NA * NC; ++x) kac_get(x) += w * kac[x];
-            } else {
-#pragma unroll
-                for (int i = 0; i < NA; ++i)
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) {
-                        const double s = seg_scan(w * kac[i * NC + k], inseg);
-                        if (run_last && s != 0.0) atomic_add(K + (size_t)(oa + i) * N + oc + k, s);
-                    }
-            }
-            if (act) {
+        for (int sp = 0; sp < NSPIN; ++sp) {
+            const cdptr Ds = Dk(sp);
+            double* __restrict__ K = Kp(sp);
+            {
+                double dbd[NB * ND], dac[NA * NC], kac[NA * NC], kbd[NB * ND];
 #pragma unroll
                 for (int j = 0; j < NB; ++j)
 #pragma unroll
-                    for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(ob + j) * N + od + l, w * kbd[j * ND + l]);
-            }
-        }
-        {
-            double dbc[NB * NC], dad[NA * ND], kad[NA * ND], kbc[NB * NC];
-#pragma unroll
-            for (int j = 0; j < NB; ++j)
-#pragma unroll
-                for (int k = 0; k < NC; ++k) dbc[j * NC + k] = Dc[(unsigned)(ob + j) * (unsigned)N + (unsigned)(oc + k)];
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) dad[i * ND + l] = Dc[(unsigned)(oa + i) * (unsigned)N + (unsigned)(od + l)];
-            contract_pair<NA, NB, NC, ND, 2>(out, dbc, dad, kad, kbc);
-#pragma unroll
-            for (int j = 0; j < NB; ++j)
-#pragma unroll
-                for (int k = 0; k < NC; ++k) {
-                    const double s = seg_scan(w * kbc[j * NC + k], inseg);
-                    if (run_last && s != 0.0) atomic_add(K + (size_t)(ob + j) * N + oc + k, s);
-                }
-            if constexpr (KEEP_KAD) {
-#pragma unroll
-                for (int x = 0; x < NA * ND; ++x) kad_get(x) += w * kad[x];
-            } else if (act) {
+                    for (int l = 0; l < ND; ++l) dbd[j * ND + l] = Ds[(unsigned)(ob + j) * (unsigned)N + (unsigned)(od + l)];
 #pragma unroll
                 for (int i = 0; i < NA; ++i)
 #pragma unroll
-                    for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(oa + i) * N + od + l, w * kad[i * ND + l]);
+                    for (int k = 0; k < NC; ++k) dac[i * NC + k] = Ds[(unsigned)(oa + i) * (unsigned)N + (unsigned)(oc + k)];
+                contract_pair<NA, NB, NC, ND, 1>(out, dbd, dac, kac, kbd);
+                if constexpr (KEEP_KAC) {
+#pragma unroll
+                    for (int x = 0; x < NA * NC; ++x) kac_get(sp, x) += w * kac[x];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < NA; ++i)
+#pragma unroll
+                        for (int k = 0; k < NC; ++k) {
+                            const double s = seg_scan(w * kac[i * NC + k], inseg);
+                            if (run_last && s != 0.0) atomic_add(K + (size_t)(oa + i) * N + oc + k, s);
+                        }
+                }
+                if (act) {
+#pragma unroll
+                    for (int j = 0; j < NB; ++j)
+#pragma unroll
+                        for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(ob + j) * N + od + l, w * kbd[j * ND + l]);
+                }
             }
-        }
+            {
+                double dbc[NB * NC], dad[NA * ND], kad[NA * ND], kbc[NB * NC];
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) dbc[j * NC + k] = Ds[(unsigned)(ob + j) * (unsigned)N + (unsigned)(oc + k)];
+#pragma unroll
+                for (int i = 0; i < NA; ++i)
+#pragma unroll
+                    for (int l = 0; l < ND; ++l) dad[i * ND + l] = Ds[(unsigned)(oa + i) * (unsigned)N + (unsigned)(od + l)];
+                contract_pair<NA, NB, NC, ND, 2>(out, dbc, dad, kad, kbc);
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+                        const double s = seg_scan(w * kbc[j * NC + k], inseg);
+                        if (run_last && s != 0.0) atomic_add(K + (size_t)(ob + j) * N + oc + k, s);
+                    }
+                if constexpr (KEEP_KAD) {
+#pragma unroll
+                    for (int x = 0; x < NA * ND; ++x) kad_get(sp, x) += w * kad[x];
+                } else if (act) {
+#pragma unroll
+                    for (int i = 0; i < NA; ++i)
+#pragma unroll
+                        for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(oa + i) * N + od + l, w * kad[i * ND + l]);
+                }
+            }
+        }  // spins
     }
     if (cur_a >= 0) flush_a();
     {

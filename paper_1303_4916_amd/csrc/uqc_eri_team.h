@@ -103,23 +103,26 @@ __device__ __forceinline__ void team_accumulate(const BinDev& B, int bra, int kb
 // Streaming digest of one lane (classes with too many outputs to hold): all six density slices gathered in the
 // lane's frame, every output digested into the six partial blocks as it is formed, then the blocks added into the
 // team's LDS block at the true component indices.
+// The J slices come from DjC (J added to the team's blocks only if with_j), the K slices from DkC.
 template <class TC, int LA, int LB, int LC, int LD>
 __device__ __forceinline__ void team_digest_stream(const double* acc, const int* src, int pidx, double w, cdptr bh,
-                                                   const BinDev& Kt, int kl, int q0, int q1, int q2, cdptr Dc, int N,
-                                                   int oa, int ob, int oc, int od, const int* pcA, const int* pcB,
-                                                   const int* pcC, const int* pcD, double* t_jab, double* t_jcd,
-                                                   double* t_kac, double* t_kad, double* t_kbc, double* t_kbd) {
+                                                   const BinDev& Kt, int kl, int q0, int q1, int q2, cdptr DjC,
+                                                   cdptr DkC, bool with_j, int N, int oa, int ob, int oc, int od,
+                                                   const int* pcA, const int* pcB, const int* pcC, const int* pcD,
+                                                   double* t_jab, double* t_jcd, double* t_kac, double* t_kad,
+                                                   double* t_kbc, double* t_kbd) {
     constexpr int NA = TC::NA, NB = TC::NB, NC = TC::NC, ND = TC::ND;
-    auto Dp = [&](int r, int c) { return Dc[(unsigned)r * (unsigned)N + (unsigned)c]; };
+    auto Dp = [&](int r, int c) { return DkC[(unsigned)r * (unsigned)N + (unsigned)c]; };
+    auto Dq = [&](int r, int c) { return with_j ? DjC[(unsigned)r * (unsigned)N + (unsigned)c] : 0.0; };
     double dab[NA * NB], dcd[NC * ND], dbd[NB * ND], dbc[NB * NC], dad[NA * ND], dac[NA * NC];
 #pragma unroll
     for (int i = 0; i < NA; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) dab[i * NB + j] = Dp(oa + pcA[i], ob + pcB[j]);
+        for (int j = 0; j < NB; ++j) dab[i * NB + j] = Dq(oa + pcA[i], ob + pcB[j]);
 #pragma unroll
     for (int k = 0; k < NC; ++k)
 #pragma unroll
-        for (int l = 0; l < ND; ++l) dcd[k * ND + l] = Dp(oc + pcC[k], od + pcD[l]);
+        for (int l = 0; l < ND; ++l) dcd[k * ND + l] = Dq(oc + pcC[k], od + pcD[l]);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
 #pragma unroll
@@ -154,14 +157,16 @@ __device__ __forceinline__ void team_digest_stream(const double* acc, const int*
     const double CDz = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q2);
     TC::hrr_digest(acc, src, pidx, w, ABx, ABy, ABz, CDx, CDy, CDz, dab, dcd, dbd, dbc, dad, dac, jab, jcd, kac, kad,
                    kbc, kbd);
+    if (with_j) {
 #pragma unroll
-    for (int i = 0; i < NA; ++i)
+        for (int i = 0; i < NA; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j) atomic_add_lds(t_jab + pcA[i] * NB + pcB[j], jab[i * NB + j]);
+            for (int j = 0; j < NB; ++j) atomic_add_lds(t_jab + pcA[i] * NB + pcB[j], jab[i * NB + j]);
 #pragma unroll
-    for (int k = 0; k < NC; ++k)
+        for (int k = 0; k < NC; ++k)
 #pragma unroll
-        for (int l = 0; l < ND; ++l) atomic_add_lds(t_jcd + pcC[k] * ND + pcD[l], jcd[k * ND + l]);
+            for (int l = 0; l < ND; ++l) atomic_add_lds(t_jcd + pcC[k] * ND + pcD[l], jcd[k * ND + l]);
+    }
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
 #pragma unroll
@@ -178,7 +183,9 @@ __device__ __forceinline__ void team_digest_stream(const double* acc, const int*
     }
 }
 
-template <int LA, int LB, int LC, int LD, bool MIXED>
+// NSPIN = 2 (spin densities): J from the total density, K_ac, K_ad, K_bc, K_bd once per spin density into its
+// own LDS blocks and accumulator.
+template <int LA, int LB, int LC, int LD, bool MIXED, int NSPIN>
 __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const TaskDev* __restrict__ tasks,
                                                         const long long* __restrict__ task_begin, int ntask,
                                                         long long item0, long long nitems,
@@ -187,10 +194,12 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
     using TC = TeamClass<LA, LB, LC, LD>;
     constexpr int NA = TC::NA, NB = TC::NB, NC = TC::NC, ND = TC::ND;
     constexpr int NAB = NA * NB, NCD = NC * ND;
-    // per-team partial blocks: J_cd, K_ac, K_ad, K_bc, K_bd, J_ab (J_ab summed over the teams when flushed); the
-    // team stride is padded to 1 mod 32 doubles, so the same entry of different teams falls in different LDS banks
+    // per-team partial blocks: J_cd, then per spin K_ac, K_ad, K_bc, K_bd, then J_ab (J_ab summed over the teams
+    // when flushed); the team stride is padded to 1 mod 32 doubles, so the same entry of different teams falls in
+    // different LDS banks
+    constexpr int KSZ = NA * NC + NA * ND + NB * NC + NB * ND;  // K blocks of one spin
     constexpr int R_JCD = 0, R_KAC = NCD, R_KAD = R_KAC + NA * NC, R_KBC = R_KAD + NA * ND, R_KBD = R_KBC + NB * NC;
-    constexpr int R_JAB = R_KBD + NB * ND;
+    constexpr int R_JAB = NCD + NSPIN * KSZ;
     constexpr int R = R_JAB + NAB;
     constexpr int RS = R + ((33 - R % 32) % 32);
     constexpr int WAVE_LDS = (kTeamsPerWave + 1) * RS;
@@ -217,9 +226,11 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
     const double* __restrict__ D = tk.D;
     // D is read-only while the kernel runs: read through the constant address space with 32-bit offsets (N < 2^16)
     const cdptr Dc = as_const(D);
+    const cdptr Dj = NSPIN == 2 ? as_const(tk.DJ) : Dc;  // density of the J pass
     double* __restrict__ J = tk.J;
-    double* __restrict__ K = tk.K;
     const int N = tk.nbf;
+    auto Dk = [&](int sp) { return sp == 0 ? Dc : as_const(tk.D2); };  // density of spin sp's K passes
+    auto Kp = [&](int sp) { return sp == 0 ? tk.K : tk.K2; };           // its accumulator
     // Only the ket index and its bound live across the loop; the ket's data, the lane's permutation tables and
     // the density blocks are re-read per bra pair through values the compiler cannot see through, which keeps
     // register use (and spills) down.
@@ -232,20 +243,24 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
     for (int x = lane; x < WAVE_LDS; x += kWave) my[x] = 0.0;
     wave_lds_sync();
     double* tm = my + team * RS;
-    // flush of the team's partial sums in [e0, e1) of its LDS block (each entry by one lane of the team), then zero
-    auto flush = [&](int e0, int e1, int oa, int ob) {
+    // flush of the team's partial sums in [e0, e1) of its LDS block (each entry by one lane of the team), then zero;
+    // the range lies inside J_cd or inside one spin's K blocks (spin sp: offsets shifted by sp * KSZ)
+    auto flush = [&](int e0, int e1, int oa, int ob, int sp) {
         const int kl = opaque(kc);
         const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
+        double* __restrict__ K = Kp(sp);
+        const int sh = sp * KSZ;
         if (team < kTeamsPerWave) {
             for (int e = e0 + lane - team * kTeam; e < e1; e += kTeam) {
                 const double s = tm[e];
                 tm[e] = 0.0;
                 if (s == 0.0) continue;
+                const int u = e - sh;
                 if (e < R_KAC) atomic_add(J + (size_t)(oc + e / ND) * N + od + e % ND, 2.0 * s);
-                else if (e < R_KAD) atomic_add(K + (size_t)(oa + (e - R_KAC) / NC) * N + oc + (e - R_KAC) % NC, s);
-                else if (e < R_KBC) atomic_add(K + (size_t)(oa + (e - R_KAD) / ND) * N + od + (e - R_KAD) % ND, s);
-                else if (e < R_KBD) atomic_add(K + (size_t)(ob + (e - R_KBC) / NC) * N + oc + (e - R_KBC) % NC, s);
-                else atomic_add(K + (size_t)(ob + (e - R_KBD) / ND) * N + od + (e - R_KBD) % ND, s);
+                else if (u < R_KAD) atomic_add(K + (size_t)(oa + (u - R_KAC) / NC) * N + oc + (u - R_KAC) % NC, s);
+                else if (u < R_KBC) atomic_add(K + (size_t)(oa + (u - R_KAD) / ND) * N + od + (u - R_KAD) % ND, s);
+                else if (u < R_KBD) atomic_add(K + (size_t)(ob + (u - R_KBC) / NC) * N + oc + (u - R_KBC) % NC, s);
+                else atomic_add(K + (size_t)(ob + (u - R_KBD) / ND) * N + od + (u - R_KBD) % ND, s);
             }
         }
     };
@@ -265,7 +280,8 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
         const int oa = ((ciptr)(bh + 5))[0], ob = ((ciptr)(bh + 5))[1];
         if (oa != cur_a) {
             if (cur_a >= 0) {
-                flush(R_KAC, R_KBC, cur_a, 0);
+#pragma unroll
+                for (int sp = 0; sp < NSPIN; ++sp) flush(R_KAC + sp * KSZ, R_KBC + sp * KSZ, cur_a, 0, sp);
                 wave_lds_sync();
             }
             cur_a = oa;
@@ -294,9 +310,14 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
         double w = act ? bh[3] * Kt.sdeg[kl] : 0.0;
         if (tk.same && ket == bra) w *= 0.5;
         if constexpr (TC::STREAM) {
-            team_digest_stream<TC, LA, LB, LC, LD>(acc, src, pidx, w, bh, Kt, kl, q0, q1, q2, Dc, N, oa, ob, oc, od,
-                                                   pcA, pcB, pcC, pcD, tm + R_JAB, tm + R_JCD, tm + R_KAC,
-                                                   tm + R_KAD, tm + R_KBC, tm + R_KBD);
+#pragma unroll
+            for (int sp = 0; sp < NSPIN; ++sp) {
+                const int sh = sp * KSZ;
+                team_digest_stream<TC, LA, LB, LC, LD>(acc, src, pidx, w, bh, Kt, kl, q0, q1, q2, Dj, Dk(sp), sp == 0,
+                                                       N, oa, ob, oc, od, pcA, pcB, pcC, pcD, tm + R_JAB, tm + R_JCD,
+                                                       tm + R_KAC + sh, tm + R_KAD + sh, tm + R_KBC + sh,
+                                                       tm + R_KBD + sh);
+            }
         } else {
         double out[TC::NOUT];
         {
@@ -310,17 +331,17 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
         }
         // Digest in three passes (J_ab with J_cd; K_ac with K_bd; K_ad with K_bc), each gathering its two density
         // slices in the lane's frame and adding its two partial blocks into LDS at the true component indices.
-        auto Dp = [&](int r, int c) { return Dc[(unsigned)r * (unsigned)N + (unsigned)c]; };
+        auto Dq = [&](int r, int c) { return Dj[(unsigned)r * (unsigned)N + (unsigned)c]; };
         {
             double d1[NCD], d2[NAB], x[NAB], y[NCD];
 #pragma unroll
             for (int k = 0; k < NC; ++k)
 #pragma unroll
-                for (int l = 0; l < ND; ++l) d1[k * ND + l] = Dp(oc + pcC[k], od + pcD[l]);
+                for (int l = 0; l < ND; ++l) d1[k * ND + l] = Dq(oc + pcC[k], od + pcD[l]);
 #pragma unroll
             for (int i = 0; i < NA; ++i)
 #pragma unroll
-                for (int j = 0; j < NB; ++j) d2[i * NB + j] = Dp(oa + pcA[i], ob + pcB[j]);
+                for (int j = 0; j < NB; ++j) d2[i * NB + j] = Dq(oa + pcA[i], ob + pcB[j]);
             TC::digest0(out, d1, d2, x, y);
 #pragma unroll
             for (int i = 0; i < NA; ++i)
@@ -331,46 +352,52 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
 #pragma unroll
                 for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_JCD + pcC[k] * ND + pcD[l], y[k * ND + l]);
         }
-        {
-            double d1[NB * ND], d2[NA * NC], x[NA * NC], y[NB * ND];
 #pragma unroll
-            for (int j = 0; j < NB; ++j)
+        for (int sp = 0; sp < NSPIN; ++sp) {
+            const cdptr Dsp = Dk(sp);
+            auto Ds = [&](int r, int c) { return Dsp[(unsigned)r * (unsigned)N + (unsigned)c]; };
+            const int sh = sp * KSZ;
+            {
+                double d1[NB * ND], d2[NA * NC], x[NA * NC], y[NB * ND];
 #pragma unroll
-                for (int l = 0; l < ND; ++l) d1[j * ND + l] = Dp(ob + pcB[j], od + pcD[l]);
+                for (int j = 0; j < NB; ++j)
 #pragma unroll
-            for (int i = 0; i < NA; ++i)
+                    for (int l = 0; l < ND; ++l) d1[j * ND + l] = Ds(ob + pcB[j], od + pcD[l]);
 #pragma unroll
-                for (int k = 0; k < NC; ++k) d2[i * NC + k] = Dp(oa + pcA[i], oc + pcC[k]);
-            TC::digest1(out, d1, d2, x, y);
+                for (int i = 0; i < NA; ++i)
 #pragma unroll
-            for (int i = 0; i < NA; ++i)
+                    for (int k = 0; k < NC; ++k) d2[i * NC + k] = Ds(oa + pcA[i], oc + pcC[k]);
+                TC::digest1(out, d1, d2, x, y);
 #pragma unroll
-                for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KAC + pcA[i] * NC + pcC[k], x[i * NC + k]);
+                for (int i = 0; i < NA; ++i)
 #pragma unroll
-            for (int j = 0; j < NB; ++j)
+                    for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KAC + sh + pcA[i] * NC + pcC[k], x[i * NC + k]);
 #pragma unroll
-                for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KBD + pcB[j] * ND + pcD[l], y[j * ND + l]);
-        }
-        {
-            double d1[NB * NC], d2[NA * ND], x[NA * ND], y[NB * NC];
+                for (int j = 0; j < NB; ++j)
 #pragma unroll
-            for (int j = 0; j < NB; ++j)
+                    for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KBD + sh + pcB[j] * ND + pcD[l], y[j * ND + l]);
+            }
+            {
+                double d1[NB * NC], d2[NA * ND], x[NA * ND], y[NB * NC];
 #pragma unroll
-                for (int k = 0; k < NC; ++k) d1[j * NC + k] = Dp(ob + pcB[j], oc + pcC[k]);
+                for (int j = 0; j < NB; ++j)
 #pragma unroll
-            for (int i = 0; i < NA; ++i)
+                    for (int k = 0; k < NC; ++k) d1[j * NC + k] = Ds(ob + pcB[j], oc + pcC[k]);
 #pragma unroll
-                for (int l = 0; l < ND; ++l) d2[i * ND + l] = Dp(oa + pcA[i], od + pcD[l]);
-            TC::digest2(out, d1, d2, x, y);
+                for (int i = 0; i < NA; ++i)
 #pragma unroll
-            for (int i = 0; i < NA; ++i)
+                    for (int l = 0; l < ND; ++l) d2[i * ND + l] = Ds(oa + pcA[i], od + pcD[l]);
+                TC::digest2(out, d1, d2, x, y);
 #pragma unroll
-                for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KAD + pcA[i] * ND + pcD[l], x[i * ND + l]);
+                for (int i = 0; i < NA; ++i)
 #pragma unroll
-            for (int j = 0; j < NB; ++j)
+                    for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KAD + sh + pcA[i] * ND + pcD[l], x[i * ND + l]);
 #pragma unroll
-                for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KBC + pcB[j] * NC + pcC[k], y[j * NC + k]);
-        }
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KBC + sh + pcB[j] * NC + pcC[k], y[j * NC + k]);
+            }
+        }  // spins
         }
         wave_lds_sync();
         // J_ab by the wavefront and the K_bc / K_bd blocks of this bra pair by each team, then cleared
@@ -383,10 +410,16 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
             }
             if (s != 0.0) atomic_add(J + (size_t)(oa + lane / NB) * N + ob + lane % NB, 2.0 * s);
         }
-        flush(R_KBC, R_JAB, oa, ob);
+#pragma unroll
+        for (int sp = 0; sp < NSPIN; ++sp)
+            flush(R_KBC + sp * KSZ, R_KBC + sp * KSZ + NB * NC + NB * ND, oa, ob, sp);
         wave_lds_sync();
     }
-    if (cur_a >= 0) flush(R_JCD, R_KBC, cur_a, 0);
+    if (cur_a >= 0) {
+        flush(R_JCD, R_KAC, cur_a, 0, 0);
+#pragma unroll
+        for (int sp = 0; sp < NSPIN; ++sp) flush(R_KAC + sp * KSZ, R_KBC + sp * KSZ, cur_a, 0, sp);
+    }
     if (lane == 0 && cnt) {
         atomicAdd(tk.count, cnt);
         atomicAdd(tk.pcount, pcnt);

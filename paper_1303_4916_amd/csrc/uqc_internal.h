@@ -74,9 +74,12 @@ struct TaskDev {
     unsigned long long* pcount;  // primitive quartets computed by this task
     int nbra;
     int same;                  // bra bin == ket bin: the diagonal quartet (bra == ket) gets an extra 1/2
-    const double* D;           // scaled density D' = f D f (nbf x nbf)
+    const double* D;           // scaled density D' = f D f (nbf x nbf); spin builds: the alpha density, for K
     double* J;                 // J accumulator (nbf x nbf), symmetrised in the finalize step
-    double* K;                 // K accumulator
+    double* K;                 // K accumulator (spin builds: of the alpha density)
+    const double* DJ;          // spin builds: the total density D'a + D'b, for J
+    const double* D2;          // spin builds: the beta density, for K
+    double* K2;                // spin builds: the beta K accumulator
     int nbf;
 };
 
@@ -96,7 +99,7 @@ enum Mode { MODE_STORE = 0, MODE_SCHWARZ = 1, MODE_SCATTER = 2 };
 
 // Host launchers of one angular-momentum class (defined in uqc_eri_class.hip, one object per class).
 struct ClassLaunchers {
-    hipError_t (*digest)(bool mixed, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
+    hipError_t (*digest)(bool mixed, int nspin, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
                          long long item0, long long nitems, const double* boys64, const float* boys32,
                          hipStream_t s);
     hipError_t (*list)(bool mixed, int mode, const ListDev& list, const double* boys64, const float* boys32,
@@ -107,8 +110,9 @@ struct ClassLaunchers {
 int class_index(int la, int lb, int lc, int ld);           // -1 if not canonical
 void class_ls(int idx, int* la, int* lb, int* lc, int* ld);
 // Work items [item0, item0 + nitems) of one (class, precision) launch group.
-hipError_t launch_digest(int cls, bool mixed, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
-                         long long item0, long long nitems, const double* boys64, const float* boys32,
+// nspin = 1: J and K of D; nspin = 2: J of DJ, K of D into K and of D2 into K2, each integral evaluated once.
+hipError_t launch_digest(int cls, bool mixed, int nspin, const TaskDev* d_tasks, const long long* d_task_begin,
+                         int ntask, long long item0, long long nitems, const double* boys64, const float* boys32,
                          hipStream_t s);
 hipError_t launch_list(int cls, bool mixed, int mode, const ListDev& list, const double* boys64,
                        const float* boys32, hipStream_t s);

@@ -44,12 +44,13 @@ double class_flops_prim(int cls) { return kClassFlopsPrim[cls]; }
 int class_team(int cls) { return kClassTeam[cls]; }
 double class_flops_contr(int cls) { return kClassFlopsContr[cls]; }
 
-hipError_t launch_digest(int cls, bool mixed, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
-                         long long item0, long long nitems, const double* boys64tab, const float* boys32tab,
-                         hipStream_t s) {
+hipError_t launch_digest(int cls, bool mixed, int nspin, const TaskDev* d_tasks, const long long* d_task_begin,
+                         int ntask, long long item0, long long nitems, const double* boys64tab,
+                         const float* boys32tab, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    if (cls < 0 || cls >= kNumClasses || item0 < 0) return hipErrorInvalidValue;
-    return launchers(cls).digest(mixed, d_tasks, d_task_begin, ntask, item0, nitems, boys64tab, boys32tab, s);
+    if (cls < 0 || cls >= kNumClasses || item0 < 0 || (nspin != 1 && nspin != 2)) return hipErrorInvalidValue;
+    return launchers(cls).digest(mixed, nspin, d_tasks, d_task_begin, ntask, item0, nitems, boys64tab, boys32tab,
+                                 s);
 }
 
 hipError_t launch_list(int cls, bool mixed, int mode, const ListDev& list, const double* boys64tab,

@@ -62,7 +62,7 @@ size_t estimate_footprint(const Req& r) {
             prim_pairs += (size_t)r.nprim[a] * r.nprim[b];
             ++pairs;
         }
-    size_t bytes = (N + 8 + 9 * NN) * sizeof(double);            // basis workspace
+    size_t bytes = (N + 8 + 10 * NN) * sizeof(double);           // basis workspace
     bytes += NN * sizeof(double) + N * r.ncol * sizeof(double);  // density + perturbation
     bytes += prim_pairs * kNumFields * sizeof(double) + pairs * (4 * sizeof(double) + 2 * sizeof(int));
     bytes += pairs * 2 * (2 * sizeof(int) + sizeof(long long)) + 64 * 1024;  // screened work lists (both precisions)
@@ -213,7 +213,7 @@ bool uqc_server::step() {
         return fail_all("server: task upload failed");
     for (size_t gi = 0; gi < groups.size(); ++gi)
         for (long long i0 = 0; i0 < groups[gi].items; i0 += kMaxItemsPerLaunch)
-            if (launch_digest(groups[gi].cls, groups[gi].mixed, ptrs[gi].first, ptrs[gi].second,
+            if (launch_digest(groups[gi].cls, groups[gi].mixed, 1, ptrs[gi].first, ptrs[gi].second,
                               (int)groups[gi].tasks.size(), i0, std::min(kMaxItemsPerLaunch, groups[gi].items - i0),
                               ctx->boys64, ctx->boys32, s) != hipSuccess)
                 return fail_all("server: class launch failed");
