@@ -103,17 +103,17 @@ __device__ __forceinline__ void team_accumulate(const BinDev& B, int bra, int kb
 // Streaming digest of one lane (classes with too many outputs to hold): all six density slices gathered in the
 // lane's frame, every output digested into the six partial blocks as it is formed, then the blocks added into the
 // team's LDS block at the true component indices.
-// The J slices come from DjC (J added to the team's blocks only if with_j), the K slices from DkC.
-template <class TC, int LA, int LB, int LC, int LD>
+// The J slices come from DjC (J added to the team's blocks only if WITH_J), the K slices from DkC.
+template <class TC, int LA, int LB, int LC, int LD, bool WITH_J>
 __device__ __forceinline__ void team_digest_stream(const double* acc, const int* src, int pidx, double w, cdptr bh,
                                                    const BinDev& Kt, int kl, int q0, int q1, int q2, cdptr DjC,
-                                                   cdptr DkC, bool with_j, int N, int oa, int ob, int oc, int od,
+                                                   cdptr DkC, int N, int oa, int ob, int oc, int od,
                                                    const int* pcA, const int* pcB, const int* pcC, const int* pcD,
                                                    double* t_jab, double* t_jcd, double* t_kac, double* t_kad,
                                                    double* t_kbc, double* t_kbd) {
     constexpr int NA = TC::NA, NB = TC::NB, NC = TC::NC, ND = TC::ND;
     auto Dp = [&](int r, int c) { return DkC[(unsigned)r * (unsigned)N + (unsigned)c]; };
-    auto Dq = [&](int r, int c) { return with_j ? DjC[(unsigned)r * (unsigned)N + (unsigned)c] : 0.0; };
+    auto Dq = [&](int r, int c) { return WITH_J ? DjC[(unsigned)r * (unsigned)N + (unsigned)c] : 0.0; };
     double dab[NA * NB], dcd[NC * ND], dbd[NB * ND], dbc[NB * NC], dad[NA * ND], dac[NA * NC];
 #pragma unroll
     for (int i = 0; i < NA; ++i)
@@ -157,7 +157,7 @@ __device__ __forceinline__ void team_digest_stream(const double* acc, const int*
     const double CDz = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q2);
     TC::hrr_digest(acc, src, pidx, w, ABx, ABy, ABz, CDx, CDy, CDz, dab, dcd, dbd, dbc, dad, dac, jab, jcd, kac, kad,
                    kbc, kbd);
-    if (with_j) {
+    if constexpr (WITH_J) {
 #pragma unroll
         for (int i = 0; i < NA; ++i)
 #pragma unroll
@@ -310,14 +310,14 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
         double w = act ? bh[3] * Kt.sdeg[kl] : 0.0;
         if (tk.same && ket == bra) w *= 0.5;
         if constexpr (TC::STREAM) {
-#pragma unroll
-            for (int sp = 0; sp < NSPIN; ++sp) {
-                const int sh = sp * KSZ;
-                team_digest_stream<TC, LA, LB, LC, LD>(acc, src, pidx, w, bh, Kt, kl, q0, q1, q2, Dj, Dk(sp), sp == 0,
-                                                       N, oa, ob, oc, od, pcA, pcB, pcC, pcD, tm + R_JAB, tm + R_JCD,
-                                                       tm + R_KAC + sh, tm + R_KAD + sh, tm + R_KBC + sh,
-                                                       tm + R_KBD + sh);
-            }
+            team_digest_stream<TC, LA, LB, LC, LD, true>(acc, src, pidx, w, bh, Kt, kl, q0, q1, q2, Dj, Dc, N, oa, ob,
+                                                         oc, od, pcA, pcB, pcC, pcD, tm + R_JAB, tm + R_JCD,
+                                                         tm + R_KAC, tm + R_KAD, tm + R_KBC, tm + R_KBD);
+            if constexpr (NSPIN == 2)
+                team_digest_stream<TC, LA, LB, LC, LD, false>(acc, src, pidx, w, bh, Kt, kl, q0, q1, q2, Dj,
+                                                              as_const(tk.D2), N, oa, ob, oc, od, pcA, pcB, pcC, pcD,
+                                                              tm + R_JAB, tm + R_JCD, tm + R_KAC + KSZ,
+                                                              tm + R_KAD + KSZ, tm + R_KBC + KSZ, tm + R_KBD + KSZ);
         } else {
         double out[TC::NOUT];
         {
