@@ -120,10 +120,10 @@ def class_name(cid: int) -> str:
 
 
 def dom_kernel_key(cid: int) -> str:
-    """rocprofv3 short name of the FP64/mixed class kernel with this class id."""
+    """rocprofv3 short name of the FP64/mixed closed-shell (one density) class kernel with this class id."""
     c = cid % 10000
     ls = [c // 1000, (c // 100) % 10, (c // 10) % 10, c % 10]
-    return "k_digest<%d, %d, %d, %d, %s>" % (ls[0], ls[1], ls[2], ls[3], "true" if cid >= 10000 else "false")
+    return "k_digest<%d, %d, %d, %d, %s, 1>" % (ls[0], ls[1], ls[2], ls[3], "true" if cid >= 10000 else "false")
 
 
 def cpu_baseline(w, target_s: float = 15.0):
