@@ -119,6 +119,22 @@ def class_name(cid: int) -> str:
            ")" + ("-mixed" if mixed else "")
 
 
+def cartesian_per_quartet(cid: int) -> int:
+    """Cartesian integrals n_a n_b n_c n_d of one shell quartet of class id la*1000 + lb*100 + lc*10 + ld."""
+    c = cid % 10000
+    return int(np.prod([(l + 1) * (l + 2) // 2 for l in (c // 1000, (c // 100) % 10, (c // 10) % 10, c % 10)]))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def dom_kernel_key(cid: int) -> str:
     """rocprofv3 short name of the FP64/mixed closed-shell (one density) class kernel with this class id."""
     c = cid % 10000
@@ -156,6 +172,7 @@ def cpu_baseline(w, target_s: float = 15.0):
             break
         n = max(16, int(len(take) * min(4.0, max(1.2, (target_s - t_used) / max(dt, 1e-3) * 0.5))))
     return {"value": kept / t_used, "unit": "shell quartets/s", "cores": nthreads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": "%d of %d bra shell pairs (uniform, seed 1234) x all canonical kets, tau=%g, 1 density: "
                       "%d quartets in %.1f s" % (pos, npair, w.tau, kept, t_used)}
 
@@ -173,6 +190,8 @@ def main():
                     help="medium (default, the benchmark line); mixed150 / large400: mixed vs FP64 accuracy and "
                          "speed; serve: Poisson request stream through the continuous-batching server")
     ap.add_argument("--nreq", type=int, default=32, help="serve: requests taken from the 512-request stream")
+    ap.add_argument("--rate", type=float, default=200.0,
+                    help="serve: mean arrival rate in requests/s (the stream's 200, or a sustainable rate)")
     ap.add_argument("--oracle-quartets", type=int, default=4000, help="mixed150/large400: oracle sample size")
     ap.add_argument("--fp64-only", action="store_true",
                     help="mixed150/large400: time the FP64 build only (no mixed build, no mixed-vs-FP64 errors)")
@@ -276,6 +295,8 @@ def main():
         "quartets_per_build": q,
         "quartets_screened_per_build": int(st0.quartets_screened),
         "prim_quartets_per_build": int(st0.prim_quartets),
+        "prim_quartets_per_s": int(st0.prim_quartets) * a.steps / elapsed,
+        "cartesian_integrals_per_s": sum(cls_q[k] * cartesian_per_quartet(k) for k in cls_q) * a.steps / elapsed,
         "algorithmic_flops_per_build": total_flops,
         "algorithmic_tflops": total_flops * a.steps / elapsed / 1e12,
         "eri_kernel_ms_per_build": eri_ms,
@@ -578,7 +599,8 @@ def bench_serve(a):
     ctx = uqc.Context(0)
     out = {"metric": METRIC, "unit": "requests/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic",
-           "config": {"workload": "poisson200_4to120atoms_8iter: first %d of 512 requests" % len(stream),
+           "config": {"workload": "poisson%g_4to120atoms_8iter: first %d of 512 requests%s" % (
+               a.rate, len(stream), "" if a.rate == 200.0 else " (arrival times of the 200 req/s stream scaled)"),
                       "budget_GiB": 64, "slots": 16}}
     for prec_name, prec in [("fp64", uqc.FP64), ("mixed", uqc.MIXED)]:
         srv = uqc.Server(ctx, 64 << 30, 16)
@@ -586,8 +608,9 @@ def bench_serve(a):
         tickets = []
         for r in stream:
             now = time.perf_counter() - t0
-            if r.arrival_s > now:
-                time.sleep(r.arrival_s - now)
+            arrive = r.arrival_s * (200.0 / a.rate)
+            if arrive > now:
+                time.sleep(arrive - now)
             tickets.append(srv.submit(r.shells, r.D0, n_iter=8, ncol=max(1, r.natoms // 2), eps=0.05,
                                       seed=4000 + r.rid, opts=uqc.default_opts(tau=1e-12, precision=prec)))
         done = {}
