@@ -221,3 +221,23 @@ def test_uhf_rejects_bad_arguments(ctx):
     r = B.scf_uhf(Z, R, 2, 1, uqc.scf_opts(max_iter=3))
     assert r["iterations"] == 3 and not r["converged"]
     B.close()
+
+
+@pytest.mark.parametrize("x", [0.0, 0.2, 0.5])
+def test_scf_with_scaled_exchange_textbook(ctx, x):
+    # minimal-basis H2: the occupied orbital is fixed by symmetry, so with G = J - (x/2) K the closed-shell energy is
+    # 2 h_gg + (2 - x) J_gg + 1/R (textbook molecular-orbital integrals); the H atom (one function, one electron)
+    # in the unrestricted driver has E = H_11 + (1 - x) (11|11) / 2
+    g = _golden()
+    sh = wl.h2_sto3g()
+    B = uqc.Basis(ctx, sh)
+    r = B.scf_rhf([1.0, 1.0], sh.center, 1, uqc.scf_opts(fock=uqc.default_opts(exchange_scale=x)))
+    assert r["converged"]
+    assert abs(r["E_total"] - (2 * g["h_gg"] + (2 - x) * g["J_gg"] + 1 / 1.4)) <= 3e-4
+    B.close()
+    sh = _h_atom()
+    B = uqc.Basis(ctx, sh)
+    r = B.scf_uhf([1.0], sh.center, 1, 0, uqc.scf_opts(fock=uqc.default_opts(exchange_scale=x)))
+    assert r["converged"]
+    assert abs(r["E_total"] - (g["T11"] + g["V1_11"] + 0.5 * (1 - x) * g["(11|11)"])) <= 2e-4
+    B.close()
