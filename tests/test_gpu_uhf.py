@@ -241,3 +241,30 @@ def test_scf_with_scaled_exchange_textbook(ctx, x):
     assert r["converged"]
     assert abs(r["E_total"] - (g["T11"] + g["V1_11"] + 0.5 * (1 - x) * g["(11|11)"])) <= 2e-4
     B.close()
+
+
+def test_spin_build_full_size(ctx):
+    """60 atoms, N = 660, tau = 1e-12 (the benchmark's launch configuration): sampled J, Ka, Kb blocks of the
+    spin-density build against the oracle's definitions computed one by one, and over every element
+    K(Da) + K(Db) = K(Da + Db) and J(Da + Db) from the closed-shell build of Da + Db (linearity)."""
+    w = wl.medium(ndens=2)
+    B = uqc.Basis(ctx, w.shells)
+    Da, Db = 0.55 * w.densities[0], 0.45 * w.densities[1]
+    o = uqc.default_opts(tau=w.tau)
+    r = B.fock_build_uhf(Da, Db, o)
+    J, K, G, st = B.fock_build(Da + Db, o)
+    assert np.max(np.abs(r["J"] - J)) <= 1e-12 * np.max(np.abs(J))
+    assert np.max(np.abs(r["Ka"] + r["Kb"] - K)) <= 1e-12 * np.max(np.abs(K))
+    assert r["stats"].quartets == st.quartets
+    O = oracle.Basis(w.shells)
+    off = B.offsets
+    rng = np.random.default_rng(17)
+    picks = [(0, 0), (5, 2)] + [tuple(int(x) for x in rng.integers(0, B.nshell, size=2)) for _ in range(2)]
+    for a, b in picks:
+        na, nb = oracle.ncart(int(B.l[a])), oracle.ncart(int(B.l[b]))
+        blocks = [("J", r["J"], O.j_block(Da + Db, a, b, tau=w.tau)), ("Ka", r["Ka"], O.k_block(Da, a, b, tau=w.tau)),
+                  ("Kb", r["Kb"], O.k_block(Db, a, b, tau=w.tau))]
+        for name, M, ref in blocks:
+            got = M[off[a]:off[a] + na, off[b]:off[b] + nb]
+            assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(M)), (name, a, b)
+    B.close()
