@@ -186,7 +186,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--workload", default="medium",
-                    choices=["medium", "mixed150", "large400", "large400kd1", "serve", "scf", "uhf", "mp2", "copy"],
+                    choices=["medium", "mixed150", "large400", "large400kd1", "serve", "scf", "uhf", "mp2", "rys", "copy"],
                     help="medium (default, the benchmark line); mixed150 / large400: mixed vs FP64 accuracy and "
                          "speed; serve: Poisson request stream through the continuous-batching server")
     ap.add_argument("--nreq", type=int, default=32, help="serve: requests taken from the 512-request stream")
@@ -222,6 +222,8 @@ def main():
         return bench_uhf(a)
     if a.workload == "mp2":
         return bench_mp2(a)
+    if a.workload == "rys":
+        return bench_rys(a)
     if a.workload in ("mixed150", "large400", "large400kd1"):
         return bench_mixed(a)
 
@@ -568,6 +570,46 @@ def bench_mp2(a):
            "ao_quartets": m["quartets"], "transform_flops": m["transform_flops"],
            "roofline_transform": {"bound": "mfma", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s",
                                   "frac": tf / 78.6, "note": "four rocBLAS FP64 GEMMs, timed together"}}
+    print(json.dumps(out), flush=True)
+    B.close()
+    ctx.close()
+
+
+def bench_rys(a):
+    """The same ERI blocks by the Obara-Saika/HGP list kernel and by Rys quadrature, per class: 4096 shell
+    quartets of each class drawn from the medium lattice's shells (seed 5); wall time of uqc_eri_blocks per method
+    (the host-side bookkeeping is identical for both) and the largest difference between the two methods.  The
+    kernel durations come from a rocprofv3 kernel trace of this command (k_list vs k_list_rys)."""
+    from paper_1303_4916_amd import uqc
+    from paper_1303_4916_amd import workloads as wl
+
+    w = wl.medium(ndens=1)
+    ctx = uqc.Context(0)
+    B = uqc.Basis(ctx, w.shells)
+    rng = np.random.default_rng(5)
+    by_l = {l: np.where(B.l == l)[0] for l in range(3)}
+    classes = [(la, lb, lc, ld) for la in range(3) for lb in range(la + 1) for lc in range(3) for ld in range(lc + 1)
+               if (la, lb) >= (lc, ld)]
+    res = {}
+    for ls in classes:
+        q = np.stack([rng.choice(by_l[l], size=4096) for l in ls], axis=1).astype(np.int32)
+        B.eri_blocks(q[:64], uqc.FP64)
+        B.eri_blocks(q[:64], uqc.RYS)
+        t = time.perf_counter()
+        x = B.eri_blocks(q, uqc.FP64)
+        t1 = time.perf_counter()
+        y = B.eri_blocks(q, uqc.RYS)
+        t2 = time.perf_counter()
+        d = max(float(np.max(np.abs(u - v))) for u, v in zip(x, y))
+        m = max(float(np.max(np.abs(u))) for u in x)
+        name = "(" + "".join("spd"[l] for l in ls[:2]) + "|" + "".join("spd"[l] for l in ls[2:]) + ")"
+        res[name] = {"hgp_ms": (t1 - t) * 1e3, "rys_ms": (t2 - t1) * 1e3, "max_abs_diff": d, "max_abs": m}
+        print("  %s hgp %.1f ms, rys %.1f ms, max |diff| %.2e" % (name, res[name]["hgp_ms"], res[name]["rys_ms"], d),
+              file=sys.stderr, flush=True)
+    out = {"metric": "shell quartets/s per method and class (explicit ERI blocks)", "unit": "shell quartets/s",
+           "value": 4096 * len(classes) / (sum(v["rys_ms"] for v in res.values()) * 1e-3), "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "eri_blocks_lattice60: 4096 quartets per class, both methods"}, "classes": res}
     print(json.dumps(out), flush=True)
     B.close()
     ctx.close()

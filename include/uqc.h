@@ -49,7 +49,9 @@ typedef enum {
     UQC_E_BUSY = -7             /* server is shutting down */
 } uqc_status;
 
-typedef enum { UQC_FP64 = 0, UQC_MIXED = 1 } uqc_precision;
+/* UQC_RYS: uqc_eri_block(s) only, FP64 integrals by Rys quadrature (the paper's method) instead of the
+ * Obara-Saika / Head-Gordon-Pople recursions; the same integrals, for per-class comparison. */
+typedef enum { UQC_FP64 = 0, UQC_MIXED = 1, UQC_RYS = 2 } uqc_precision;
 
 /* Progress report of a Fock build: called on the calling thread after every class sub-launch has completed on the
  * device (items_done of items_total work items of class class_id, encoded as in uqc_stats.class_id).  Setting it
@@ -127,7 +129,8 @@ uqc_status uqc_schwarz(const uqc_basis* b, double* Q);
 
 /* One contracted block (ab|cd), Eq. (5): n_a*n_b*n_c*n_d doubles written to host memory `out`, row-major [i][j][k][l]
  * over the Cartesian components of shells a, b, c, d (any order of the four shell indices).  precision selects the
- * recursions' arithmetic (UQC_MIXED: FP32 recursions, FP64 contraction).  Never screened. */
+ * recursions' arithmetic (UQC_MIXED: FP32 recursions, FP64 contraction) or, with UQC_RYS, Rys quadrature in FP64.
+ * Never screened (every primitive is evaluated). */
 uqc_status uqc_eri_block(uqc_basis* b, int a, int bb, int c, int d, int precision, double* out);
 
 /* n blocks at once: quartets[4*q .. 4*q+3] = (a, b, c, d); blocks are written one after another to `out` (host),

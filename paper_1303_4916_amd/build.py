@@ -62,7 +62,9 @@ def _units():
                 os.path.join(GEN, "one_electron.h")]
     units = []
     team = _team_classes()
-    headers = headers + [os.path.join(CSRC, "uqc_eri_team.h"), os.path.join(GEN, "eri_team.h")]
+    headers = headers + [os.path.join(CSRC, "uqc_eri_team.h"), os.path.join(GEN, "eri_team.h"),
+                         os.path.join(CSRC, "uqc_rys.h"), os.path.join(GEN, "rys_consts.h"),
+                         os.path.join(GEN, "rys_table.h")]
     for i, (la, lb, lc, ld) in enumerate(classes()):
         units.append((os.path.join(CSRC, "uqc_eri_class.hip"), os.path.join(OBJ, "eri_class_%02d.o" % i),
                       ["-DUQC_CLASS_ID=%d" % i, "-DUQC_LA=%d" % la, "-DUQC_LB=%d" % lb, "-DUQC_LC=%d" % lc,
@@ -98,6 +100,11 @@ def build(incremental: bool = False, jobs: int = None, verbose: bool = True) -> 
     os.makedirs(OBJ, exist_ok=True)
     for gen in ("gen_eri.py", "gen_one.py"):
         subprocess.check_call([sys.executable, os.path.join(CSRC, gen), GEN])
+    # the Rys table takes ~15 s to compute: regenerated only when missing or older than its generator
+    rys_out = [os.path.join(GEN, f) for f in ("rys_consts.h", "rys_table.h")]
+    if any(not os.path.exists(f) or os.path.getmtime(f) < os.path.getmtime(os.path.join(CSRC, "gen_rys.py"))
+           for f in rys_out):
+        subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_rys.py"), GEN])
     units = _units()
     todo = [u for u in units if not incremental or _stale(u[1], [u[0]] + u[3])]
     jobs = jobs or min(16, os.cpu_count() or 4)

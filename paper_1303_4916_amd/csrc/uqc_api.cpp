@@ -1,6 +1,7 @@
 // Host side of libuqc: contexts, basis plans (normalisation, primitive-pair data, Schwarz bounds, pair bins and
 // screened work lists), the ERI-block and Fock-build entry points of include/uqc.h.
 #include "uqc_api_internal.h"
+#include "generated/rys_table.h"
 
 #include <algorithm>
 #include <chrono>
@@ -139,6 +140,11 @@ uqc_status uqc_init(int device, void* hip_stream, uqc_ctx** out) {
         uqc_finalize(c);
         return uqc_fail(UQC_E_DEVICE, "uqc_init: cannot upload the Boys table");
     }
+    if (hipMalloc(&c->rys, sizeof(kRysTab)) != hipSuccess ||
+        hipMemcpy(c->rys, kRysTab, sizeof(kRysTab), hipMemcpyHostToDevice) != hipSuccess) {
+        uqc_finalize(c);
+        return uqc_fail(UQC_E_DEVICE, "uqc_init: cannot upload the Rys table");
+    }
     *out = c;
     return UQC_OK;
 }
@@ -151,6 +157,7 @@ uqc_status uqc_finalize(uqc_ctx* c) {
     release_blas(c);
     if (c->boys64) (void)hipFree(c->boys64);
     if (c->boys32) (void)hipFree(c->boys32);
+    if (c->rys) (void)hipFree(c->rys);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return UQC_OK;
@@ -920,7 +927,8 @@ bool uqc::is_device_ptr(const void* p) {
 uqc_status uqc_eri_blocks(uqc_basis* B, int n, const int* q, int precision, double* out) {
     if (!B || (n > 0 && (!q || !out))) return uqc_fail(UQC_E_ARG, "uqc_eri_blocks: NULL argument");
     if (n < 0) return uqc_fail(UQC_E_ARG, "uqc_eri_blocks: negative count");
-    if (precision != UQC_FP64 && precision != UQC_MIXED) return uqc_fail(UQC_E_ARG, "uqc_eri_blocks: bad precision");
+    if (precision != UQC_FP64 && precision != UQC_MIXED && precision != UQC_RYS)
+        return uqc_fail(UQC_E_ARG, "uqc_eri_blocks: bad precision");
     if (n == 0) return UQC_OK;
     const int ns = B->nshell;
     struct Item {
@@ -1014,8 +1022,11 @@ uqc_status uqc_eri_blocks(uqc_basis* B, int n, const int* q, int precision, doub
         ld.ket_idx = didx + n + L.first;
         ld.n = L.count;
         ld.out = dout + L.out;
-        if (launch_list(L.cls, precision == UQC_MIXED, MODE_STORE, ld, ctx->boys64, ctx->boys32, ctx->stream) !=
-            hipSuccess)
+        const hipError_t e = precision == UQC_RYS
+                                 ? launch_list_rys(L.cls, ld, ctx->rys, ctx->stream)
+                                 : launch_list(L.cls, precision == UQC_MIXED, MODE_STORE, ld, ctx->boys64,
+                                               ctx->boys32, ctx->stream);
+        if (e != hipSuccess)
             st = uqc_fail(UQC_E_DEVICE, "uqc_eri_blocks: kernel launch failed");
     }
     std::vector<double> hout(total_out);

@@ -24,6 +24,7 @@ struct uqc_ctx {
     bool own_stream = false;
     double* boys64 = nullptr;
     float* boys32 = nullptr;
+    double* rys = nullptr;   // Rys quadrature table (generated/rys_consts.h layout)
     std::vector<hipEvent_t> events;
     void* blas = nullptr;  // rocblas_handle of the SCF driver, created on first use
 };

@@ -2,6 +2,7 @@
 // -DUQC_CLASS_ID=n -DUQC_LA=.. -DUQC_LB=.. -DUQC_LC=.. -DUQC_LD=.. -DUQC_TEAM=0|1 so that the classes build in
 // parallel; UQC_TEAM selects the six-lane team kernel for the Fock build.
 #include "uqc_eri_impl.h"
+#include "uqc_rys.h"
 #if UQC_TEAM
 #include "uqc_eri_team.h"
 #endif
@@ -64,6 +65,15 @@ static hipError_t launch_list_cls(bool mixed, int mode, const ListDev& L, const 
     return hipGetLastError();
 }
 
-ClassLaunchers UQC_CAT(class_launchers_, UQC_CLASS_ID)() { return ClassLaunchers{&launch_digest_cls, &launch_list_cls}; }
+static hipError_t launch_list_rys_cls(const ListDev& L, const double* rystab, hipStream_t s) {
+    if (L.n <= 0) return hipSuccess;
+    const unsigned nblocks = (unsigned)((L.n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_list_rys<UQC_LA, UQC_LB, UQC_LC, UQC_LD>), dim3(nblocks), dim3(kBlock), 0, s, L, rystab);
+    return hipGetLastError();
+}
+
+ClassLaunchers UQC_CAT(class_launchers_, UQC_CLASS_ID)() {
+    return ClassLaunchers{&launch_digest_cls, &launch_list_cls, &launch_list_rys_cls};
+}
 
 }  // namespace uqc

@@ -104,6 +104,7 @@ struct ClassLaunchers {
                          hipStream_t s);
     hipError_t (*list)(bool mixed, int mode, const ListDev& list, const double* boys64, const float* boys32,
                        hipStream_t s);
+    hipError_t (*list_rys)(const ListDev& list, const double* rystab, hipStream_t s);  // MODE_STORE by Rys quadrature
 };
 
 // Host-side launchers (defined in uqc_kernels.hip).
@@ -116,6 +117,7 @@ hipError_t launch_digest(int cls, bool mixed, int nspin, const TaskDev* d_tasks,
                          hipStream_t s);
 hipError_t launch_list(int cls, bool mixed, int mode, const ListDev& list, const double* boys64,
                        const float* boys32, hipStream_t s);
+hipError_t launch_list_rys(int cls, const ListDev& list, const double* rystab, hipStream_t s);
 hipError_t launch_prepare(const double* D, const double* f, double* Dp, int nbf, unsigned long long* maxbits,
                           hipStream_t s);
 hipError_t launch_zero(double* p, size_t n, hipStream_t s);

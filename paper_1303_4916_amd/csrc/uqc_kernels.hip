@@ -53,6 +53,12 @@ hipError_t launch_digest(int cls, bool mixed, int nspin, const TaskDev* d_tasks,
                                  s);
 }
 
+hipError_t launch_list_rys(int cls, const ListDev& list, const double* rystab, hipStream_t s) {
+    if (list.n <= 0) return hipSuccess;
+    if (cls < 0 || cls >= kNumClasses) return hipErrorInvalidValue;
+    return launchers(cls).list_rys(list, rystab, s);
+}
+
 hipError_t launch_list(int cls, bool mixed, int mode, const ListDev& list, const double* boys64tab,
                        const float* boys32tab, hipStream_t s) {
     if (list.n <= 0) return hipSuccess;

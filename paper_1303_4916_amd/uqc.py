@@ -22,6 +22,7 @@ UQC_OK, UQC_PENDING = 0, 1
 UQC_E_ARG, UQC_E_UNSUPPORTED, UQC_E_NOMEM, UQC_E_DEVICE = -1, -2, -3, -4
 UQC_E_NOT_SYMMETRIC, UQC_E_NOT_FOUND, UQC_E_BUSY = -5, -6, -7
 FP64, MIXED = 0, 1
+RYS = 2  # uqc_eri_block(s) only: the same integrals by Rys quadrature
 MAX_CLASS_STATS = 96
 MAX_ITER = 64
 

@@ -91,6 +91,34 @@ def test_full_tensor_cube(ctx):
         assert np.max(np.abs(T - T.transpose(perm))) <= 1e-13 * m
 
 
+# ------------------------------------------------------------------------------------ Rys quadrature (UQC_RYS)
+@pytest.mark.parametrize("ls", CLASSES, ids=lambda x: "".join("spd"[i] for i in x))
+def test_eri_block_every_class_rys(ctx, ls):
+    """The same blocks by Rys quadrature (the paper's method) against the oracle's McMurchie-Davidson integrals."""
+    sh = wl.random_quartet_shells(200 + sum(v * 3 ** i for i, v in enumerate(ls)), ls, k=3)
+    B = uqc.Basis(ctx, sh)
+    O = oracle.Basis(sh)
+    for q in [(0, 1, 2, 3), (1, 0, 3, 2), (2, 3, 0, 1), (3, 2, 1, 0), (0, 1, 0, 1), (2, 2, 3, 3), (0, 0, 0, 0)]:
+        ok, err, m = close(B.eri_block(*q, precision=uqc.RYS), O.eri(*q))
+        assert ok, (q, err, m)
+
+
+def test_full_tensor_cube_rys(ctx):
+    w = wl.cube()
+    B = uqc.Basis(ctx, w.shells)
+    T = B.eri_tensor(precision=uqc.RYS)
+    ok, err, m = close(T, oracle.Basis(w.shells).eri_tensor())
+    assert ok, (err, m)
+    # both GPU methods on a lattice with distant pairs (large T: the asymptotic rule)
+    sh = wl.lattice(6, seed=12, ndens=1).shells
+    B2 = uqc.Basis(ctx, sh)
+    rng = np.random.default_rng(3)
+    q = rng.integers(0, B2.nshell, size=(400, 4)).astype(np.int32)
+    for x, y in zip(B2.eri_blocks(q, uqc.FP64), B2.eri_blocks(q, uqc.RYS)):
+        ok, err, m = close(y, x)
+        assert ok, (err, m)
+
+
 def test_schwarz_bounds(ctx):
     w = wl.lattice(6, seed=12, ndens=1)
     B = uqc.Basis(ctx, w.shells)
