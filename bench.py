@@ -31,12 +31,15 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_medium60_fp64.json")
 
 
 def kernel_sources_sha256() -> str:
-    """Hash of every source the device kernels are built from (traffic counters are only valid for these)."""
+    """Hash of every source the device kernels are built from (traffic counters are only valid for these); the Rys
+    table headers are generated at build time from gen_rys.py, which is hashed, so they are left out."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1303_4916_amd", "csrc")
     for d in (csrc, os.path.join(csrc, "generated")):
         for f in sorted(os.listdir(d)):
+            if f in ("rys_consts.h", "rys_table.h"):
+                continue
             if f.endswith((".h", ".hip", ".cpp", ".py")):
                 h.update(f.encode())
                 h.update(open(os.path.join(d, f), "rb").read())
