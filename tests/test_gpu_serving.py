@@ -150,3 +150,24 @@ def test_server_rejects_bad_requests(ctx):
     out = srv.poll(t)
     assert out is not None and out["n_iter"] == 2
     srv.close()
+
+
+def test_server_honours_exchange_scale(ctx):
+    """A request with exchange weight x = 0.25: every iteration's E2 and the final G equal a direct build of the
+    same density with the same options (G = J - (x/2) K)."""
+    sh = wl.lattice(4, seed=91, ndens=1).shells
+    D0 = wl.random_density(np.random.default_rng(9), sh.nbf, 3, 4.0)
+    opts = uqc.default_opts(tau=1e-12, exchange_scale=0.25)
+    srv = uqc.Server(ctx, 1 << 30, 2)
+    t = srv.submit(sh, D0, n_iter=3, ncol=2, eps=0.1, seed=77, opts=opts)
+    srv.drain()
+    r = srv.poll(t)
+    Ds = density_sequence(D0, 3, 2, 0.1, 77)
+    B = uqc.Basis(ctx, sh)
+    for k, D in enumerate(Ds):
+        J, K, G, st = B.fock_build(D, opts)
+        assert abs(r["E2"][k] - st.E2) <= 1e-11 * abs(st.E2), k
+    assert np.max(np.abs(r["G"] - G)) <= 1e-11 * np.max(np.abs(G))
+    assert np.max(np.abs(G - (J - 0.125 * K))) <= 1e-13 * np.max(np.abs(G))
+    B.close()
+    srv.close()

@@ -268,3 +268,19 @@ def test_spin_build_full_size(ctx):
             got = M[off[a]:off[a] + na, off[b]:off[b] + nb]
             assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(M)), (name, a, b)
     B.close()
+
+
+def test_spin_build_mixed_precision(ctx):
+    """Mixed precision (FP32 recursions, FP64 accumulation) in the one-pass spin build: E2 within 1e-6 Eh of the
+    FP64 spin build on a 12-atom lattice, the matrices within 1e-6 of their largest element, and some quartets
+    routed to FP32."""
+    sh = wl.lattice(12, seed=63, ndens=1).shells
+    B = uqc.Basis(ctx, sh)
+    Da, Db = _spin_densities(sh.nbf, 63, 6, 5)
+    r64 = B.fock_build_uhf(Da, Db, uqc.default_opts(tau=1e-12))
+    rmx = B.fock_build_uhf(Da, Db, uqc.default_opts(tau=1e-12, precision=uqc.MIXED))
+    assert abs(rmx["stats"].E2 - r64["stats"].E2) <= 1e-6
+    for k in ("J", "Ka", "Kb", "Ga", "Gb"):
+        assert np.max(np.abs(rmx[k] - r64[k])) <= 1e-6 * np.max(np.abs(r64[k])), k
+    assert rmx["stats"].fp64_quartets < rmx["stats"].quartets
+    B.close()
