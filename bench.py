@@ -189,7 +189,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--workload", default="medium",
-                    choices=["medium", "mixed150", "large400", "large400kd1", "serve", "scf", "uhf", "mp2", "rys", "copy"],
+                    choices=["medium", "mixed150", "large400", "large400kd1", "serve", "scf", "uhf", "mp2", "rys", "oracle-c1", "copy"],
                     help="medium (default, the benchmark line); mixed150 / large400: mixed vs FP64 accuracy and "
                          "speed; serve: Poisson request stream through the continuous-batching server")
     ap.add_argument("--nreq", type=int, default=32, help="serve: requests taken from the 512-request stream")
@@ -227,6 +227,8 @@ def main():
         return bench_mp2(a)
     if a.workload == "rys":
         return bench_rys(a)
+    if a.workload == "oracle-c1":
+        return bench_oracle_c1(a)
     if a.workload in ("mixed150", "large400", "large400kd1"):
         return bench_mixed(a)
 
@@ -616,6 +618,24 @@ def bench_rys(a):
     print(json.dumps(out), flush=True)
     B.close()
     ctx.close()
+
+
+def bench_oracle_c1(a):
+    """The oracle alone on the host, one thread, on the 8-atom cube (16 shells, N = 32): the full ERI tensor and one
+    J/K build of its density by the definition of Eq. (12), every quartet (no GPU)."""
+    import oracle
+    from paper_1303_4916_amd import workloads as wl
+    w = wl.cube()
+    oracle.set_threads(1)
+    O = oracle.Basis(w.shells)
+    t = time.perf_counter()
+    O.eri_tensor()
+    t_tensor = time.perf_counter() - t
+    t = time.perf_counter()
+    O.jk_direct([w.densities[0]])
+    t_jk = time.perf_counter() - t
+    print(json.dumps({"workload": "oracle_cube8: 16 shells, N = 32, one thread", "cpu_model": cpu_model(),
+                      "eri_tensor_s": t_tensor, "jk_direct_s": t_jk}), flush=True)
 
 
 def bench_copy(a):
