@@ -716,6 +716,20 @@ void uqc::plan_account(Plan& p) {
     p.screened = p.canonical - p.quartets;
 }
 
+// Bra pairs per work item: kGroupBras for the 64-ket kernels and kTeamGroupBras for the team kernels, more for the
+// classes measured faster with larger groups (the item's ket loads, J_cd flush and task lookup spread over more bra
+// pairs, at the price of fewer wavefronts): (ds|ss), (dp|ss), (dd|ss), (ds|ds), (ds|pp), (dp|ds) take 16; the team
+// kernels of (dp|dp), (dd|ds), (dd|dp) take 8.
+static int group_bras(int cls) {
+    int la, lb, lc, ld;
+    class_ls(cls, &la, &lb, &lc, &ld);
+    switch (la * 1000 + lb * 100 + lc * 10 + ld) {
+        case 2000: case 2100: case 2200: case 2020: case 2011: case 2120: return 16;
+        case 2121: case 2220: case 2221: return 8;
+        default: return class_team(cls) ? kTeamGroupBras : kGroupBras;
+    }
+}
+
 Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st) {
     for (auto& kv : B->plans)
         if (kv.first.tau == tau && kv.first.prec == prec && (prec == UQC_FP64 || kv.first.bound == bound))
@@ -769,7 +783,7 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
             std::iota(by_a.begin(), by_a.end(), 0);
             std::stable_sort(by_a.begin(), by_a.end(), [&](int x, int y) { return bx.off_a[x] < bx.off_a[y]; });
             const int S = class_team(cls) ? kTeamKets : kWave;
-            const int GB = class_team(cls) ? kTeamGroupBras : kGroupBras;
+            const int GB = group_bras(cls);
             for (HostTask* t : {&t64, &t32}) {
                 if (t->mixed && !mixed) continue;
                 int nch = 0;
