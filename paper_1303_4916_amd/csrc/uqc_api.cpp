@@ -718,14 +718,15 @@ void uqc::plan_account(Plan& p) {
 
 // Bra pairs per work item: kGroupBras for the 64-ket kernels and kTeamGroupBras for the team kernels, more for the
 // classes measured faster with larger groups (the item's ket loads, J_cd flush and task lookup spread over more bra
-// pairs, at the price of fewer wavefronts): (ds|ss), (dp|ss), (dd|ss), (ds|ds), (ds|pp), (dp|ds) take 16; the team
-// kernels of (dp|dp), (dd|ds), (dd|dp) take 8.
+// pairs, at the price of fewer wavefronts): (ds|ss), (dp|ss), (dd|ss), (ds|ds), (ds|pp), (dp|ds) take 16 (32 is
+// slower); the team kernels of (dp|dp) and (dd|dp) take 8, (dd|ds) 12.
 static int group_bras(int cls) {
     int la, lb, lc, ld;
     class_ls(cls, &la, &lb, &lc, &ld);
     switch (la * 1000 + lb * 100 + lc * 10 + ld) {
         case 2000: case 2100: case 2200: case 2020: case 2011: case 2120: return 16;
-        case 2121: case 2220: case 2221: return 8;
+        case 2220: return 12;
+        case 2121: case 2221: return 8;
         default: return class_team(cls) ? kTeamGroupBras : kGroupBras;
     }
 }
