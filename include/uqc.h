@@ -75,6 +75,12 @@ typedef struct {
                                densities).  1 (default) is Hartree-Fock; the exact-exchange fraction a0 of a hybrid
                                functional (Sec. "Implementation details", B3LYP) gives its scaled exchange, the
                                exchange-correlation functional itself not being part of this library.  Finite. */
+    int streams;            /* number of HIP streams the class launches of one build are spread over, 1..4 (0 is
+                               read as 1).  Stream 0 is the context's; the others are the context's own (default
+                               priority), ordered after the work already queued on the context's stream and joined
+                               back into it before the build's final pass, so callers see one stream either way.
+                               Kernels of different classes then run side by side, which fills the chip while
+                               one class's launch drains.  Default 3.  Ignored (1) with progress. */
 } uqc_fock_opts;
 
 #define UQC_MAX_CLASS_STATS 96
@@ -97,7 +103,7 @@ typedef struct {
 } uqc_stats;
 
 /* Fills *o with: tau = 1e-12, precision = UQC_FP64, fp64_bound = 1e-8, timing = 0, progress = NULL,
- * max_items_per_launch = 0, exchange_scale = 1. */
+ * max_items_per_launch = 0, exchange_scale = 1, streams = 3. */
 void uqc_fock_opts_default(uqc_fock_opts* o);
 
 /* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t the library launches on (NULL: the

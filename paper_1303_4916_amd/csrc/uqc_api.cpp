@@ -36,6 +36,7 @@ void uqc_fock_opts_default(uqc_fock_opts* o) {
     o->progress_user = nullptr;
     o->max_items_per_launch = 0;
     o->exchange_scale = 1.0;
+    o->streams = 3;
 }
 
 // ---------------------------------------------------------------------------------------------- Boys table
@@ -154,6 +155,14 @@ uqc_status uqc_finalize(uqc_ctx* c) {
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto& e : c->events) (void)hipEventDestroy(e);
+    for (int i = 0; i < 3; ++i) {
+        if (c->side[i]) {
+            (void)hipStreamSynchronize(c->side[i]);
+            (void)hipStreamDestroy(c->side[i]);
+        }
+        if (c->join[i]) (void)hipEventDestroy(c->join[i]);
+    }
+    if (c->fork) (void)hipEventDestroy(c->fork);
     release_blas(c);
     if (c->boys64) (void)hipFree(c->boys64);
     if (c->boys32) (void)hipFree(c->boys32);
@@ -170,6 +179,24 @@ hipEvent_t ctx_event(uqc_ctx* c, size_t i) {
         c->events.push_back(e);
     }
     return c->events[i];
+}
+
+hipStream_t ctx_stream(uqc_ctx* c, int i) {
+    if (i == 0) return c->stream;
+    if (i < 1 || i > 3) return nullptr;
+    if (!c->fork && hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess) {
+        c->fork = nullptr;
+        return nullptr;
+    }
+    if (!c->join[i - 1] && hipEventCreateWithFlags(&c->join[i - 1], hipEventDisableTiming) != hipSuccess) {
+        c->join[i - 1] = nullptr;
+        return nullptr;
+    }
+    if (!c->side[i - 1] && hipStreamCreateWithFlags(&c->side[i - 1], hipStreamNonBlocking) != hipSuccess) {
+        c->side[i - 1] = nullptr;
+        return nullptr;
+    }
+    return c->side[i - 1];
 }
 
 // ---------------------------------------------------------------------------------------------- basis
@@ -1096,6 +1123,7 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
     if (o.precision == UQC_MIXED && !(o.fp64_bound >= 0)) return uqc_fail(UQC_E_ARG, nm + ": bad fp64_bound");
     if (o.max_items_per_launch < 0) return uqc_fail(UQC_E_ARG, nm + ": negative max_items_per_launch");
     if (!std::isfinite(o.exchange_scale)) return uqc_fail(UQC_E_ARG, nm + ": exchange_scale is not finite");
+    if (o.streams < 0 || o.streams > 4) return uqc_fail(UQC_E_ARG, nm + ": streams must be in 0..4");
     const long long max_items = o.max_items_per_launch > 0 ? o.max_items_per_launch : kMaxItemsPerLaunch;
     const int nout = nspin == 1 ? 3 : 5;
     uqc_ctx* ctx = B->ctx;
@@ -1151,24 +1179,57 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
     }
     const bool timing = o.timing != 0;
     std::vector<double> cls_ms(plan->groups.size(), 0.0);
+    // Classes spread over several streams: largest first (FLOPs of the previous build, else work items), each to
+    // the stream with the least work so far.  The extra streams wait for everything queued on the context's stream
+    // so far and are joined back into it after their last launch.
+    const int nst = o.progress ? 1 : std::max(1, o.streams);
+    const size_t ng = plan->groups.size();
+    std::vector<size_t> order(ng);
+    std::vector<int> gstream(ng, 0);
+    for (size_t gi = 0; gi < ng; ++gi) order[gi] = gi;
+    if (nst > 1) {
+        auto weight = [&](size_t gi) {
+            const LaunchGroup& g = plan->groups[gi];
+            return g.flops > 0 ? g.flops : (double)g.nitems;
+        };
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return weight(x) > weight(y); });
+        std::vector<double> load(nst, 0.0);
+        for (size_t gi : order) {
+            const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            gstream[gi] = k;
+            load[k] += weight(gi);
+        }
+    }
+    hipStream_t S[4] = {s, nullptr, nullptr, nullptr};
+    for (int k = 1; k < nst; ++k)
+        if (!(S[k] = ctx_stream(ctx, k))) return uqc_fail(UQC_E_DEVICE, nm + ": stream creation failed");
     auto pass = [&]() -> uqc_status {
         if (plan->ntasks) UQC_HIP(launch_zero((double*)plan->d_count, 2 * (size_t)plan->ntasks, s));
-        size_t ev = 0;
-        for (auto& g : plan->groups) {
-            if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, ev++), s));
+        if (nst > 1) {
+            UQC_HIP(hipEventRecord(ctx->fork, s));
+            for (int k = 1; k < nst; ++k) UQC_HIP(hipStreamWaitEvent(S[k], ctx->fork, 0));
+        }
+        for (size_t gi : order) {
+            const LaunchGroup& g = plan->groups[gi];
+            hipStream_t gs = S[gstream[gi]];
+            if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, 2 * gi), gs));
             int la, lb, lc, ld;
             class_ls(g.cls, &la, &lb, &lc, &ld);
             const int cid = la * 1000 + lb * 100 + lc * 10 + ld + (g.mixed ? 10000 : 0);
             for (long long i0 = 0; i0 < g.nitems; i0 += max_items) {
                 const long long n = std::min(max_items, g.nitems - i0);
                 UQC_HIP(launch_digest(g.cls, g.mixed, nspin, g.d_tasks, g.d_begin, g.ntask, i0, n, ctx->boys64,
-                                      ctx->boys32, s));
+                                      ctx->boys32, gs));
                 if (o.progress) {
-                    UQC_HIP(hipStreamSynchronize(s));
+                    UQC_HIP(hipStreamSynchronize(gs));
                     o.progress(o.progress_user, cid, i0 + n, g.nitems);
                 }
             }
-            if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, ev++), s));
+            if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, 2 * gi + 1), gs));
+        }
+        for (int k = 1; k < nst; ++k) {
+            UQC_HIP(hipEventRecord(ctx->join[k - 1], S[k]));
+            UQC_HIP(hipStreamWaitEvent(s, ctx->join[k - 1], 0));
         }
         if (timing) {
             UQC_HIP(hipStreamSynchronize(s));

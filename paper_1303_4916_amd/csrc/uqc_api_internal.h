@@ -26,12 +26,17 @@ struct uqc_ctx {
     float* boys32 = nullptr;
     double* rys = nullptr;   // Rys quadrature table (generated/rys_consts.h layout)
     std::vector<hipEvent_t> events;
+    hipStream_t side[3] = {nullptr, nullptr, nullptr};  // extra streams of a build spread over several (lazy)
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
     void* blas = nullptr;  // rocblas_handle of the SCF driver, created on first use
 };
 
 void release_blas(uqc_ctx* c);  // destroys the rocBLAS handle if one was created
 
 hipEvent_t ctx_event(uqc_ctx* c, size_t i);
+// Stream i of a build spread over several: 0 is the context's stream, 1..3 the context's extra streams (created on
+// first use, default priority).  nullptr if creation fails.
+hipStream_t ctx_stream(uqc_ctx* c, int i);
 
 namespace uqc {
 

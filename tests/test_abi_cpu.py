@@ -35,6 +35,7 @@ def test_library_has_gfx950_code_object():
 def test_default_options():
     o = uqc.default_opts()
     assert o.schwarz_tau == 1e-12 and o.precision == uqc.FP64 and o.fp64_bound == 1e-8 and o.timing == 0
+    assert o.streams == 3
     assert not o.progress and o.max_items_per_launch == 0 and o.exchange_scale == 1.0
 
 
@@ -75,7 +76,8 @@ def test_struct_layouts_match_header(tmp_path):
     """The ctypes mirrors of the public structs have the C compiler's sizes and field offsets."""
     import subprocess
     fields = {"uqc_fock_opts": (uqc.FockOpts, ["schwarz_tau", "precision", "fp64_bound", "timing", "progress",
-                                                 "progress_user", "max_items_per_launch", "exchange_scale"]),
+                                                 "progress_user", "max_items_per_launch", "exchange_scale",
+                                                 "streams"]),
               "uqc_stats": (uqc.Stats, [f for f, _ in uqc.Stats._fields_]),
               "uqc_scf_opts": (uqc.ScfOpts, [f for f, _ in uqc.ScfOpts._fields_]),
               "uqc_scf_result": (uqc.ScfResult, [f for f, _ in uqc.ScfResult._fields_]),

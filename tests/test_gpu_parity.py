@@ -198,6 +198,36 @@ def test_fock_split_launches_and_progress(ctx):
     _check_fock(B, O, D, 1e-12, J2, K2, G2, st2)
 
 
+@pytest.mark.parametrize("streams", [2, 3, 4])
+def test_fock_several_streams(ctx, streams):
+    """Class launches spread over several HIP streams (joined back before the final pass) give the one-stream J, K,
+    G up to atomic-order rounding and match the oracle; timing still reports every class; the spin-density build
+    takes the same path; out-of-range stream counts are rejected."""
+    w = wl.lattice(9, seed=36, ndens=1, tau=1e-12)
+    B = uqc.Basis(ctx, w.shells)
+    O = oracle.Basis(w.shells)
+    D = w.densities[0]
+    J1, K1, G1, st1 = B.fock_build(D, uqc.default_opts(tau=1e-12, streams=1))
+    for rep in range(2):  # the second build orders classes by the first one's FLOPs
+        J2, K2, G2, st2 = B.fock_build(D, uqc.default_opts(tau=1e-12, streams=streams, timing=True))
+        for a, b in [(J1, J2), (K1, K2), (G1, G2)]:
+            ok, err, m = close(b, a, tol=1e-13)
+            assert ok, (rep, err, m)
+        assert st1.quartets == st2.quartets and st2.nclass > 1 and all(
+            st2.class_ms[c] > 0 for c in range(st2.nclass))
+    _check_fock(B, O, D, 1e-12, J2, K2, G2, st2)
+    Db = 0.5 * D
+    one = B.fock_build_uhf(D, Db, uqc.default_opts(tau=1e-12, streams=1), want=("Ga", "Gb"))
+    many = B.fock_build_uhf(D, Db, uqc.default_opts(tau=1e-12, streams=streams), want=("Ga", "Gb"))
+    for k in ("Ga", "Gb"):
+        ok, err, m = close(many[k], one[k], tol=1e-13)
+        assert ok, (k, err, m)
+    for bad in (-1, 5):
+        with pytest.raises(uqc.UqcError) as e:
+            B.fock_build(D, uqc.default_opts(tau=1e-12, streams=bad))
+        assert e.value.status == uqc.UQC_E_ARG
+
+
 def test_fock_zero_and_linear(ctx):
     w = wl.lattice(4, seed=33, ndens=2)
     B = uqc.Basis(ctx, w.shells)
