@@ -690,7 +690,8 @@ def bench_serve(a):
             if arrive > now:
                 time.sleep(arrive - now)
             tickets.append(srv.submit(r.shells, r.D0, n_iter=8, ncol=max(1, r.natoms // 2), eps=0.05,
-                                      seed=4000 + r.rid, opts=uqc.default_opts(tau=1e-12, precision=prec)))
+                                      seed=4000 + r.rid, opts=uqc.default_opts(tau=1e-12, precision=prec,
+                                                                                streams=a.streams)))
         done = {}
         last = time.perf_counter()
         while len(done) < len(tickets):

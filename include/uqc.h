@@ -262,7 +262,8 @@ typedef struct {
     int ncol;                   /* columns of R_t (>= 1) */
     double eps;                 /* perturbation weight in [0, 1] */
     unsigned long long seed;
-    uqc_fock_opts opts;         /* its progress callback is not used by the server */
+    uqc_fock_opts opts;         /* its progress callback is not used by the server; a step spreads its class
+                                   launches over as many streams as any admitted request's opts.streams asks for */
     double arrival_ms;          /* arrival time stamp on the caller's clock (reported back; informational) */
 } uqc_request;
 

@@ -166,6 +166,7 @@ bool uqc_server::step() {
         std::vector<TaskDev> tasks;
         std::vector<long long> begin;
         long long items = 0;
+        double flops = 0;  // of the requests' previous builds (0 before the first)
     };
     std::vector<G> groups;
     for (Req* r : act)
@@ -174,9 +175,10 @@ bool uqc_server::step() {
             for (auto& x : groups)
                 if (x.cls == g.cls && x.mixed == g.mixed) dst = &x;
             if (!dst) {
-                groups.push_back(G{g.cls, g.mixed, {}, {}, 0});
+                groups.push_back(G{g.cls, g.mixed, {}, {}, 0, 0.0});
                 dst = &groups.back();
             }
+            dst->flops += g.flops;
             for (TaskDev t : g.host_tasks) {
                 t.item_begin = dst->items;
                 dst->begin.push_back(dst->items);
@@ -211,12 +213,37 @@ bool uqc_server::step() {
     }
     if (pos && hipMemcpyAsync(d_tasks, host.data(), pos, hipMemcpyHostToDevice, s) != hipSuccess)
         return fail_all("server: task upload failed");
-    for (size_t gi = 0; gi < groups.size(); ++gi)
+    // classes side by side on several streams, as in a single build (the most any admitted request asks for):
+    // largest first, each to the least-loaded stream (weights: FLOPs of the previous step when every group has
+    // them, else work items)
+    int kStreams = 1;
+    for (Req* r : act) kStreams = std::max(kStreams, r->opts.streams);
+    hipStream_t S[4] = {s, nullptr, nullptr, nullptr};
+    for (int k = 1; k < kStreams; ++k)
+        if (!(S[k] = ctx_stream(ctx, k))) return fail_all("server: stream creation failed");
+    bool have_flops = true;
+    for (auto& g : groups) have_flops = have_flops && g.flops > 0;
+    std::vector<size_t> order(groups.size());
+    for (size_t gi = 0; gi < groups.size(); ++gi) order[gi] = gi;
+    auto weight = [&](size_t gi) { return have_flops ? groups[gi].flops : (double)groups[gi].items; };
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return weight(x) > weight(y); });
+    if (kStreams > 1 && hipEventRecord(ctx->fork, s) != hipSuccess) return fail_all("server: event record failed");
+    for (int k = 1; k < kStreams; ++k)
+        if (hipStreamWaitEvent(S[k], ctx->fork, 0) != hipSuccess) return fail_all("server: stream wait failed");
+    double load[4] = {0, 0, 0, 0};
+    for (size_t gi : order) {
+        const int k = (int)(std::min_element(load, load + kStreams) - load);
+        load[k] += weight(gi);
         for (long long i0 = 0; i0 < groups[gi].items; i0 += kMaxItemsPerLaunch)
             if (launch_digest(groups[gi].cls, groups[gi].mixed, 1, ptrs[gi].first, ptrs[gi].second,
                               (int)groups[gi].tasks.size(), i0, std::min(kMaxItemsPerLaunch, groups[gi].items - i0),
-                              ctx->boys64, ctx->boys32, s) != hipSuccess)
+                              ctx->boys64, ctx->boys32, S[k]) != hipSuccess)
                 return fail_all("server: class launch failed");
+    }
+    for (int k = 1; k < kStreams; ++k)
+        if (hipEventRecord(ctx->join[k - 1], S[k]) != hipSuccess || hipStreamWaitEvent(s, ctx->join[k - 1], 0) !=
+                                                                         hipSuccess)
+            return fail_all("server: stream join failed");
     std::vector<double> e2(act.size());
     for (size_t i = 0; i < act.size(); ++i) {
         uqc_basis* B = act[i]->basis;
@@ -355,6 +382,10 @@ uqc_status uqc_submit(uqc_server* s, const uqc_request* q, long long* ticket) {
     if (!std::isfinite(r->opts.exchange_scale)) {
         delete r;
         return uqc_fail(UQC_E_ARG, "uqc_submit: exchange_scale is not finite");
+    }
+    if (r->opts.streams < 0 || r->opts.streams > 4) {
+        delete r;
+        return uqc_fail(UQC_E_ARG, "uqc_submit: streams must be in 0..4");
     }
     r->footprint = estimate_footprint(*r);
     std::lock_guard<std::mutex> lk(s->mu);

@@ -145,11 +145,33 @@ def test_server_rejects_bad_requests(ctx):
     with pytest.raises(uqc.UqcError) as e:
         srv.submit(sh, D, n_iter=0)
     assert e.value.status == uqc.UQC_E_ARG
+    for bad in (-1, 5):
+        with pytest.raises(uqc.UqcError) as e:
+            srv.submit(sh, D, n_iter=2, opts=uqc.default_opts(streams=bad))
+        assert e.value.status == uqc.UQC_E_ARG
     t = srv.submit(sh, D, n_iter=2)
     srv.drain()
     out = srv.poll(t)
     assert out is not None and out["n_iter"] == 2
     srv.close()
+
+
+def test_server_steps_on_one_or_several_streams(ctx):
+    """The batched step with its class launches on one stream and spread over four gives the same E2 sequence and
+    final G for every request (up to atomic-order rounding)."""
+    reqs = _requests()
+    res = {}
+    for ns in (1, 4):
+        rq = []
+        for r in reqs:
+            o = r["opts"]
+            rq.append(dict(r, opts=uqc.default_opts(tau=o.schwarz_tau, precision=o.precision,
+                                                    fp64_bound=o.fp64_bound, streams=ns)))
+        res[ns] = _run(ctx, rq, slots=4, stagger_s=0.002)
+    for a, b in zip(res[1], res[4]):
+        assert a["n_iter"] == b["n_iter"]
+        assert np.max(np.abs(np.array(a["E2"]) - np.array(b["E2"]))) <= 1e-12 * np.max(np.abs(a["E2"]))
+        assert np.max(np.abs(a["G"] - b["G"])) <= 1e-12 * np.max(np.abs(a["G"]))
 
 
 def test_server_honours_exchange_scale(ctx):
