@@ -54,8 +54,10 @@ typedef enum {
 typedef enum { UQC_FP64 = 0, UQC_MIXED = 1, UQC_RYS = 2 } uqc_precision;
 
 /* Progress report of a Fock build: called on the calling thread after every class sub-launch has completed on the
- * device (items_done of items_total work items of class class_id, encoded as in uqc_stats.class_id).  Setting it
- * makes the build wait for each sub-launch; the work itself is unchanged. */
+ * device (items_done of items_total work items of class class_id, encoded as in uqc_stats.class_id; for each class
+ * in increasing order).  On one stream the build waits for each sub-launch before queuing the next; on several,
+ * every sub-launch is queued first and the reports follow their completion, in the order they were queued.  The
+ * work itself is unchanged. */
 typedef void (*uqc_progress_fn)(void* user, int class_id, long long items_done, long long items_total);
 
 /* Options of a Fock build.  Call uqc_fock_opts_default() first. */
@@ -80,7 +82,7 @@ typedef struct {
                                priority), ordered after the work already queued on the context's stream and joined
                                back into it before the build's final pass, so callers see one stream either way.
                                Kernels of different classes then run side by side, which fills the chip while
-                               one class's launch drains.  Default 3.  Ignored (1) with progress. */
+                               one class's launch drains.  Default 3. */
 } uqc_fock_opts;
 
 #define UQC_MAX_CLASS_STATS 96

@@ -1182,7 +1182,7 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
     // Classes spread over several streams: largest first (FLOPs of the previous build, else work items), each to
     // the stream with the least work so far.  The extra streams wait for everything queued on the context's stream
     // so far and are joined back into it after their last launch.
-    const int nst = o.progress ? 1 : std::max(1, o.streams);
+    const int nst = std::max(1, o.streams);
     const size_t ng = plan->groups.size();
     std::vector<size_t> order(ng);
     std::vector<int> gstream(ng, 0);
@@ -1203,6 +1203,13 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
     hipStream_t S[4] = {s, nullptr, nullptr, nullptr};
     for (int k = 1; k < nst; ++k)
         if (!(S[k] = ctx_stream(ctx, k))) return uqc_fail(UQC_E_DEVICE, nm + ": stream creation failed");
+    // progress on several streams: an event after every sub-launch, waited for in issue order once all are queued
+    struct SubLaunch {
+        size_t ev;
+        int cid;
+        long long done, total;
+    };
+    std::vector<SubLaunch> subs;
     auto pass = [&]() -> uqc_status {
         if (plan->ntasks) UQC_HIP(launch_zero((double*)plan->d_count, 2 * (size_t)plan->ntasks, s));
         if (nst > 1) {
@@ -1220,9 +1227,15 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
                 const long long n = std::min(max_items, g.nitems - i0);
                 UQC_HIP(launch_digest(g.cls, g.mixed, nspin, g.d_tasks, g.d_begin, g.ntask, i0, n, ctx->boys64,
                                       ctx->boys32, gs));
-                if (o.progress) {
+                if (o.progress && nst == 1) {
                     UQC_HIP(hipStreamSynchronize(gs));
                     o.progress(o.progress_user, cid, i0 + n, g.nitems);
+                } else if (o.progress) {
+                    const size_t ev = 2 * ng + subs.size();
+                    hipEvent_t e = ctx_event(ctx, ev);
+                    if (!e) return uqc_fail(UQC_E_DEVICE, nm + ": event creation failed");
+                    UQC_HIP(hipEventRecord(e, gs));
+                    subs.push_back(SubLaunch{ev, cid, i0 + n, g.nitems});
                 }
             }
             if (timing) UQC_HIP(hipEventRecord(ctx_event(ctx, 2 * gi + 1), gs));
@@ -1230,6 +1243,10 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
         for (int k = 1; k < nst; ++k) {
             UQC_HIP(hipEventRecord(ctx->join[k - 1], S[k]));
             UQC_HIP(hipStreamWaitEvent(s, ctx->join[k - 1], 0));
+        }
+        for (const SubLaunch& sb : subs) {
+            UQC_HIP(hipEventSynchronize(ctx->events[sb.ev]));
+            o.progress(o.progress_user, sb.cid, sb.done, sb.total);
         }
         if (timing) {
             UQC_HIP(hipStreamSynchronize(s));

@@ -206,10 +206,10 @@ def default_opts(tau: float = 1e-12, precision: int = FP64, fp64_bound: float = 
                  progress=None, max_items_per_launch: int = 0, exchange_scale: float = 1.0,
                  streams: int | None = None):
     """Fock-build options.  progress: None or a callable(class_id, items_done, items_total) called after every
-    class sub-launch has completed on the device (the build then waits for each one).  max_items_per_launch: cap
-    on the work items of one class-kernel launch (0: the library default).  exchange_scale: weight x of exchange
-    (G = J - (x/2) K; spin densities G^s = J - x K^s).  streams: HIP streams the class launches are spread over
-    (None: the library default)."""
+    class sub-launch has completed on the device (on one stream the build then waits for each one).
+    max_items_per_launch: cap on the work items of one class-kernel launch (0: the library default).
+    exchange_scale: weight x of exchange (G = J - (x/2) K; spin densities G^s = J - x K^s).  streams: HIP streams
+    the class launches are spread over (None: the library default)."""
     o = FockOpts()
     load().uqc_fock_opts_default(ctypes.byref(o))
     o.schwarz_tau = float(tau)

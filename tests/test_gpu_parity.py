@@ -173,9 +173,11 @@ def test_fock_device_pointers_match_host(ctx):
     assert abs(st.E2 - st2.E2) <= 1e-13 * abs(st.E2)
 
 
-def test_fock_split_launches_and_progress(ctx):
+@pytest.mark.parametrize("streams", [1, 3])
+def test_fock_split_launches_and_progress(ctx, streams):
     """Class launches split into many small ones (7 work items each, ragged ends) give the same J, K, G as single
-    launches; the progress report reaches every class's item total, in increasing steps."""
+    launches; the progress report reaches every class's item total, in increasing steps, with the class launches on
+    one stream (a wait after each) and on three (reports after all are queued)."""
     w = wl.lattice(9, seed=35, ndens=1, tau=1e-12)
     B = uqc.Basis(ctx, w.shells)
     O = oracle.Basis(w.shells)
@@ -188,7 +190,8 @@ def test_fock_split_launches_and_progress(ctx):
         assert prev[1] == total and done > prev[0] and done <= total
         seen[cid] = (done, total)
 
-    J2, K2, G2, st2 = B.fock_build(D, uqc.default_opts(tau=1e-12, progress=report, max_items_per_launch=7))
+    J2, K2, G2, st2 = B.fock_build(D, uqc.default_opts(tau=1e-12, progress=report, max_items_per_launch=7,
+                                                        streams=streams))
     assert seen and all(done == total for done, total in seen.values())
     assert any(total > 7 for _, total in seen.values())
     for a, b in [(J1, J2), (K1, K2), (G1, G2)]:
