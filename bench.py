@@ -30,19 +30,26 @@ METRIC = "shell quartets/s and Fock builds/s at ≤1e-6 Eh vs FP64; p50/p99 buil
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_medium60_fp64.json")
 
 
+# Sources of the Fock-build kernels (the class-kernel unit and the headers it includes, the prepare/finalize unit,
+# the generators and what they wrote); host-only files (the C ABI, SCF driver, server) do not change the kernels.
+KERNEL_SOURCES = ("uqc_eri_class.hip", "uqc_eri_impl.h", "uqc_eri_team.h", "uqc_rys.h", "uqc_device_common.h",
+                  "uqc_internal.h", "uqc_kernels.hip")
+
+
 def kernel_sources_sha256() -> str:
-    """Hash of every source the device kernels are built from (traffic counters are only valid for these); the Rys
-    table headers are generated at build time from gen_rys.py, which is hashed, so they are left out."""
+    """Hash of every source the Fock-build kernels are built from (traffic counters are only valid for these); the
+    Rys table headers are generated at build time from gen_rys.py, which is hashed, so they are left out."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1303_4916_amd", "csrc")
-    for d in (csrc, os.path.join(csrc, "generated")):
-        for f in sorted(os.listdir(d)):
-            if f in ("rys_consts.h", "rys_table.h"):
-                continue
-            if f.endswith((".h", ".hip", ".cpp", ".py")):
-                h.update(f.encode())
-                h.update(open(os.path.join(d, f), "rb").read())
+    names = [os.path.join(csrc, f) for f in KERNEL_SOURCES]
+    names += sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith(".py"))
+    gen = os.path.join(csrc, "generated")
+    names += sorted(os.path.join(gen, f) for f in os.listdir(gen)
+                    if f.endswith((".h", ".json")) and f not in ("rys_consts.h", "rys_table.h"))
+    for n in names:
+        h.update(os.path.basename(n).encode())
+        h.update(open(n, "rb").read())
     return h.hexdigest()
 
 
