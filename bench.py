@@ -31,7 +31,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_medium60_fp64.json")
 
 
 # Sources of the Fock-build kernels (the class-kernel unit and the headers it includes, the prepare/finalize unit,
-# the generators and what they wrote); host-only files (the C ABI, SCF driver, server) do not change the kernels.
+# the generators and what they wrote, and the build step that sets per-class compile options); host-only files (the
+# C ABI, SCF driver, server) do not change the kernels.
 KERNEL_SOURCES = ("uqc_eri_class.hip", "uqc_eri_impl.h", "uqc_eri_team.h", "uqc_rys.h", "uqc_device_common.h",
                   "uqc_internal.h", "uqc_kernels.hip")
 
@@ -44,6 +45,7 @@ def kernel_sources_sha256() -> str:
     csrc = os.path.join(ROOT, "paper_1303_4916_amd", "csrc")
     names = [os.path.join(csrc, f) for f in KERNEL_SOURCES]
     names += sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith(".py"))
+    names.append(os.path.join(ROOT, "paper_1303_4916_amd", "build.py"))
     gen = os.path.join(csrc, "generated")
     names += sorted(os.path.join(gen, f) for f in os.listdir(gen)
                     if f.endswith((".h", ".json")) and f not in ("rys_consts.h", "rys_table.h"))

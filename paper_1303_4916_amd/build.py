@@ -30,9 +30,10 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-ato
 
 PAIR = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 
-# classes whose quartet kernel is asked to fit two wavefronts per SIMD (a few bytes of spill buy twice the
-# occupancy); the others keep the compiler's register choice
-TWO_WAVES = {(2, 0, 1, 1), (2, 1, 2, 1), (2, 2, 1, 1)}
+# classes whose quartet kernel is asked to fit a given number of wavefronts per SIMD, one more than the compiler's
+# own register choice gives (none to a few dozen bytes of spill, measured faster per class); the others keep the
+# compiler's choice (for them one more wavefront costs 130-340 bytes of spill per lane and was slower)
+WAVES_PER_EU = {(2, 0, 1, 1): 2, (2, 1, 2, 1): 2, (2, 2, 1, 1): 2, (1, 1, 0, 0): 4, (1, 0, 1, 0): 4, (2, 0, 1, 0): 3}
 # classes that do not keep their K_ac sums in LDS (the slots would cost them a wavefront per SIMD)
 KAC_NOT_IN_LDS = {(2, 1, 1, 0)}
 
@@ -69,8 +70,8 @@ def _units():
         units.append((os.path.join(CSRC, "uqc_eri_class.hip"), os.path.join(OBJ, "eri_class_%02d.o" % i),
                       ["-DUQC_CLASS_ID=%d" % i, "-DUQC_LA=%d" % la, "-DUQC_LB=%d" % lb, "-DUQC_LC=%d" % lc,
                        "-DUQC_LD=%d" % ld, "-DUQC_TEAM=%d" % (1 if (la, lb, lc, ld) in team else 0)] +
-                      (["-DUQC_WAVES_ATTR=__attribute__((amdgpu_waves_per_eu(2)))"]
-                       if (la, lb, lc, ld) in TWO_WAVES else []) +
+                      (["-DUQC_WAVES_ATTR=__attribute__((amdgpu_waves_per_eu(%d)))" % WAVES_PER_EU[(la, lb, lc, ld)]]
+                       if (la, lb, lc, ld) in WAVES_PER_EU else []) +
                       (["-DUQC_KAC_LDS=0"] if (la, lb, lc, ld) in KAC_NOT_IN_LDS else []), headers))
     for src in ("uqc_kernels.hip", "uqc_one.hip", "uqc_mp2.hip", "uqc_api.cpp", "uqc_serve.cpp", "uqc_scf.cpp"):
         units.append((os.path.join(CSRC, src), os.path.join(OBJ, os.path.splitext(src)[0] + ".o"), [], headers))
