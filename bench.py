@@ -208,7 +208,7 @@ def main():
     ap.add_argument("--streams", type=int, default=None,
                     help="HIP streams the class launches of one Fock build are spread over (default: the library's)")
     ap.add_argument("--fp64-only", action="store_true",
-                    help="mixed150/large400: time the FP64 build only (no mixed build, no mixed-vs-FP64 errors)")
+                    help="mixed150/large400/serve: time the FP64 leg only (no mixed build, no mixed-vs-FP64 errors)")
     ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                                                          "COPY_WRITE_CSV", "CMD"),
                     help="write the per-kernel traffic summary from rocprofv3 counter CSVs and exit")
@@ -689,7 +689,8 @@ def bench_serve(a):
            "config": {"workload": "poisson%g_4to120atoms_8iter: first %d of 512 requests%s" % (
                a.rate, len(stream), "" if a.rate == 200.0 else " (arrival times of the 200 req/s stream scaled)"),
                       "budget_GiB": 64, "slots": 16}}
-    for prec_name, prec in [("fp64", uqc.FP64), ("mixed", uqc.MIXED)]:
+    legs = [("fp64", uqc.FP64), ("mixed", uqc.MIXED)]
+    for prec_name, prec in legs[:1] if a.fp64_only else legs:
         srv = uqc.Server(ctx, 64 << 30, 16)
         t0 = time.perf_counter()
         tickets = []
@@ -728,7 +729,8 @@ def bench_serve(a):
                           "p99_latency_ms": float(np.percentile(lat, 99))}
     out["value"] = out["fp64"]["quartets_per_s"]
     out["unit"] = "shell quartets/s"
-    out["mixed_speedup_vs_fp64"] = out["fp64"]["wall_s"] / out["mixed"]["wall_s"]
+    if "mixed" in out:
+        out["mixed_speedup_vs_fp64"] = out["fp64"]["wall_s"] / out["mixed"]["wall_s"]
     print(json.dumps(out), flush=True)
     ctx.close()
 
