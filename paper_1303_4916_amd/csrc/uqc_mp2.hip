@@ -109,43 +109,62 @@ uqc_status uqc_mp2(uqc_basis* B, const double* C, const double* eps, int nocc, i
     UQC_HIP(launch_zero(T0, N4, s));
     long long quartets = 0;
     {
-        size_t maxn = 0;
-        for (size_t X = 0; X < B->bins.size(); ++X)
-            for (size_t Y = 0; Y <= X; ++Y) maxn = std::max(maxn, (size_t)B->bins[X].np * B->bins[Y].np);
-        DevBuf ib;
-        if (hipMalloc(&ib.p, 2 * std::max<size_t>(maxn, 1) * sizeof(int)) != hipSuccess)
-            return uqc_fail(UQC_E_NOMEM, "uqc_mp2: quartet list");
-        int* dbra = (int*)ib.p;
-        int* dket = dbra + maxn;
+        // the lists of every bin pair in one host buffer and one upload; the class launches then run side by side on
+        // the context's stream and two more (the tensor positions they write are disjoint across canonical quartets)
+        struct Seg {
+            size_t X, Y, off;
+            int n;
+        };
+        std::vector<Seg> segs;
         std::vector<int> hb, hk;
         for (size_t X = 0; X < B->bins.size(); ++X)
             for (size_t Y = 0; Y <= X; ++Y) {
                 const Bin &bx = B->bins[X], &by = B->bins[Y];
-                hb.clear();
-                hk.clear();
+                const size_t off = hb.size();
                 for (int p = 0; p < bx.np; ++p)
                     for (int q = 0; q < (X == Y ? p + 1 : by.np); ++q)
                         if (bx.Q[p] * by.Q[q] >= tau) {
                             hb.push_back(p);
                             hk.push_back(q);
                         }
-                if (hb.empty()) continue;
-                const int n = (int)hb.size();
-                UQC_HIP(hipMemcpyAsync(dbra, hb.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
-                UQC_HIP(hipMemcpyAsync(dket, hk.data(), n * sizeof(int), hipMemcpyHostToDevice, s));
-                ListDev L;
-                L.bra = bx.dev;
-                L.ket = by.dev;
-                L.bra_idx = dbra;
-                L.ket_idx = dket;
-                L.n = n;
-                L.out = T0;
-                L.nbf = N;
-                UQC_HIP(launch_list(class_index(bx.la, bx.lb, by.la, by.lb), false, MODE_SCATTER, L, ctx->boys64,
-                                    ctx->boys32, s));
-                UQC_HIP(hipStreamSynchronize(s));  // the host index arrays are reused
-                quartets += n;
+                if (hb.size() > off) segs.push_back(Seg{X, Y, off, (int)(hb.size() - off)});
             }
+        const size_t total = hb.size();
+        DevBuf ib;
+        if (hipMalloc(&ib.p, 2 * std::max<size_t>(total, 1) * sizeof(int)) != hipSuccess)
+            return uqc_fail(UQC_E_NOMEM, "uqc_mp2: quartet list");
+        int* dbra = (int*)ib.p;
+        int* dket = dbra + total;
+        if (total) {
+            UQC_HIP(hipMemcpyAsync(dbra, hb.data(), total * sizeof(int), hipMemcpyHostToDevice, s));
+            UQC_HIP(hipMemcpyAsync(dket, hk.data(), total * sizeof(int), hipMemcpyHostToDevice, s));
+        }
+        constexpr int kStreams = 3;
+        hipStream_t S[kStreams] = {s, nullptr, nullptr};
+        for (int k = 1; k < kStreams; ++k)
+            if (!(S[k] = ctx_stream(ctx, k))) return uqc_fail(UQC_E_DEVICE, "uqc_mp2: stream creation failed");
+        UQC_HIP(hipEventRecord(ctx->fork, s));
+        for (int k = 1; k < kStreams; ++k) UQC_HIP(hipStreamWaitEvent(S[k], ctx->fork, 0));
+        for (size_t i = 0; i < segs.size(); ++i) {
+            const Seg& g = segs[i];
+            const Bin &bx = B->bins[g.X], &by = B->bins[g.Y];
+            ListDev L;
+            L.bra = bx.dev;
+            L.ket = by.dev;
+            L.bra_idx = dbra + g.off;
+            L.ket_idx = dket + g.off;
+            L.n = g.n;
+            L.out = T0;
+            L.nbf = N;
+            UQC_HIP(launch_list(class_index(bx.la, bx.lb, by.la, by.lb), false, MODE_SCATTER, L, ctx->boys64,
+                                ctx->boys32, S[i % kStreams]));
+            quartets += g.n;
+        }
+        for (int k = 1; k < kStreams; ++k) {
+            UQC_HIP(hipEventRecord(ctx->join[k - 1], S[k]));
+            UQC_HIP(hipStreamWaitEvent(s, ctx->join[k - 1], 0));
+        }
+        UQC_HIP(hipStreamSynchronize(s));  // the index lists are freed at the end of this block
     }
     const auto t1 = std::chrono::steady_clock::now();
 
