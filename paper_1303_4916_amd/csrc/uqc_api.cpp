@@ -181,6 +181,17 @@ hipEvent_t ctx_event(uqc_ctx* c, size_t i) {
     return c->events[i];
 }
 
+std::vector<size_t> interleave_ends(const std::vector<size_t>& v) {
+    std::vector<size_t> out;
+    out.reserve(v.size());
+    size_t lo = 0, hi = v.size();
+    while (lo < hi) {
+        out.push_back(v[lo++]);
+        if (lo < hi) out.push_back(v[--hi]);
+    }
+    return out;
+}
+
 hipStream_t ctx_stream(uqc_ctx* c, int i) {
     if (i == 0) return c->stream;
     if (i < 1 || i > 3) return nullptr;
@@ -1180,8 +1191,9 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
     const bool timing = o.timing != 0;
     std::vector<double> cls_ms(plan->groups.size(), 0.0);
     // Classes spread over several streams: largest first (FLOPs of the previous build, else work items), each to
-    // the stream with the least work so far.  The extra streams wait for everything queued on the context's stream
-    // so far and are joined back into it after their last launch.
+    // the stream with the least work so far; then queued largest, smallest, second largest, second smallest, ...,
+    // so that every stream alternates long and short kernels and their drains overlap.  The extra streams wait for
+    // everything queued on the context's stream so far and are joined back into it after their last launch.
     const int nst = std::max(1, o.streams);
     const size_t ng = plan->groups.size();
     std::vector<size_t> order(ng);
@@ -1199,6 +1211,7 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
             gstream[gi] = k;
             load[k] += weight(gi);
         }
+        order = interleave_ends(order);
     }
     hipStream_t S[4] = {s, nullptr, nullptr, nullptr};
     for (int k = 1; k < nst; ++k)

@@ -37,6 +37,8 @@ hipEvent_t ctx_event(uqc_ctx* c, size_t i);
 // Stream i of a build spread over several: 0 is the context's stream, 1..3 the context's extra streams (created on
 // first use, default priority).  nullptr if creation fails.
 hipStream_t ctx_stream(uqc_ctx* c, int i);
+// v[0], v[n-1], v[1], v[n-2], ...: launch order of classes sorted largest first
+std::vector<size_t> interleave_ends(const std::vector<size_t>& v);
 
 namespace uqc {
 

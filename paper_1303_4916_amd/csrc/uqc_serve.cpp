@@ -215,7 +215,7 @@ bool uqc_server::step() {
         return fail_all("server: task upload failed");
     // classes side by side on several streams, as in a single build (the most any admitted request asks for):
     // largest first, each to the least-loaded stream (weights: FLOPs of the previous step when every group has
-    // them, else work items)
+    // them, else work items), queued alternately from the large and the small end
     int kStreams = 1;
     for (Req* r : act) kStreams = std::max(kStreams, r->opts.streams);
     hipStream_t S[4] = {s, nullptr, nullptr, nullptr};
@@ -231,9 +231,14 @@ bool uqc_server::step() {
     for (int k = 1; k < kStreams; ++k)
         if (hipStreamWaitEvent(S[k], ctx->fork, 0) != hipSuccess) return fail_all("server: stream wait failed");
     double load[4] = {0, 0, 0, 0};
+    std::vector<int> gstream(groups.size(), 0);
     for (size_t gi : order) {
         const int k = (int)(std::min_element(load, load + kStreams) - load);
         load[k] += weight(gi);
+        gstream[gi] = k;
+    }
+    for (size_t gi : interleave_ends(order)) {
+        const int k = gstream[gi];
         for (long long i0 = 0; i0 < groups[gi].items; i0 += kMaxItemsPerLaunch)
             if (launch_digest(groups[gi].cls, groups[gi].mixed, 1, ptrs[gi].first, ptrs[gi].second,
                               (int)groups[gi].tasks.size(), i0, std::min(kMaxItemsPerLaunch, groups[gi].items - i0),
