@@ -222,7 +222,7 @@ def main():
         summarize_pmc(*a.summarize_pmc[:4], TRAFFIC_FILE, a.summarize_pmc[4])
         return
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the Fock build would shard by "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the Fock build would shard by "
               "bra-pair work lists with one all-reduce of J and K; not built).", file=sys.stderr)
         sys.exit(2)
 
