@@ -8,9 +8,11 @@ ten fresh PSD densities (trace 60) cycled over the steps.  The basis plan (norma
 work lists) is built once before the timed region and reported separately (plan_ms).  Densities and outputs stay
 in device memory (torch tensors); the call is synchronous.
 
+The timed builds use the library's default launch configuration (class kernels spread over three HIP streams).
 Printed: one JSON line with the metric, the per-build latency percentiles, the roofline line of the dominant
 class kernel (algorithmic FLOPs from the frozen per-class operation counts / its average launch time measured with
-HIP events on the library's stream) and the oracle timed on a bounded sample on the host cores.
+HIP events on the stream it runs on, in a second pass of the same builds with every class launch on one stream)
+and the oracle timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
 
