@@ -67,7 +67,8 @@ typedef struct {
                              quartets with Q_ab Q_cd > fp64_bound (whole quartet in FP64) and Boys arguments
                              T > 30 (Boys function evaluated in FP64); J, K, G, E2 always accumulated in FP64 */
     double fp64_bound;    /* default 1e-8 */
-    int timing;           /* 1: time every class launch with HIP events (reported in uqc_stats) */
+    int timing;           /* 1: time every class launch with HIP events on its stream (reported in uqc_stats; with
+                             several streams a class's time includes the kernels that run beside it) */
     uqc_progress_fn progress;   /* NULL (default) or a progress report, see uqc_progress_fn */
     void* progress_user;        /* passed to progress */
     long long max_items_per_launch;  /* > 0: cap on the work items of one class-kernel launch (longer classes are
@@ -82,7 +83,7 @@ typedef struct {
                                priority), ordered after the work already queued on the context's stream and joined
                                back into it before the build's final pass, so callers see one stream either way.
                                Kernels of different classes then run side by side, which fills the chip while
-                               one class's launch drains.  Default 3. */
+                               one class's launch drains.  Default 3; outside 0..4: UQC_E_ARG. */
 } uqc_fock_opts;
 
 #define UQC_MAX_CLASS_STATS 96
