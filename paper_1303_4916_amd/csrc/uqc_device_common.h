@@ -119,13 +119,16 @@ __device__ __forceinline__ void boys64(double T, double pref, const double* __re
 }
 
 // FP32 variant (mixed mode, T <= 30 only): Taylor order 5 around the same grid points (truncation < 1e-10
-// relative); the grid offset d is exact in FP32 because the grid spacing is a power of two.  No step rounds the
-// same way for every argument (no library exp, no rounded reciprocal constant), so the FP32 errors of many small
-// integrals do not add up to a bias.
+// relative).  The argument arrives in FP64: the grid point and the offset d = T_g - T are taken from it before
+// rounding (rounding T itself to FP32 first would move F_m by up to (m + 1/2) units of FP32 rounding through
+// dF_m/dT = -F_{m+1}), so only the series and the downward recursion run in FP32.  No step rounds the same way for
+// every argument (no library exp, no rounded reciprocal constant), so the FP32 errors of many small integrals do
+// not add up to a bias.
 template <int L>
-__device__ __forceinline__ void boys32(float T, const float* __restrict__ tab, float* F) {
-    const int g = (int)(T * (float)kBoysGridPerUnit + 0.5f);
-    const float d = (float)g * (1.0f / kBoysGridPerUnit) - T;
+__device__ __forceinline__ void boys32(double Td, const float* __restrict__ tab, float* F) {
+    const int g = (int)(Td * (double)kBoysGridPerUnit + 0.5);
+    const float d = (float)((double)g * (1.0 / kBoysGridPerUnit) - Td);
+    const float T = (float)Td;
     const float* r = tab + g * kBoysNm + L;
     float p = r[5];
     p = fmaf(p, d * 0.2f, r[4]);

@@ -140,7 +140,7 @@ __device__ __forceinline__ void accumulate(const BinDev& B, int bra, int kbn, co
                 g.o2ze = (float)(0.5 * inv);
                 float F[C::L + 1];
                 if (T <= (double)kBoysTmax32) {
-                    boys32<C::L>((float)T, boys32tab, F);
+                    boys32<C::L>(T, boys32tab, F);
                     const float pf = (float)pref;
 #pragma unroll
                     for (int m = 0; m <= C::L; ++m) F[m] *= pf;

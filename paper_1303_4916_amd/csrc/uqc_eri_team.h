@@ -84,7 +84,7 @@ __device__ __forceinline__ void team_accumulate(const BinDev& B, int bra, int kb
                 g.o2ze = (float)(0.5 * inv);
                 float F[TC::L + 1];
                 if (T <= (double)kBoysTmax32) {
-                    boys32<TC::L>((float)T, boys32tab, F);
+                    boys32<TC::L>(T, boys32tab, F);
                     const float pf = (float)pref;
 #pragma unroll
                     for (int m = 0; m <= TC::L; ++m) F[m] *= pf;

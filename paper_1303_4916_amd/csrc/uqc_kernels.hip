@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_boys(int prec, int n, const double* 
         for (int m = 0; m <= L; ++m) out[(size_t)x * (L + 1) + m] = F[m];
     } else {
         float F[L + 1];
-        boys32<L>((float)t, b32, F);
+        boys32<L>(t, b32, F);
         for (int m = 0; m <= L; ++m) out[(size_t)x * (L + 1) + m] = (double)F[m];
     }
 }

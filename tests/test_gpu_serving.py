@@ -193,3 +193,32 @@ def test_server_honours_exchange_scale(ctx):
     assert np.max(np.abs(G - (J - 0.125 * K))) <= 1e-13 * np.max(np.abs(G))
     B.close()
     srv.close()
+
+
+def test_server_results_match_oracle(ctx):
+    """Every request of a mix (3 to 20 atoms, FP64 and mixed precision) against the CPU oracle: the densities are
+    recomputed on the host from the published recurrence, the oracle contracts its own integrals with each of them
+    (Eq. (12), same screening rule), and every iteration's E2 and the last iteration's J, K, G must match: FP64
+    requests within 1e-10 of each matrix's largest element and 1e-10 relative in E2, mixed requests within
+    1e-6 Eh in every E2 (the benchmark's energy criterion) and 1e-6 of each matrix's largest element."""
+    import oracle
+    spec = [(20, uqc.FP64), (4, uqc.MIXED), (3, uqc.FP64), (10, uqc.MIXED), (9, uqc.FP64)]
+    reqs = []
+    for i, (n, prec) in enumerate(spec):
+        sh = wl.lattice_shells(n, 800 + i)
+        D0 = wl.random_density(np.random.default_rng(900 + i), sh.nbf, 3, float(n))
+        reqs.append(dict(shells=sh, D0=D0, n_iter=3, ncol=2, eps=0.05, seed=8100 + i,
+                         opts=uqc.default_opts(tau=1e-12, precision=prec)))
+    out = _run(ctx, reqs, slots=3, stagger_s=0.002)
+    for r, (n, prec), m in zip(reqs, spec, out):
+        Ds = density_sequence(r["D0"], r["n_iter"], r["ncol"], r["eps"], r["seed"])
+        O = oracle.Basis(r["shells"])
+        J, K, _ = O.jk_symmetric(Ds, tau=1e-12)
+        tol = 1e-10 if prec == uqc.FP64 else 1e-6
+        for t, D in enumerate(Ds):
+            G, E2 = oracle.fock_parts(J[t], K[t], D)
+            bound = 1e-10 * abs(E2) if prec == uqc.FP64 else 1e-6
+            assert abs(m["E2"][t] - E2) <= bound, (n, t, m["E2"][t], E2)
+        Gr, _ = oracle.fock_parts(J[-1], K[-1], Ds[-1])
+        for name, ref in (("J", J[-1]), ("K", K[-1]), ("G", Gr)):
+            assert np.max(np.abs(m[name] - ref)) <= tol * np.max(np.abs(ref)), (n, name)
