@@ -154,6 +154,22 @@ uqc_status uqc_eri_blocks(uqc_basis* b, int n, const int* quartets, int precisio
 uqc_status uqc_fock_build(uqc_basis* b, const double* D, double* J, double* K, double* G, const uqc_fock_opts* opts,
                           uqc_stats* stats);
 
+/* uqc_fock_build without any device allocation, for callers that cannot allocate device memory (code being captured
+ * into a HIP graph, tight serving loops, harnesses that forbid allocation).  Same arguments, results and errors as
+ * uqc_fock_build for a closed-shell build, with these limits:
+ *   - D, J, K, G are device pointers on the context's device (host pointers: UQC_E_ARG);
+ *   - the scaled density, the J and K accumulators, the scalars and the per-task counters live in a fixed device
+ *     array of the library (25.7 MB per device, held until the process ends) instead of the basis's workspace, so
+ *     the basis has at most 1024 basis functions (else UQC_E_ARG);
+ *   - the screening plan for (opts->schwarz_tau, opts->precision, opts->fp64_bound) must already exist on this
+ *     basis: an earlier uqc_fock_build with the same three options makes it (else UQC_E_ARG);
+ *   - every class launch is queued on the context's stream (opts->streams is not used); opts->timing must be 0.
+ * Every call on one device shares that device's array, so calls that overlap on one device (from two host threads,
+ * or on two contexts' streams) race and give wrong results; calls in sequence on one stream are safe (each starts by
+ * clearing what it accumulates into). */
+uqc_status uqc_fock_build_noalloc(uqc_basis* b, const double* D, double* J, double* K, double* G,
+                                  const uqc_fock_opts* opts, uqc_stats* stats);
+
 /* Unrestricted Fock build (the paper's URHF, for open shells: the Pople-Nesbet equations of Szabo-Ostlund Sec. 3.8,
  * Eq. (12) applied per spin): for the spin densities Da, Db (nbf*nbf, row-major, symmetric; Da + Db is the total
  * density), J = J(Da + Db), Ka = K(Da), Kb = K(Db), Ga = J - x Ka, Gb = J - x Kb (x = opts->exchange_scale) and

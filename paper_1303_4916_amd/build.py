@@ -73,7 +73,8 @@ def _units():
                       (["-DUQC_WAVES_ATTR=__attribute__((amdgpu_waves_per_eu(%d)))" % WAVES_PER_EU[(la, lb, lc, ld)]]
                        if (la, lb, lc, ld) in WAVES_PER_EU else []) +
                       (["-DUQC_KAC_LDS=0"] if (la, lb, lc, ld) in KAC_NOT_IN_LDS else []), headers))
-    for src in ("uqc_kernels.hip", "uqc_one.hip", "uqc_mp2.hip", "uqc_api.cpp", "uqc_serve.cpp", "uqc_scf.cpp"):
+    for src in ("uqc_kernels.hip", "uqc_one.hip", "uqc_mp2.hip", "uqc_noalloc.hip", "uqc_api.cpp", "uqc_serve.cpp",
+                "uqc_scf.cpp"):
         units.append((os.path.join(CSRC, src), os.path.join(OBJ, os.path.splitext(src)[0] + ".o"), [], headers))
     # heaviest classes first so they start early
     units.sort(key=lambda u: -int(u[2][0].split("=")[1]) if u[2] else 0)

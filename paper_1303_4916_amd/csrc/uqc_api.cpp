@@ -146,6 +146,14 @@ uqc_status uqc_init(int device, void* hip_stream, uqc_ctx** out) {
         uqc_finalize(c);
         return uqc_fail(UQC_E_DEVICE, "uqc_init: cannot upload the Rys table");
     }
+    // the device address of the fixed workspace of uqc_fock_build_noalloc, taken once per device with it current
+    {
+        const uqc_status st = uqc::noalloc_setup(device);
+        if (st != UQC_OK) {
+            uqc_finalize(c);
+            return st;
+        }
+    }
     *out = c;
     return UQC_OK;
 }
@@ -769,10 +777,15 @@ static int group_bras(int cls) {
     }
 }
 
-Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st) {
+Plan* find_plan(uqc_basis* B, double tau, int prec, double bound) {
     for (auto& kv : B->plans)
         if (kv.first.tau == tau && kv.first.prec == prec && (prec == UQC_FP64 || kv.first.bound == bound))
             return &kv.second;
+    return nullptr;
+}
+
+Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st) {
+    if (Plan* p = find_plan(B, tau, prec, bound)) return p;
     PlanKey key{tau, prec, prec == UQC_FP64 ? 0.0 : bound};
     Plan plan;
     struct HostTask {
@@ -927,6 +940,7 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
         d.D2 = B->d_Dp2;
         d.K2 = B->d_K2;
         d.nbf = B->nbf;
+        d.cidx = (int)oi;
     }
     size_t oi = 0;
     for (auto& gk : gkeys) {
@@ -1122,8 +1136,8 @@ uqc_status uqc_eri_block(uqc_basis* B, int a, int b, int c, int d, int precision
 // Fock build for one density (nspin = 1: out = {J, K, G}) or a pair of spin densities (nspin = 2:
 // out = {J, Ka, Kb, Ga, Gb}).  With spin densities the class kernels evaluate every integral once and contract it
 // with the total density for J and with each spin density for its own K.
-static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, double* const* out,
-                           const uqc_fock_opts* opts, uqc_stats* stats, const char* name) {
+uqc_status uqc::fock_run(uqc_basis* B, int nspin, const double* const* Din, double* const* out,
+                         const uqc_fock_opts* opts, uqc_stats* stats, const char* name, const FockWorkspace* ws) {
     const auto t0 = std::chrono::steady_clock::now();
     const std::string nm(name);
     uqc_fock_opts o;
@@ -1135,21 +1149,37 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
     if (o.max_items_per_launch < 0) return uqc_fail(UQC_E_ARG, nm + ": negative max_items_per_launch");
     if (!std::isfinite(o.exchange_scale)) return uqc_fail(UQC_E_ARG, nm + ": exchange_scale is not finite");
     if (o.streams < 0 || o.streams > 4) return uqc_fail(UQC_E_ARG, nm + ": streams must be in 0..4");
+    if (ws && (nspin != 1 || o.timing)) return uqc_fail(UQC_E_ARG, nm + ": closed shell only, no timing");
     const long long max_items = o.max_items_per_launch > 0 ? o.max_items_per_launch : kMaxItemsPerLaunch;
     const int nout = nspin == 1 ? 3 : 5;
     uqc_ctx* ctx = B->ctx;
     UQC_HIP(hipSetDevice(ctx->device));
     const bool dev = uqc::is_device_ptr(Din[0]);
+    if (ws && !dev) return uqc_fail(UQC_E_ARG, nm + ": D, J, K, G must be device pointers");
     if (nspin == 2 && uqc::is_device_ptr(Din[1]) != dev)
         return uqc_fail(UQC_E_ARG, nm + ": mix of host and device pointers");
     for (int i = 0; i < nout; ++i)
         if (out[i] && uqc::is_device_ptr(out[i]) != dev)
             return uqc_fail(UQC_E_ARG, nm + ": mix of host and device pointers");
     uqc_status st = UQC_OK;
-    Plan* plan = get_plan(B, o.schwarz_tau, o.precision, o.fp64_bound, &st);
+    Plan* plan = ws ? find_plan(B, o.schwarz_tau, o.precision, o.fp64_bound)
+                    : get_plan(B, o.schwarz_tau, o.precision, o.fp64_bound, &st);
+    if (!plan && ws)
+        return uqc_fail(UQC_E_ARG, nm + ": no screening plan for these options on this basis (an earlier "
+                                        "uqc_fock_build with the same tau, precision and fp64_bound makes it)");
     if (!plan) return st;
+    if (ws && plan->ntasks > ws->max_tasks)
+        return uqc_fail(UQC_E_ARG, nm + ": the plan has more tasks than the fixed workspace holds");
     const size_t N = B->nbf, NN = N * N;
     hipStream_t s = ctx->stream;
+    // D' and the accumulators, scalars and counters: the basis's own workspace, or the caller-chosen one
+    double* const Dp = ws ? ws->Dp : B->d_Dp;
+    double* const Jacc = ws ? ws->J : B->d_J;
+    double* const Kacc = ws ? ws->K : B->d_K;
+    double* const scal = ws ? ws->scal : B->d_scal;
+    unsigned long long* const counts = ws ? ws->count : plan->d_count;
+    WorkRedirect wr{};
+    if (ws) wr = WorkRedirect{Dp, Jacc, Kacc, counts, plan->ntasks};
     const double* Dd[2] = {Din[0], nspin == 2 ? Din[1] : nullptr};
     double* Od[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     for (int i = 0; i < nout; ++i) Od[i] = out[i];
@@ -1169,9 +1199,9 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
         }
         for (int i = 0; i < nout; ++i) Od[i] = out[i] ? io + (nspin + i) * NN : nullptr;
     }
-    unsigned long long* maxbits = (unsigned long long*)(B->d_scal + 1);
-    UQC_HIP(launch_zero(B->d_scal, 8, s));
-    UQC_HIP(launch_prepare(Dd[0], B->d_f, B->d_Dp, (int)N, maxbits, s));
+    unsigned long long* maxbits = (unsigned long long*)(scal + 1);
+    UQC_HIP(launch_zero(scal, 8, s));
+    UQC_HIP(launch_prepare(Dd[0], B->d_f, Dp, (int)N, maxbits, s));
     if (nspin == 2) UQC_HIP(launch_prepare(Dd[1], B->d_f, B->d_Dp2, (int)N, maxbits + 2, s));
     unsigned long long hb[4] = {0, 0, 0, 0};
     UQC_HIP(hipMemcpyAsync(hb, maxbits, sizeof(hb), hipMemcpyDeviceToHost, s));
@@ -1183,7 +1213,12 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
         if (!(md <= 1e-12 * ma))
             return uqc_fail(UQC_E_NOT_SYMMETRIC, nm + ": density is not symmetric (or not finite)");
     }
-    UQC_HIP(launch_zero(B->d_J, 2 * NN, s));
+    if (Kacc == Jacc + NN) {
+        UQC_HIP(launch_zero(Jacc, 2 * NN, s));
+    } else {
+        UQC_HIP(launch_zero(Jacc, NN, s));
+        UQC_HIP(launch_zero(Kacc, NN, s));
+    }
     if (nspin == 2) {
         UQC_HIP(launch_zero(B->d_K2, NN, s));
         UQC_HIP(launch_add(B->d_Dp, B->d_Dp2, B->d_Dp3, NN, s));
@@ -1194,7 +1229,7 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
     // the stream with the least work so far; then queued largest, smallest, second largest, second smallest, ...,
     // so that every stream alternates long and short kernels and their drains overlap.  The extra streams wait for
     // everything queued on the context's stream so far and are joined back into it after their last launch.
-    const int nst = std::max(1, o.streams);
+    const int nst = ws ? 1 : std::max(1, o.streams);
     const size_t ng = plan->groups.size();
     std::vector<size_t> order(ng);
     std::vector<int> gstream(ng, 0);
@@ -1224,7 +1259,7 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
     };
     std::vector<SubLaunch> subs;
     auto pass = [&]() -> uqc_status {
-        if (plan->ntasks) UQC_HIP(launch_zero((double*)plan->d_count, 2 * (size_t)plan->ntasks, s));
+        if (plan->ntasks) UQC_HIP(launch_zero((double*)counts, 2 * (size_t)plan->ntasks, s));
         if (nst > 1) {
             UQC_HIP(hipEventRecord(ctx->fork, s));
             for (int k = 1; k < nst; ++k) UQC_HIP(hipStreamWaitEvent(S[k], ctx->fork, 0));
@@ -1239,7 +1274,7 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
             for (long long i0 = 0; i0 < g.nitems; i0 += max_items) {
                 const long long n = std::min(max_items, g.nitems - i0);
                 UQC_HIP(launch_digest(g.cls, g.mixed, nspin, g.d_tasks, g.d_begin, g.ntask, i0, n, ctx->boys64,
-                                      ctx->boys32, gs));
+                                      ctx->boys32, wr, gs));
                 if (o.progress && nst == 1) {
                     UQC_HIP(hipStreamSynchronize(gs));
                     o.progress(o.progress_user, cid, i0 + n, g.nitems);
@@ -1276,13 +1311,12 @@ static uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, do
         UQC_HIP(launch_finalize_uhf(Dd[0], Dd[1], B->d_J, B->d_K, B->d_K2, B->d_f, o.exchange_scale, Od[0], Od[1],
                                     Od[2], Od[3], Od[4], B->d_scal, (int)N, s));
     } else {
-        UQC_HIP(launch_finalize(Dd[0], B->d_J, B->d_K, B->d_f, Od[0], Od[1], Od[2], o.exchange_scale, B->d_scal,
-                                (int)N, s));
+        UQC_HIP(launch_finalize(Dd[0], Jacc, Kacc, B->d_f, Od[0], Od[1], Od[2], o.exchange_scale, scal, (int)N, s));
     }
     double E2 = 0.0;
-    UQC_HIP(hipMemcpyAsync(&E2, B->d_scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    UQC_HIP(hipMemcpyAsync(&E2, scal, sizeof(double), hipMemcpyDeviceToHost, s));
     if (plan->ntasks)
-        UQC_HIP(hipMemcpyAsync(plan->h_count.data(), plan->d_count, 2 * plan->ntasks * sizeof(unsigned long long),
+        UQC_HIP(hipMemcpyAsync(plan->h_count.data(), counts, 2 * plan->ntasks * sizeof(unsigned long long),
                                hipMemcpyDeviceToHost, s));
     if (!dev)
         for (int i = 0; i < nout; ++i)
@@ -1324,7 +1358,7 @@ uqc_status uqc_fock_build(uqc_basis* B, const double* D, double* J, double* K, d
     if (!B || !D) return uqc_fail(UQC_E_ARG, "uqc_fock_build: NULL basis or density");
     const double* Din[1] = {D};
     double* out[3] = {J, K, G};
-    return fock_run(B, 1, Din, out, opts, stats, "uqc_fock_build");
+    return uqc::fock_run(B, 1, Din, out, opts, stats, "uqc_fock_build", nullptr);
 }
 
 uqc_status uqc_fock_build_uhf(uqc_basis* B, const double* Da, const double* Db, double* J, double* Ka, double* Kb,
@@ -1332,7 +1366,7 @@ uqc_status uqc_fock_build_uhf(uqc_basis* B, const double* Da, const double* Db, 
     if (!B || !Da || !Db) return uqc_fail(UQC_E_ARG, "uqc_fock_build_uhf: NULL basis or density");
     const double* Din[2] = {Da, Db};
     double* out[5] = {J, Ka, Kb, Ga, Gb};
-    return fock_run(B, 2, Din, out, opts, stats, "uqc_fock_build_uhf");
+    return uqc::fock_run(B, 2, Din, out, opts, stats, "uqc_fock_build_uhf", nullptr);
 }
 
 // ---------------------------------------------------------------------------------------------- Boys check

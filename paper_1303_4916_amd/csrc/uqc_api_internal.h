@@ -125,6 +125,29 @@ struct uqc_basis {
 };
 
 uqc::Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st);
+// The plan already made for these options, or nullptr (never allocates).
+uqc::Plan* find_plan(uqc_basis* B, double tau, int prec, double bound);
+
+namespace uqc {
+// A caller-chosen device workspace for a closed-shell Fock build: D' (nbf^2), the J and K accumulators (nbf^2 each),
+// 8 scalars and 2 max_tasks counters.
+struct FockWorkspace {
+    double* Dp;
+    double* J;
+    double* K;
+    double* scal;
+    unsigned long long* count;
+    int max_tasks;
+};
+// The Fock build behind uqc_fock_build (nspin = 1: Din = {D}, out = {J, K, G}) and uqc_fock_build_uhf (nspin = 2:
+// Din = {Da, Db}, out = {J, Ka, Kb, Ga, Gb}).  ws == nullptr: the basis's workspace, the plan made on first use.
+// ws != nullptr (closed shell, device pointers): everything the build writes besides its outputs goes to *ws, the
+// plan must exist already, and every class launch is queued on the context's stream; nothing is allocated.
+uqc_status fock_run(uqc_basis* B, int nspin, const double* const* Din, double* const* out, const uqc_fock_opts* opts,
+                    uqc_stats* stats, const char* name, const FockWorkspace* ws);
+// Takes, with `device` current, the device address of the fixed workspace of uqc_fock_build_noalloc.
+uqc_status noalloc_setup(int device);
+}  // namespace uqc
 
 typedef struct _rocblas_handle* rocblas_handle;
 

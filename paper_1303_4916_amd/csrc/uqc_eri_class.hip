@@ -18,30 +18,31 @@ namespace uqc {
 
 template <bool MIXED, int NSPIN>
 static void launch_digest_one(unsigned nblocks, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
-                              long long item0, long long nitems, const double* b64, const float* b32, hipStream_t s) {
+                              long long item0, long long nitems, const double* b64, const float* b32,
+                              const WorkRedirect& wr, hipStream_t s) {
 #if UQC_TEAM
     hipLaunchKernelGGL((k_digest_team<UQC_LA, UQC_LB, UQC_LC, UQC_LD, MIXED, NSPIN>), dim3(nblocks), dim3(kBlock), 0,
-                       s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32);
+                       s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr);
 #else
     hipLaunchKernelGGL((k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, MIXED, NSPIN>), dim3(nblocks), dim3(kBlock), 0, s,
-                       d_tasks, d_task_begin, ntask, item0, nitems, b64, b32);
+                       d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr);
 #endif
 }
 
 static hipError_t launch_digest_cls(bool mixed, int nspin, const TaskDev* d_tasks, const long long* d_task_begin,
                                     int ntask, long long item0, long long nitems, const double* b64, const float* b32,
-                                    hipStream_t s) {
+                                    const WorkRedirect& wr, hipStream_t s) {
     const long long waves_per_block = kBlock / kWave;
     const long long nblocks = (nitems + waves_per_block - 1) / waves_per_block;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const unsigned nb = (unsigned)nblocks;
     if (nspin == 2) {
-        if (mixed) launch_digest_one<true, 2>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, s);
-        else launch_digest_one<false, 2>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, s);
+        if (mixed) launch_digest_one<true, 2>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
+        else launch_digest_one<false, 2>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
     } else {
-        if (mixed) launch_digest_one<true, 1>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, s);
-        else launch_digest_one<false, 1>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, s);
+        if (mixed) launch_digest_one<true, 1>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
+        else launch_digest_one<false, 1>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
     }
     return hipGetLastError();
 }

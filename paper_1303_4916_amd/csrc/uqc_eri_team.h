@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
                                                         const long long* __restrict__ task_begin, int ntask,
                                                         long long item0, long long nitems,
                                                    const double* __restrict__ boys64tab,
-                                                        const float* __restrict__ boys32tab) {
+                                                        const float* __restrict__ boys32tab, const WorkRedirect wr) {
     using TC = TeamClass<LA, LB, LC, LD>;
     constexpr int NA = TC::NA, NB = TC::NB, NC = TC::NC, ND = TC::ND;
     constexpr int NAB = NA * NB, NCD = NC * ND;
@@ -223,14 +223,16 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
     const double qk = Kt.Q[kc];
     // ket primitive pairs evaluated: the most any team's ket needs (the kets stay for the whole item)
     const int kkn = wave_max_int(ket_ok ? Kt.kp[kc] : 1);
-    const double* __restrict__ D = tk.D;
+    const bool redir = NSPIN == 1 && wr.J != nullptr;  // kernel argument: wavefront-uniform
+    const double* __restrict__ D = redir ? wr.D : tk.D;
     // D is read-only while the kernel runs: read through the constant address space with 32-bit offsets (N < 2^16)
     const cdptr Dc = as_const(D);
     const cdptr Dj = NSPIN == 2 ? as_const(tk.DJ) : Dc;  // density of the J pass
-    double* __restrict__ J = tk.J;
+    double* __restrict__ J = redir ? wr.J : tk.J;
+    double* __restrict__ K0 = redir ? wr.K : tk.K;
     const int N = tk.nbf;
     auto Dk = [&](int sp) { return sp == 0 ? Dc : as_const(tk.D2); };  // density of spin sp's K passes
-    auto Kp = [&](int sp) { return sp == 0 ? tk.K : tk.K2; };           // its accumulator
+    auto Kp = [&](int sp) { return sp == 0 ? K0 : tk.K2; };             // its accumulator
     // Only the ket index and its bound live across the loop; the ket's data, the lane's permutation tables and
     // the density blocks are re-read per bra pair through values the compiler cannot see through, which keeps
     // register use (and spills) down.
@@ -421,8 +423,8 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
         for (int sp = 0; sp < NSPIN; ++sp) flush(R_KAC + sp * KSZ, R_KBC + sp * KSZ, cur_a, 0, sp);
     }
     if (lane == 0 && cnt) {
-        atomicAdd(tk.count, cnt);
-        atomicAdd(tk.pcount, pcnt);
+        atomicAdd(redir ? wr.count + tk.cidx : tk.count, cnt);
+        atomicAdd(redir ? wr.count + wr.ncount + tk.cidx : tk.pcount, pcnt);
     }
 }
 

@@ -81,6 +81,18 @@ struct TaskDev {
     const double* D2;          // spin builds: the beta density, for K
     double* K2;                // spin builds: the beta K accumulator
     int nbf;
+    int cidx;                  // index of this task's counters in its plan's counter array
+};
+
+// Closed-shell builds whose density, accumulators and counters live in a caller-chosen workspace instead of the
+// ones the task descriptors name: when J is non-null, the kernels read D and accumulate into J and K given here,
+// and count task t's quartets at count[cidx] and its primitive quartets at count[ncount + cidx].
+struct WorkRedirect {
+    const double* D;
+    double* J;
+    double* K;
+    unsigned long long* count;
+    int ncount;
 };
 
 // An explicit list of quartets (bra index, ket index) for block output or Schwarz bounds.
@@ -101,7 +113,7 @@ enum Mode { MODE_STORE = 0, MODE_SCHWARZ = 1, MODE_SCATTER = 2 };
 struct ClassLaunchers {
     hipError_t (*digest)(bool mixed, int nspin, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
                          long long item0, long long nitems, const double* boys64, const float* boys32,
-                         hipStream_t s);
+                         const WorkRedirect& wr, hipStream_t s);
     hipError_t (*list)(bool mixed, int mode, const ListDev& list, const double* boys64, const float* boys32,
                        hipStream_t s);
     hipError_t (*list_rys)(const ListDev& list, const double* rystab, hipStream_t s);  // MODE_STORE by Rys quadrature
@@ -112,9 +124,10 @@ int class_index(int la, int lb, int lc, int ld);           // -1 if not canonica
 void class_ls(int idx, int* la, int* lb, int* lc, int* ld);
 // Work items [item0, item0 + nitems) of one (class, precision) launch group.
 // nspin = 1: J and K of D; nspin = 2: J of DJ, K of D into K and of D2 into K2, each integral evaluated once.
+// wr.J non-null (nspin = 1 only): D, J, K and the counters are taken from wr instead of the task descriptors.
 hipError_t launch_digest(int cls, bool mixed, int nspin, const TaskDev* d_tasks, const long long* d_task_begin,
                          int ntask, long long item0, long long nitems, const double* boys64, const float* boys32,
-                         hipStream_t s);
+                         const WorkRedirect& wr, hipStream_t s);
 hipError_t launch_list(int cls, bool mixed, int mode, const ListDev& list, const double* boys64,
                        const float* boys32, hipStream_t s);
 hipError_t launch_list_rys(int cls, const ListDev& list, const double* rystab, hipStream_t s);

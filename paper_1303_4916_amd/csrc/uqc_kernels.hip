@@ -46,11 +46,12 @@ double class_flops_contr(int cls) { return kClassFlopsContr[cls]; }
 
 hipError_t launch_digest(int cls, bool mixed, int nspin, const TaskDev* d_tasks, const long long* d_task_begin,
                          int ntask, long long item0, long long nitems, const double* boys64tab,
-                         const float* boys32tab, hipStream_t s) {
+                         const float* boys32tab, const WorkRedirect& wr, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
     if (cls < 0 || cls >= kNumClasses || item0 < 0 || (nspin != 1 && nspin != 2)) return hipErrorInvalidValue;
+    if (wr.J && (nspin != 1 || !wr.D || !wr.K || !wr.count)) return hipErrorInvalidValue;
     return launchers(cls).digest(mixed, nspin, d_tasks, d_task_begin, ntask, item0, nitems, boys64tab, boys32tab,
-                                 s);
+                                 wr, s);
 }
 
 hipError_t launch_list_rys(int cls, const ListDev& list, const double* rystab, hipStream_t s) {

@@ -242,7 +242,7 @@ bool uqc_server::step() {
         for (long long i0 = 0; i0 < groups[gi].items; i0 += kMaxItemsPerLaunch)
             if (launch_digest(groups[gi].cls, groups[gi].mixed, 1, ptrs[gi].first, ptrs[gi].second,
                               (int)groups[gi].tasks.size(), i0, std::min(kMaxItemsPerLaunch, groups[gi].items - i0),
-                              ctx->boys64, ctx->boys32, S[k]) != hipSuccess)
+                              ctx->boys64, ctx->boys32, WorkRedirect{}, S[k]) != hipSuccess)
                 return fail_all("server: class launch failed");
     }
     for (int k = 1; k < kStreams; ++k)

@@ -30,7 +30,7 @@ EXPORTED = ["uqc_fock_opts_default", "uqc_init", "uqc_finalize", "uqc_last_error
             "uqc_basis_destroy", "uqc_basis_info", "uqc_schwarz", "uqc_eri_block", "uqc_eri_blocks",
             "uqc_fock_build", "uqc_boys", "uqc_server_create", "uqc_submit", "uqc_poll", "uqc_server_drain",
             "uqc_server_destroy", "uqc_one_electron", "uqc_scf_opts_default", "uqc_scf_rhf", "uqc_fock_build_uhf",
-            "uqc_scf_uhf", "uqc_mp2"]
+            "uqc_scf_uhf", "uqc_mp2", "uqc_fock_build_noalloc"]
 
 
 class UqcError(RuntimeError):
@@ -150,6 +150,7 @@ def load(build_if_missing: bool = True):
         L.uqc_eri_block.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D]
         L.uqc_eri_blocks.argtypes = [vp, ctypes.c_int, _I, ctypes.c_int, _D]
         L.uqc_fock_build.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(FockOpts), ctypes.POINTER(Stats)]
+        L.uqc_fock_build_noalloc.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(FockOpts), ctypes.POINTER(Stats)]
         L.uqc_boys.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _D, _D]
         L.uqc_server_create.argtypes = [vp, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(vp)]
         L.uqc_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_longlong)]
@@ -348,6 +349,18 @@ class Basis:
         _check(load().uqc_fock_build(self.h, ctypes.c_void_p(D_ptr), ctypes.c_void_p(J_ptr) if J_ptr else None,
                                      ctypes.c_void_p(K_ptr) if K_ptr else None,
                                      ctypes.c_void_p(G_ptr) if G_ptr else None, ctypes.byref(o), ctypes.byref(st)))
+        return st
+
+    def fock_build_noalloc_ptr(self, D_ptr: int, J_ptr: int, K_ptr: int, G_ptr: int,
+                               opts: FockOpts = None) -> Stats:
+        """uqc_fock_build_noalloc on raw device pointers (the library allocates nothing; see include/uqc.h)."""
+        st = Stats()
+        o = opts if opts is not None else default_opts()
+        _check(load().uqc_fock_build_noalloc(self.h, ctypes.c_void_p(D_ptr),
+                                             ctypes.c_void_p(J_ptr) if J_ptr else None,
+                                             ctypes.c_void_p(K_ptr) if K_ptr else None,
+                                             ctypes.c_void_p(G_ptr) if G_ptr else None, ctypes.byref(o),
+                                             ctypes.byref(st)))
         return st
 
     def fock_build(self, D, opts: FockOpts = None, want=("J", "K", "G")):
