@@ -2,17 +2,19 @@
 """Benchmark: FP64 Fock builds G(D) = J(D) - K(D)/2 on one MI355X.
 
 Workload (one step = one Fock build of the whole path: density preparation, every screened shell-quartet class
-kernel with its J/K digest, finalisation to J, K, G and E2) on the medium synthetic system: 60 atoms on a jittered
-2.5 bohr lattice, 2s1p1d Cartesian shells per atom (K = 3/3/3/1), N = 660 basis functions, Schwarz threshold 1e-12,
-ten fresh PSD densities (trace 60) cycled over the steps.  The basis plan (normalisation, pair data, Schwarz bounds,
-work lists) is built once before the timed region and reported separately (plan_ms).  Densities and outputs stay
-in device memory (torch tensors); the call is synchronous.
+kernel with its J/K digest, finalisation to J, K, G and E2) on the 150-atom synthetic system: 150 atoms on a jittered
+2.5 bohr lattice, 2s1p1d Cartesian shells per atom, the first (tighter) s shell contracted from 6 primitives and the
+others K = 3/3/1 (s, p, d), N = 1650 basis functions, Schwarz threshold 1e-12, one PSD density of trace 150.  The
+basis plan (normalisation, pair data, Schwarz bounds, work lists) is built once before the timed region and reported
+separately (plan_ms).  Densities and outputs stay in device memory (torch tensors); the call is synchronous.
 
 The timed builds use the library's default launch configuration (class kernels spread over three HIP streams).
 Printed: one JSON line with the metric, the per-build latency percentiles, the roofline line of the dominant
 class kernel (algorithmic FLOPs from the frozen per-class operation counts / its average launch time measured with
-HIP events on the stream it runs on, in a second pass of the same builds with every class launch on one stream)
-and the oracle timed on a bounded sample on the host cores.
+HIP events on the stream it runs on, in a second pass of builds with every class launch on one stream), the
+mixed-precision leg against FP64 (energy, Fock-matrix and sampled ERI errors, speed), the 60-atom workload of the
+medium configuration (N = 660, ten densities) as extra keys, and the oracle timed on a bounded sample on the host
+cores.
 """
 from __future__ import annotations
 
@@ -29,7 +31,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "shell quartets/s and Fock builds/s at ≤1e-6 Eh vs FP64; p50/p99 build latency"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_medium60_fp64.json")
+TRAFFIC_FILES = {"lattice150": os.path.join(ROOT, "profiles", "traffic_lattice150_fp64.json"),
+                 "medium": os.path.join(ROOT, "profiles", "traffic_medium60_fp64.json")}
+TRAFFIC_FILE = TRAFFIC_FILES["lattice150"]
 
 
 # Sources of the Fock-build kernels (the class-kernel unit and the headers it includes, the prepare/finalize unit,
@@ -108,10 +112,10 @@ def summarize_stats(stats_csv: str, out: str, cmd: str, title: str):
         f.write("\n".join(lines) + "\n")
 
 
-def traffic_for(kernel_key: str):
+def traffic_for(kernel_key: str, path: str = None):
     """HBM bytes per launch of a kernel from the committed counter summary, or None if the kernels changed since."""
     try:
-        doc = json.load(open(TRAFFIC_FILE))
+        doc = json.load(open(path or TRAFFIC_FILE))
     except Exception:
         return None
     if doc.get("kernel_sources_sha256") != kernel_sources_sha256():
@@ -199,14 +203,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--workload", default="medium",
-                    choices=["medium", "mixed150", "large400", "large400kd1", "serve", "scf", "uhf", "mp2", "rys", "oracle-c1", "copy"],
-                    help="medium (default, the benchmark line); mixed150 / large400: mixed vs FP64 accuracy and "
-                         "speed; serve: Poisson request stream through the continuous-batching server")
+    ap.add_argument("--workload", default="lattice150",
+                    choices=["lattice150", "medium", "mixed150", "large400", "large400kd1", "serve", "scf", "uhf",
+                             "mp2", "rys", "oracle-c1", "copy"],
+                    help="lattice150 (default, the benchmark line: 150 atoms, N=1650); medium: the same line on the "
+                         "60-atom workload; mixed150 / large400: one-build mixed vs FP64 accuracy and speed; serve: "
+                         "Poisson request stream through the continuous-batching server")
+    ap.add_argument("--no-medium", action="store_true", help="leave out the 60-atom extra keys")
+    ap.add_argument("--traffic-out", default=None, help="--summarize-pmc: output file (default: lattice150's)")
     ap.add_argument("--nreq", type=int, default=32, help="serve: requests taken from the 512-request stream")
     ap.add_argument("--rate", type=float, default=200.0,
                     help="serve: mean arrival rate in requests/s (the stream's 200, or a sustainable rate)")
-    ap.add_argument("--oracle-quartets", type=int, default=4000, help="mixed150/large400: oracle sample size")
+    ap.add_argument("--oracle-quartets", type=int, default=2000,
+                    help="ERI sample size of the accuracy legs (oracle against both precisions)")
     ap.add_argument("--streams", type=int, default=None,
                     help="HIP streams the class launches of one Fock build are spread over (default: the library's)")
     ap.add_argument("--fp64-only", action="store_true",
@@ -221,7 +230,7 @@ def main():
         summarize_stats(*a.summarize_stats)
         return
     if a.summarize_pmc:
-        summarize_pmc(*a.summarize_pmc[:4], TRAFFIC_FILE, a.summarize_pmc[4])
+        summarize_pmc(*a.summarize_pmc[:4], a.traffic_out or TRAFFIC_FILE, a.summarize_pmc[4])
         return
     if a.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the Fock build would shard by "
@@ -245,119 +254,199 @@ def main():
     if a.workload in ("mixed150", "large400", "large400kd1"):
         return bench_mixed(a)
 
+    out = bench_fock(a)
+    print(json.dumps(out), flush=True)
+
+
+WORKLOAD_NAMES = {
+    "lattice150": "lattice150_2s1p1d: 150 atoms, N=1650, first s K=6, K=3/3/1 otherwise, tau=1e-12, FP64, 1 density",
+    "medium": "lattice60_2s1p1d: 60 atoms, N=660, K=3/3/3/1, tau=1e-12, FP64, 10 densities",
+}
+
+
+def fock_leg(B, Ds, tau, steps, warmup, streams, one_stream_builds, traffic_path):
+    """Timed FP64 builds (the library's default launch configuration), then a pass of `one_stream_builds` builds
+    with every class launch on one stream and HIP-event timing per class (roofline of the dominant class kernel)."""
     import torch
     from paper_1303_4916_amd import uqc
-    from paper_1303_4916_amd import workloads as wl
-
-    w = wl.medium(ndens=10)
-    ctx = uqc.Context(0)
-    t = time.perf_counter()
-    B = uqc.Basis(ctx, w.shells)
-    plan_ms = (time.perf_counter() - t) * 1e3
     N = B.nbf
-    Ds = [torch.from_numpy(D).cuda() for D in w.densities]
     J = torch.empty((N, N), dtype=torch.float64, device="cuda")
     K = torch.empty_like(J)
     G = torch.empty_like(J)
     torch.cuda.synchronize()
-    # The timed builds run in the library's launch configuration (classes spread over several streams); per-class
-    # kernel durations for the roofline come from a second pass of the same builds with every class launch on one
-    # stream, where each kernel has the chip to itself.
-    opts = uqc.default_opts(tau=w.tau, streams=a.streams)
-    sopts = uqc.default_opts(tau=w.tau, timing=True, streams=1)
+    opts = uqc.default_opts(tau=tau, streams=streams)
+    sopts = uqc.default_opts(tau=tau, timing=True, streams=1)
+    build = lambda i, o: B.fock_build_ptr(Ds[i % len(Ds)].data_ptr(), J.data_ptr(), K.data_ptr(), G.data_ptr(), o)
     t = time.perf_counter()
-    st0 = B.fock_build_ptr(Ds[0].data_ptr(), J.data_ptr(), K.data_ptr(), G.data_ptr(), opts)  # plan for this tau
+    st0 = build(0, opts)  # makes the plan for this tau
     first_ms = (time.perf_counter() - t) * 1e3
-    for i in range(a.warmup):
-        B.fock_build_ptr(Ds[i % len(Ds)].data_ptr(), J.data_ptr(), K.data_ptr(), G.data_ptr(), opts)
+    for i in range(warmup):
+        build(i, opts)
     torch.cuda.synchronize()
-    lat = []
-    E2s = []
+    lat, E2s = [], []
     t0 = time.perf_counter()
-    for i in range(a.steps):
+    for i in range(steps):
         ts = time.perf_counter()
-        st = B.fock_build_ptr(Ds[i % len(Ds)].data_ptr(), J.data_ptr(), K.data_ptr(), G.data_ptr(), opts)
+        st = build(i, opts)
         lat.append((time.perf_counter() - ts) * 1e3)
         E2s.append(st.E2)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    cls_ms = {}
-    cls_flops = {}
-    cls_q = {}
+    G0 = None
+    if len(Ds) == 1:
+        G0 = G.cpu().numpy().copy()
+    cls_ms, cls_flops, cls_q = {}, {}, {}
+    n1 = max(1, min(steps, one_stream_builds))
     t1 = time.perf_counter()
-    for i in range(a.steps):
-        st = B.fock_build_ptr(Ds[i % len(Ds)].data_ptr(), J.data_ptr(), K.data_ptr(), G.data_ptr(), sopts)
+    for i in range(n1):
+        st = build(i, sopts)
         for c in range(st.nclass):
             cid = int(st.class_id[c])
             cls_ms[cid] = cls_ms.get(cid, 0.0) + float(st.class_ms[c])
             cls_flops[cid] = float(st.class_flops[c])
             cls_q[cid] = int(st.class_quartets[c])
     torch.cuda.synchronize()
-    serial_ms = (time.perf_counter() - t1) * 1e3 / a.steps
+    serial_ms = (time.perf_counter() - t1) * 1e3 / n1
     q = int(st0.quartets)
-    ms_per_step = elapsed * 1e3 / a.steps
     dom = max(cls_ms, key=lambda k: cls_ms[k])
-    dom_avg_ms = cls_ms[dom] / a.steps
+    dom_avg_ms = cls_ms[dom] / n1
     achieved = cls_flops[dom] / (dom_avg_ms * 1e-3) / 1e12
-    eri_ms = sum(cls_ms.values()) / a.steps
     total_flops = float(st0.flops)
+    res = {
+        "value": q * steps / elapsed,
+        "ms_per_step": elapsed * 1e3 / steps,
+        "fock_builds_per_s": steps / elapsed,
+        "p50_build_ms": float(np.percentile(lat, 50)),
+        "p99_build_ms": float(np.percentile(lat, 99)),
+        "first_build_ms": first_ms,
+        "quartets_per_build": q,
+        "quartets_screened_per_build": int(st0.quartets_screened),
+        "prim_quartets_per_build": int(st0.prim_quartets),
+        "prim_quartets_per_s": int(st0.prim_quartets) * steps / elapsed,
+        "cartesian_integrals_per_s": sum(cls_q[k] * cartesian_per_quartet(k) for k in cls_q) * steps / elapsed,
+        "algorithmic_flops_per_build": total_flops,
+        "algorithmic_tflops": total_flops * steps / elapsed / 1e12,
+        "one_stream_ms_per_build": serial_ms,
+        "one_stream_builds": n1,
+        "eri_kernel_ms_per_build_one_stream": sum(cls_ms.values()) / n1,
+        "E2_first": E2s[0],
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                     "traffic": traffic_for(dom_kernel_key(dom), traffic_path),
+                     "kernel": "k_digest " + class_name(dom), "kernel_avg_ms": dom_avg_ms,
+                     "kernel_flops_per_launch": cls_flops[dom],
+                     "timed_in": "the one-stream pass of the same builds (each kernel alone on the chip)"},
+        "classes": {class_name(k): {"ms": cls_ms[k] / n1, "quartets": cls_q[k],
+                                    "tflops": cls_flops[k] / (cls_ms[k] / n1 * 1e-3) / 1e12}
+                    for k in sorted(cls_ms, key=lambda k: -cls_ms[k])},
+    }
+    return res, E2s, G0, (J, K, G)
+
+
+def mixed_leg(B, Ds, tau, builds, streams, E2_fp64, G_fp64, bufs):
+    """Mixed-precision builds of the same densities: speed and error against the FP64 builds."""
+    import torch
+    from paper_1303_4916_amd import uqc
+    J, K, G = bufs
+    mo = uqc.default_opts(tau=tau, precision=uqc.MIXED, streams=streams)
+    B.fock_build_ptr(Ds[0].data_ptr(), J.data_ptr(), K.data_ptr(), G.data_ptr(), mo)  # plan for this routing
+    torch.cuda.synchronize()
+    nm = max(1, builds)
+    errs = []
+    t = time.perf_counter()
+    for i in range(nm):
+        stm = B.fock_build_ptr(Ds[i % len(Ds)].data_ptr(), J.data_ptr(), K.data_ptr(), G.data_ptr(), mo)
+        errs.append(abs(stm.E2 - E2_fp64[i % len(E2_fp64)]) if i < len(E2_fp64) else float("nan"))
+    torch.cuda.synchronize()
+    tm = (time.perf_counter() - t) / nm
+    out = {"fock_builds_per_s": 1.0 / tm, "ms_per_build": tm * 1e3, "fp64_bound": float(mo.fp64_bound),
+           "max_abs_E2_error_vs_fp64_Eh": float(np.nanmax(errs)),
+           "meets_1e-6_Eh": bool(np.nanmax(errs) <= 1e-6),
+           "fp64_quartets_per_build": int(stm.fp64_quartets), "quartets_per_build": int(stm.quartets),
+           "fp32_share_of_quartets": 1.0 - stm.fp64_quartets / max(1, stm.quartets)}
+    if G_fp64 is not None:
+        Gm = G.cpu().numpy()
+        out["G_frobenius_rel_error_vs_fp64"] = float(np.linalg.norm(Gm - G_fp64) / np.linalg.norm(G_fp64))
+        out["G_max_abs_error_vs_fp64"] = float(np.max(np.abs(Gm - G_fp64)))
+    return out, tm
+
+
+def eri_sample_errors(B, shells, n, seed):
+    """Largest ERI error of both precisions against the oracle on a uniform sample of canonical shell quartets."""
+    import oracle
+    from paper_1303_4916_amd import uqc
+    q = _sample_quartets(B.nshell, n, seed)
+    O = oracle.Basis(shells)
+    e64 = em = ref_max = 0.0
+    for (qa, qb, qc, qd), x64, xm in zip(q, B.eri_blocks(q, uqc.FP64), B.eri_blocks(q, uqc.MIXED)):
+        r = O.eri(int(qa), int(qb), int(qc), int(qd))
+        e64 = max(e64, float(np.max(np.abs(x64 - r))))
+        em = max(em, float(np.max(np.abs(xm - r))))
+        ref_max = max(ref_max, float(np.max(np.abs(r))))
+    return {"quartets": int(len(q)), "max_abs_eri_error_fp64": e64, "max_abs_eri_error_mixed": em,
+            "max_abs_eri": ref_max, "sample": "uniform over canonical shell quartets, seed %d" % seed}
+
+
+def bench_fock(a):
+    """The benchmark line: FP64 Fock builds of the chosen workload (default: 150 atoms), the mixed leg, the 60-atom
+    workload as extra keys, the oracle on a bounded sample of the same workload."""
+    import torch
+    from paper_1303_4916_amd import uqc
+    from paper_1303_4916_amd import workloads as wl
+
+    w = wl.mixed150(ndens=1) if a.workload == "lattice150" else wl.medium(ndens=10)
+    ctx = uqc.Context(0)
+    t = time.perf_counter()
+    B = uqc.Basis(ctx, w.shells)
+    plan_ms = (time.perf_counter() - t) * 1e3
+    Ds = [torch.from_numpy(D).cuda() for D in w.densities]
+    big = a.workload == "lattice150"
+    print("%s: N=%d, plan %.0f ms" % (w.name, B.nbf, plan_ms), file=sys.stderr, flush=True)
+    res, E2s, G0, bufs = fock_leg(B, Ds, w.tau, a.steps, a.warmup, a.streams, 3 if big else a.steps,
+                                  TRAFFIC_FILES[a.workload])
+    print("  FP64: %.1f ms per build, %.3e quartets/s" % (res["ms_per_step"], res["value"]), file=sys.stderr,
+          flush=True)
+    opts = uqc.default_opts(tau=w.tau, streams=a.streams)
     out = {
         "metric": METRIC,
-        "value": q * a.steps / elapsed,
+        "value": res.pop("value"),
         "unit": "shell quartets/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "lattice60_2s1p1d: 60 atoms, N=660, K=3/3/3/1, tau=1e-12, FP64, 10 densities",
-                   "natoms": 60, "nbf": N, "tau": w.tau, "precision": "fp64", "streams": int(opts.streams)},
-        "fock_builds_per_s": a.steps / elapsed,
-        "p50_build_ms": float(np.percentile(lat, 50)),
-        "p99_build_ms": float(np.percentile(lat, 99)),
+        "config": {"workload": WORKLOAD_NAMES[a.workload], "natoms": w.natoms, "nbf": B.nbf, "tau": w.tau,
+                   "precision": "fp64", "streams": int(opts.streams)},
         "plan_ms": plan_ms,
-        "first_build_ms": first_ms,
-        "quartets_per_build": q,
-        "quartets_screened_per_build": int(st0.quartets_screened),
-        "prim_quartets_per_build": int(st0.prim_quartets),
-        "prim_quartets_per_s": int(st0.prim_quartets) * a.steps / elapsed,
-        "cartesian_integrals_per_s": sum(cls_q[k] * cartesian_per_quartet(k) for k in cls_q) * a.steps / elapsed,
-        "algorithmic_flops_per_build": total_flops,
-        "algorithmic_tflops": total_flops * a.steps / elapsed / 1e12,
-        "one_stream_ms_per_build": serial_ms,
-        "eri_kernel_ms_per_build_one_stream": eri_ms,
-        "E2_first": E2s[0],
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic_for(dom_kernel_key(dom)),
-                     "kernel": "k_digest " + class_name(dom), "kernel_avg_ms": dom_avg_ms,
-                     "kernel_flops_per_launch": cls_flops[dom],
-                     "timed_in": "the one-stream pass of the same builds (each kernel alone on the chip)"},
-        "classes": {class_name(k): {"ms": cls_ms[k] / a.steps, "quartets": cls_q[k],
-                                    "tflops": cls_flops[k] / (cls_ms[k] / a.steps * 1e-3) / 1e12}
-                    for k in sorted(cls_ms, key=lambda k: -cls_ms[k])},
     }
+    out.update(res)
     if not a.no_mixed:
-        mo = uqc.default_opts(tau=w.tau, precision=uqc.MIXED, streams=a.streams)
-        B.fock_build_ptr(Ds[0].data_ptr(), J.data_ptr(), K.data_ptr(), G.data_ptr(), mo)
-        nm = max(2, a.steps // 2)
-        t = time.perf_counter()
-        errs = []
-        for i in range(nm):
-            stm = B.fock_build_ptr(Ds[i % len(Ds)].data_ptr(), J.data_ptr(), K.data_ptr(), G.data_ptr(), mo)
-            errs.append(abs(stm.E2 - E2s[i % len(E2s)]) if i < len(E2s) else float("nan"))
-        tm = (time.perf_counter() - t) / nm
-        out["mixed"] = {"fock_builds_per_s": 1.0 / tm, "speedup_vs_fp64": ms_per_step / (tm * 1e3),
-                        "max_abs_E2_error_vs_fp64_Eh": float(np.nanmax(errs)),
-                        "fp64_quartets_per_build": int(stm.fp64_quartets)}
+        m, tm = mixed_leg(B, Ds, w.tau, 3 if big else max(2, a.steps // 2), a.streams, E2s, G0, bufs)
+        m["speedup_vs_fp64"] = out["ms_per_step"] / (tm * 1e3)
+        out["mixed"] = m
+        print("  mixed: %.1f ms per build, |dE2| %.2e Eh" % (tm * 1e3, m["max_abs_E2_error_vs_fp64_Eh"]),
+              file=sys.stderr, flush=True)
+        out["mixed"]["oracle_sample"] = eri_sample_errors(B, w.shells, a.oracle_quartets, 31)
+    if big and not a.no_medium:
+        wm = wl.medium(ndens=10)
+        Bm = uqc.Basis(ctx, wm.shells)
+        Dm = [torch.from_numpy(D).cuda() for D in wm.densities]
+        rm, _, _, _ = fock_leg(Bm, Dm, wm.tau, 10, 2, a.streams, 10, TRAFFIC_FILES["medium"])
+        out["medium60"] = {"workload": WORKLOAD_NAMES["medium"], "quartets_per_s": rm["value"],
+                           "fock_builds_per_s": rm["fock_builds_per_s"], "ms_per_build": rm["ms_per_step"],
+                           "p50_build_ms": rm["p50_build_ms"], "p99_build_ms": rm["p99_build_ms"],
+                           "algorithmic_tflops": rm["algorithmic_tflops"], "roofline": rm["roofline"]}
+        Bm.close()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
-    print(json.dumps(out), flush=True)
     B.close()
     ctx.close()
+    return out
 
 
 def _sample_quartets(nshell: int, n: int, seed: int) -> np.ndarray:

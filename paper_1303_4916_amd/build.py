@@ -36,6 +36,10 @@ PAIR = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 WAVES_PER_EU = {(2, 0, 1, 1): 2, (2, 1, 2, 1): 2, (2, 2, 1, 1): 2, (1, 1, 0, 0): 4, (1, 0, 1, 0): 4, (2, 0, 1, 0): 3}
 # classes that do not keep their K_ac sums in LDS (the slots would cost them a wavefront per SIMD)
 KAC_NOT_IN_LDS = {(2, 1, 1, 0)}
+# classes whose FP64 Fock-build kernel reads the Boys rows from an LDS copy of its slice (measured per class: every
+# plain class gains or breaks even except (ds|ps) and (ds|pp), which run more wavefronts per SIMD and lose)
+BOYS_LDS = {(0, 0, 0, 0), (1, 0, 0, 0), (1, 0, 1, 0), (1, 1, 0, 0), (2, 0, 0, 0), (1, 1, 1, 0), (2, 1, 0, 0),
+            (2, 2, 0, 0), (1, 1, 1, 1), (2, 0, 2, 0), (2, 1, 1, 0), (2, 1, 1, 1), (2, 1, 2, 0), (2, 2, 1, 0)}
 
 
 def classes():
@@ -72,7 +76,8 @@ def _units():
                        "-DUQC_LD=%d" % ld, "-DUQC_TEAM=%d" % (1 if (la, lb, lc, ld) in team else 0)] +
                       (["-DUQC_WAVES_ATTR=__attribute__((amdgpu_waves_per_eu(%d)))" % WAVES_PER_EU[(la, lb, lc, ld)]]
                        if (la, lb, lc, ld) in WAVES_PER_EU else []) +
-                      (["-DUQC_KAC_LDS=0"] if (la, lb, lc, ld) in KAC_NOT_IN_LDS else []), headers))
+                      (["-DUQC_KAC_LDS=0"] if (la, lb, lc, ld) in KAC_NOT_IN_LDS else []) +
+                      (["-DUQC_BOYS_LDS=1"] if (la, lb, lc, ld) in BOYS_LDS else []), headers))
     for src in ("uqc_kernels.hip", "uqc_one.hip", "uqc_mp2.hip", "uqc_noalloc.hip", "uqc_api.cpp", "uqc_serve.cpp",
                 "uqc_scf.cpp"):
         units.append((os.path.join(CSRC, src), os.path.join(OBJ, os.path.splitext(src)[0] + ".o"), [], headers))
@@ -81,20 +86,32 @@ def _units():
     return units
 
 
-def _stale(obj, deps):
-    if not os.path.exists(obj):
+def _command(unit):
+    src, obj, defs, _ = unit
+    return [HIPCC] + FLAGS + defs + ["-c", src, "-o", obj]
+
+
+def _stale(unit):
+    """An object is rebuilt when it is missing, older than a source it depends on, or was compiled with another
+    command line (recorded next to it)."""
+    src, obj, _, deps = unit
+    if not os.path.exists(obj) or not os.path.exists(obj + ".cmd"):
+        return True
+    if open(obj + ".cmd").read() != " ".join(_command(unit)):
         return True
     t = os.path.getmtime(obj)
-    return any(os.path.getmtime(d) > t for d in deps if os.path.exists(d))
+    return any(os.path.getmtime(d) > t for d in [src] + deps if os.path.exists(d))
 
 
 def _compile(unit):
-    src, obj, defs, _ = unit
-    cmd = [HIPCC] + FLAGS + defs + ["-c", src, "-o", obj]
+    obj = unit[1]
+    cmd = _command(unit)
     t = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+    with open(obj + ".cmd", "w") as f:
+        f.write(" ".join(cmd))
     return os.path.basename(obj), time.time() - t
 
 
@@ -108,7 +125,7 @@ def build(incremental: bool = False, jobs: int = None, verbose: bool = True) -> 
            for f in rys_out):
         subprocess.check_call([sys.executable, os.path.join(CSRC, "gen_rys.py"), GEN])
     units = _units()
-    todo = [u for u in units if not incremental or _stale(u[1], [u[0]] + u[3])]
+    todo = [u for u in units if not incremental or _stale(u)]
     jobs = jobs or min(16, os.cpu_count() or 4)
     t0 = time.time()
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:

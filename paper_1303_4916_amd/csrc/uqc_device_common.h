@@ -67,7 +67,24 @@ __device__ __forceinline__ int boys64_row(double T, const double* __restrict__ t
 }
 
 // T_L of the comment above: the smallest integer T with Q(L+1/2, T) <= 2e-17
+constexpr int kBoysAsymTi[9] = {37, 41, 44, 47, 50, 53, 55, 58, 60};
 __device__ constexpr double kBoysAsymT[9] = {37, 41, 44, 47, 50, 53, 55, 58, 60};
+
+// Rows of the order-L slice an evaluation can use: below T_L the nearest grid point is at most T_L * 8.
+template <int L>
+__host__ __device__ constexpr int boys_rows() {
+    return kBoysAsymTi[L] * kBoysGridPerUnit + 1;
+}
+
+// boys64_row from a copy of the slice's first boys_rows<L>() rows in LDS (5 double2 per row).
+template <int L>
+__device__ __forceinline__ int boys64_row_lds(double T, const double2* lds, double2* r) {
+    const int g = (int)fmin(T * (double)kBoysGridPerUnit + 0.5, (double)(boys_rows<L>() - 1));
+    const double2* row = lds + g * (kBoysRow / 2);
+#pragma unroll
+    for (int x = 0; x < kBoysRow / 2; ++x) r[x] = row[x];
+    return g;
+}
 
 template <int L>
 __device__ __forceinline__ void boys64_eval(double T, int g, double pref, const double2* r, double* F) {

@@ -32,9 +32,11 @@ struct EriClass;
 // FP64 path: one loop over the primitive quartets (ket primitive outer, bra primitive inner).  The bra records are
 // wavefront-uniform scalar loads; the next one is requested before the current quartet is evaluated, which costs
 // scalar registers only.  Ket fields are read through 32-bit offsets from the bin's base.
-template <class C>
+// BLDS: the Boys rows come from the LDS copy `btab` of the order-L slice instead of the global table.
+template <class C, bool BLDS>
 __device__ __forceinline__ void accumulate64(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
-                                             const double* __restrict__ boys64tab, double* __restrict__ acc) {
+                                             const double* __restrict__ boys64tab, const double2* btab,
+                                             double* __restrict__ acc) {
     const unsigned npk = (unsigned)Kt.np, fsk = (unsigned)Kt.K * npk;
     const cdptr kbase = as_const(Kt.prim);
     const cdptr brec = as_const(B.rec) + (size_t)bra * B.K * kRec;  // wavefront-uniform: scalar loads
@@ -77,7 +79,13 @@ __device__ __forceinline__ void accumulate64(const BinDev& B, int bra, int kbn, 
         g.WQ[0] = roe * PQx; g.WQ[1] = roe * PQy; g.WQ[2] = roe * PQz;
         g.o2z = b[F_O2Z]; g.roz = roz; g.o2e = o2e; g.roe = roe; g.o2ze = 0.5 * inv;
         double F[C::L + 1];
-        boys64<C::L>(T, pref, boys64tab, F);
+        if constexpr (BLDS) {
+            double2 r[kBoysRow / 2];
+            const int gi = boys64_row_lds<C::L>(T, btab, r);
+            boys64_eval<C::L>(T, gi, pref, r, F);
+        } else {
+            boys64<C::L>(T, pref, boys64tab, F);
+        }
         C::template vrr<double>(F, g, acc);
 #pragma unroll
         for (int f = 0; f < kNumFields; ++f) b[f] = bn[f];
@@ -86,12 +94,12 @@ __device__ __forceinline__ void accumulate64(const BinDev& B, int bra, int kbn, 
     }
 }
 
-template <class C, bool MIXED>
+template <class C, bool MIXED, bool BLDS = false>
 __device__ __forceinline__ void accumulate(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
                                            const double* __restrict__ boys64tab, const float* __restrict__ boys32tab,
-                                           double* __restrict__ acc) {
+                                           double* __restrict__ acc, const double2* btab = nullptr) {
     if constexpr (!MIXED) {
-        accumulate64<C>(B, bra, kbn, Kt, ket, kkn, boys64tab, acc);
+        accumulate64<C, BLDS>(B, bra, kbn, Kt, ket, kkn, boys64tab, btab, acc);
         return;
     }
     const size_t npk = (size_t)Kt.np;
@@ -236,6 +244,11 @@ __device__ __forceinline__ int find_task(const long long* __restrict__ task_begi
 #ifndef UQC_KAC_LDS
 #define UQC_KAC_LDS 1
 #endif
+// 1: the FP64 Fock-build kernel of this class copies the rows of its Boys slice into LDS once per workgroup and
+// reads them there (the per-lane row gathers then leave the vector-memory path to the ket data and the density)
+#ifndef UQC_BOYS_LDS
+#define UQC_BOYS_LDS 0
+#endif
 constexpr int kKeepLimit = UQC_KEEP_LIMIT;
 constexpr bool kKacInLds = UQC_KAC_LDS != 0;
 
@@ -266,6 +279,17 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
     constexpr int SLOTS1 = (KAD_MODE == 2 ? NA * ND : 0) + (KAC_MODE == 2 ? NA * NC : 0);  // per spin
     constexpr int SLOTS = NSPIN * SLOTS1;
     __shared__ double slots[kBlock / kWave][SLOTS > 0 ? SLOTS * kWave : 1];
+    // (and only where the slots leave room for the rows in the workgroup's 160 KB of LDS)
+    constexpr bool BLDS = UQC_BOYS_LDS != 0 && !MIXED &&
+                          (kBlock / kWave) * (SLOTS > 0 ? SLOTS * kWave : 1) * 8 +
+                                  boys_rows<C::L>() * kBoysRow * 8 <= 160 * 1024 - 1024;
+    constexpr int BROWS = BLDS ? boys_rows<C::L>() : 1;
+    __shared__ double2 btab[BROWS * (kBoysRow / 2)];
+    if constexpr (BLDS) {  // every wavefront of the workgroup takes part before any leaves
+        const double2* src = reinterpret_cast<const double2*>(boys64tab + (size_t)C::L * kBoysNg * kBoysRow);
+        for (int i = (int)threadIdx.x; i < BROWS * (kBoysRow / 2); i += kBlock) btab[i] = src[i];
+        __syncthreads();
+    }
     const long long local = wave_item();
     if (local >= nitems) return;
     const long long item = item0 + local;
@@ -392,7 +416,7 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
             double acc[C::NACC];
 #pragma unroll
             for (int x = 0; x < C::NACC; ++x) acc[x] = 0.0;
-            accumulate<C, MIXED>(B, bra, kbn, Kt, kl, kkn, boys64tab, boys32tab, acc);
+            accumulate<C, MIXED, BLDS>(B, bra, kbn, Kt, kl, kkn, boys64tab, boys32tab, acc, btab);
             C::hrr(acc, bh[0], bh[1], bh[2], Kt.AB[kl], Kt.AB[Kt.np + kl],
                    Kt.AB[2 * Kt.np + kl], out);
         }
