@@ -264,6 +264,11 @@ uqc_status uqc_boys(uqc_ctx* ctx, int precision, int mmax, int n, const double* 
  * Serving: a request loop that admits Fock-build requests for molecules of different sizes as they arrive,
  * subject to an HBM budget and a slot limit, keeps each request's basis plan and density resident on the device
  * between iterations, and runs the quartet classes of all admitted requests together, one launch per class.
+ * A step carries a bounded amount of work (about 1.5e12 algorithmic FLOPs when several requests are admitted):
+ * the builds of small requests complete within a step, those of large ones are spread over several steps, so an
+ * admitted small request is not held back by a large one.  The next step is queued while the current one runs.
+ * Admission takes queued requests in arrival order; one that does not fit the remaining budget is passed over for
+ * later ones that do, until it has waited 2 s, after which nothing more is admitted before it.
  *
  * A request runs n_iter builds.  Iteration t uses density D_t; after it, D_{t+1} = (1-eps) D_t + eps R_t R_t^T
  * rescaled to tr(D_0), with R_t an nbf x ncol matrix of standard normal numbers drawn on the device from a
@@ -300,6 +305,8 @@ typedef struct {
     double* K;                  /* NULL before calling uqc_poll; filled when the request is done */
     double* G;
     double* D;                  /* density of the last iteration */
+    long long device_bytes;     /* device memory the request held while admitted (what the HBM budget was charged) */
+    int steps;                  /* server steps the request took part in (a build may span several) */
 } uqc_result;
 
 /* hbm_budget_bytes: device memory the server may hold for admitted requests; max_slots: admitted at once. */

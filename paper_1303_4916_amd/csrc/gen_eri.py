@@ -482,12 +482,19 @@ def perm_comp_table():
         rows.append([[idx[perm_q(t, p)] for t in cl] + [0] * (6 - len(cl)) for p in PERMS])
     return rows
 
+# Transcendental operations per primitive quartet, counted apart from the FLOPs: the reciprocal square root of
+# zeta + eta (1/(zeta+eta) is its square, and the prefactor takes its other factor) and exp(-T) of the Boys
+# function's downward recursion.
+TRANS_PER_PRIM = 2
+
+
 def setup_flops(L):
-    """Per-primitive-quartet set-up outside the recursion: zeta+eta, 1/(zeta+eta) (counted as 1), rho, PQ, T,
-    WP, WQ, recursion constants, prefactor with sqrt (counted as 1), Boys (Taylor of order 7 at F_L: 7 mul +
-    7 fma; downward recursion 2 per order; exp counted as 1) and scaling of the L+1 Boys values."""
-    f = 1 + 1 + 3 + 3 + 5 + 6 + 6 + 4 + 4
-    f += 14 + 1 + (3 * L if L > 0 else 0)
+    """Per-primitive-quartet FLOPs outside the recursion: zeta+eta (1), 1/(zeta+eta) as the square of
+    1/sqrt(zeta+eta) (1), rho, PQ, T, WP, WQ, recursion constants, prefactor (the square root itself is one of the
+    TRANS_PER_PRIM transcendental operations, not a FLOP), Boys (Taylor of order 7 at F_L: 7 mul + 7 fma; downward
+    recursion 2 per order; exp(-T) is the other transcendental operation) and scaling of the L+1 Boys values."""
+    f = 1 + 1 + 3 + 3 + 5 + 6 + 6 + 4 + 3
+    f += 14 + (3 * L if L > 0 else 0)
     f += L + 1
     return f
 
@@ -562,6 +569,7 @@ def main(outdir):
             "nout": nout,
             "vrr_flops": vrr_flops,
             "setup_flops": setup_flops(L),
+            "trans_per_prim": TRANS_PER_PRIM,
             "acc_flops": nacc,
             "f_prim": vrr_flops + setup_flops(L) + nacc,
             "hrr_flops": hrr_flops,

@@ -237,6 +237,23 @@ uqc_basis::~uqc_basis() {
     if (d_nuc) (void)hipFree(d_nuc);
 }
 
+size_t uqc_basis::device_bytes() const {
+    size_t n = work_bytes;
+    for (const auto& b : bins) n += b.bytes;
+    for (const auto& kv : plans) n += kv.second.bytes;
+    return n;
+}
+
+uqc_status uqc::check_fock_opts(const uqc_fock_opts& o, const std::string& nm) {
+    if (!(o.schwarz_tau >= 0) || !std::isfinite(o.schwarz_tau)) return uqc_fail(UQC_E_ARG, nm + ": bad tau");
+    if (o.precision != UQC_FP64 && o.precision != UQC_MIXED) return uqc_fail(UQC_E_ARG, nm + ": bad precision");
+    if (o.precision == UQC_MIXED && !(o.fp64_bound >= 0)) return uqc_fail(UQC_E_ARG, nm + ": bad fp64_bound");
+    if (o.max_items_per_launch < 0) return uqc_fail(UQC_E_ARG, nm + ": negative max_items_per_launch");
+    if (!std::isfinite(o.exchange_scale)) return uqc_fail(UQC_E_ARG, nm + ": exchange_scale is not finite");
+    if (o.streams < 0 || o.streams > 4) return uqc_fail(UQC_E_ARG, nm + ": streams must be in 0..4");
+    return UQC_OK;
+}
+
 void uqc::free_plan(Plan& p) {
     if (p.d_mem) (void)hipFree(p.d_mem);
     p.d_mem = nullptr;
@@ -251,6 +268,7 @@ static uqc_status upload_bin(Bin& b) {
     const size_t bytes = nd * sizeof(double) + 3 * np * sizeof(int);
     if (!b.d_mem) {
         if (hipMalloc(&b.d_mem, bytes) != hipSuccess) return uqc_fail(UQC_E_NOMEM, "basis: bin allocation failed");
+        b.bytes = bytes;
     }
     std::vector<char> host(bytes, 0);
     double* hd = (double*)host.data();
@@ -895,6 +913,7 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
         *st = uqc_fail(UQC_E_NOMEM, "plan: allocation failed");
         return nullptr;
     }
+    plan.bytes = std::max(bytes, (size_t)256);
     char* dbase = (char*)plan.d_mem;
     size_t pos = 0;
     plan.d_count = (unsigned long long*)dbase;  // [ntasks] quartets, then [ntasks] primitive quartets
@@ -1143,12 +1162,7 @@ uqc_status uqc::fock_run(uqc_basis* B, int nspin, const double* const* Din, doub
     uqc_fock_opts o;
     uqc_fock_opts_default(&o);
     if (opts) o = *opts;
-    if (!(o.schwarz_tau >= 0) || !std::isfinite(o.schwarz_tau)) return uqc_fail(UQC_E_ARG, nm + ": bad tau");
-    if (o.precision != UQC_FP64 && o.precision != UQC_MIXED) return uqc_fail(UQC_E_ARG, nm + ": bad precision");
-    if (o.precision == UQC_MIXED && !(o.fp64_bound >= 0)) return uqc_fail(UQC_E_ARG, nm + ": bad fp64_bound");
-    if (o.max_items_per_launch < 0) return uqc_fail(UQC_E_ARG, nm + ": negative max_items_per_launch");
-    if (!std::isfinite(o.exchange_scale)) return uqc_fail(UQC_E_ARG, nm + ": exchange_scale is not finite");
-    if (o.streams < 0 || o.streams > 4) return uqc_fail(UQC_E_ARG, nm + ": streams must be in 0..4");
+    if (const uqc_status e = uqc::check_fock_opts(o, nm)) return e;
     if (ws && (nspin != 1 || o.timing)) return uqc_fail(UQC_E_ARG, nm + ": closed shell only, no timing");
     const long long max_items = o.max_items_per_launch > 0 ? o.max_items_per_launch : kMaxItemsPerLaunch;
     const int nout = nspin == 1 ? 3 : 5;

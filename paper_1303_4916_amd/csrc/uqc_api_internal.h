@@ -58,6 +58,7 @@ struct Bin {
     int first_below(int dec) const;            // first index whose decade is < dec (np if none)
     int first_at_or_below(int dec) const;      // first index whose decade is <= dec (np if none)
     void* d_mem = nullptr;
+    size_t bytes = 0;                          // device bytes of d_mem
     BinDev dev{};
 };
 
@@ -89,6 +90,7 @@ struct Plan {
     unsigned long long* d_count = nullptr;         // [2 ntasks] per-task quartet, then primitive-quartet counters
     std::vector<unsigned long long> h_count;
     void* d_mem = nullptr;
+    size_t bytes = 0;                              // device bytes of d_mem
 };
 
 // Counts of the last build, from the per-task counters (h_count must hold the device values).
@@ -121,8 +123,15 @@ struct uqc_basis {
     int npairs[6] = {};
     double* d_nuc = nullptr;
     size_t nuc_cap = 0;
+    size_t device_bytes() const;  // device memory held for Fock builds: pair bins, workspace and plans
     ~uqc_basis();
 };
+
+namespace uqc {
+// Checks the options of a Fock build (tau, precision, fp64_bound, max_items_per_launch, exchange_scale, streams);
+// UQC_E_ARG with a message naming `who` otherwise.
+uqc_status check_fock_opts(const uqc_fock_opts& o, const std::string& who);
+}
 
 uqc::Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st);
 // The plan already made for these options, or nullptr (never allocates).

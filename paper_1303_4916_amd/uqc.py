@@ -97,7 +97,8 @@ class Request(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("n_iter", ctypes.c_int), ("nbf", ctypes.c_int), ("E2", ctypes.c_double * MAX_ITER),
                 ("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double), ("finish_ms", ctypes.c_double),
-                ("quartets", ctypes.c_longlong), ("J", _D), ("K", _D), ("G", _D), ("D", _D)]
+                ("quartets", ctypes.c_longlong), ("J", _D), ("K", _D), ("G", _D), ("D", _D),
+                ("device_bytes", ctypes.c_longlong), ("steps", ctypes.c_int)]
 
 
 _lock = threading.Lock()
@@ -530,7 +531,7 @@ class Server:
         self._keep.pop(ticket, None)
         out = {"n_iter": res.n_iter, "nbf": res.nbf, "E2": [res.E2[i] for i in range(res.n_iter)],
                "submit_ms": res.submit_ms, "admit_ms": res.admit_ms, "finish_ms": res.finish_ms,
-               "quartets": res.quartets}
+               "quartets": res.quartets, "device_bytes": res.device_bytes, "steps": res.steps}
         out.update(mats)
         return out
 

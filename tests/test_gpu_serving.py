@@ -222,3 +222,83 @@ def test_server_results_match_oracle(ctx):
         Gr, _ = oracle.fock_parts(J[-1], K[-1], Ds[-1])
         for name, ref in (("J", J[-1]), ("K", K[-1]), ("G", Gr)):
             assert np.max(np.abs(m[name] - ref)) <= tol * np.max(np.abs(ref)), (n, name)
+
+
+def test_server_charges_what_a_request_holds(ctx):
+    """The budget is charged the device memory a request really holds once admitted (basis bins, workspace,
+    screening plan, density): it matches the drop of free device memory while the request is on the device (to
+    allocation granularity) and is returned when it retires."""
+    import torch
+    sh = wl.lattice_shells(60, 911)
+    D0 = wl.random_density(np.random.default_rng(912), sh.nbf, 3, 60.0)
+    srv = uqc.Server(ctx, 8 << 30, 2)
+    torch.cuda.synchronize()
+    time.sleep(0.2)
+    free0 = torch.cuda.mem_get_info()[0]
+    t = srv.submit(sh, D0, n_iter=64, ncol=2, eps=0.01, seed=5)
+    low = free0
+    out = None
+    t0 = time.time()
+    while out is None:
+        low = min(low, torch.cuda.mem_get_info()[0])
+        out = srv.poll(t)
+        assert time.time() - t0 < 120
+        time.sleep(0.01)
+    held = out["device_bytes"]
+    drop = free0 - low
+    assert held > 40 * (1 << 20)
+    assert held <= drop <= 1.5 * held + (64 << 20), (held, drop)
+    time.sleep(0.2)
+    assert free0 - torch.cuda.mem_get_info()[0] <= (64 << 20)
+    srv.close()
+
+
+def test_server_small_request_not_held_back_by_large(ctx):
+    """A large request's builds are spread over several bounded steps, so a small request admitted beside it
+    finishes first; both still equal the same requests run alone."""
+    big = dict(shells=wl.lattice_shells(100, 921), n_iter=2, ncol=2, eps=0.05, seed=31,
+               opts=uqc.default_opts(tau=1e-12))
+    big["D0"] = wl.random_density(np.random.default_rng(922), big["shells"].nbf, 3, 100.0)
+    small = dict(shells=wl.lattice_shells(3, 923), n_iter=2, ncol=2, eps=0.05, seed=32,
+                 opts=uqc.default_opts(tau=1e-12))
+    small["D0"] = wl.random_density(np.random.default_rng(924), small["shells"].nbf, 3, 3.0)
+    mix = _run(ctx, [big, small], slots=4)
+    assert mix[0]["steps"] > mix[0]["n_iter"]
+    assert mix[1]["finish_ms"] < mix[0]["finish_ms"] - 100.0
+    alone = _run(ctx, [big, small], slots=1)
+    for m, a in zip(mix, alone):
+        assert np.max(np.abs(np.array(m["E2"]) - np.array(a["E2"]))) <= 1e-12 * np.max(np.abs(a["E2"]))
+        assert np.max(np.abs(m["G"] - a["G"])) <= 1e-12 * np.max(np.abs(a["G"]))
+
+
+def test_server_admission_passes_over_a_request_that_does_not_fit(ctx):
+    """With room for one large request and one small one, a second large request that arrives first waits while the
+    small one behind it is admitted and finishes."""
+    def req(n, seed, n_iter):
+        sh = wl.lattice_shells(n, seed)
+        return dict(shells=sh, D0=wl.random_density(np.random.default_rng(seed + 1), sh.nbf, 3, float(n)),
+                    n_iter=n_iter, ncol=2, eps=0.05, seed=seed, opts=uqc.default_opts(tau=1e-12))
+    big1, big2, small = req(40, 931, 6), req(40, 933, 1), req(3, 935, 1)
+    srv = uqc.Server(ctx, 1 << 30, 4)
+    t = srv.submit(**big1)
+    srv.drain()
+    one = srv.poll(t)["device_bytes"]
+    srv.close()
+    # room for one of the large requests (their admission estimate and what they hold are within +-50 %) and small
+    # ones, not for two large ones
+    out = _run(ctx, [big1, big2, small], slots=4, budget=int(1.5 * one))
+    assert out[2]["admit_ms"] < out[1]["admit_ms"]
+    assert out[2]["finish_ms"] < out[1]["admit_ms"]
+    assert all(o["n_iter"] == r["n_iter"] for o, r in zip(out, [big1, big2, small]))
+
+
+def test_server_rejects_bad_options_at_submit(ctx):
+    srv = uqc.Server(ctx, 1 << 30, 2)
+    sh = wl.lattice_shells(3, 3)
+    D = wl.random_density(np.random.default_rng(2), sh.nbf, 3, 3.0)
+    for o in (uqc.default_opts(tau=float("nan")), uqc.default_opts(tau=-1.0),
+              uqc.default_opts(precision=7), uqc.default_opts(precision=uqc.MIXED, fp64_bound=float("nan"))):
+        with pytest.raises(uqc.UqcError) as e:
+            srv.submit(sh, D, n_iter=1, opts=o)
+        assert e.value.status == uqc.UQC_E_ARG
+    srv.close()
