@@ -61,9 +61,11 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def summarize_pmc(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_write_csv: str, out: str, cmd: str):
+def summarize_pmc(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_write_csv: str, out: str, cmd: str,
+                  builds: int = 0):
     """Per-kernel HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch), each scaled
-    by the counter's reading for a plain 1 GiB device-to-device copy (bytes known)."""
+    by the counter's reading for a plain 1 GiB device-to-device copy (bytes known).  builds > 0: the Fock builds of
+    the counted run, so that bytes per build (a class may run as several dispatches per build) can be derived."""
     import csv
 
     def per_kernel(path, counter):
@@ -90,24 +92,44 @@ def summarize_pmc(fetch_csv: str, write_csv: str, copy_fetch_csv: str, copy_writ
         kernels[k] = {"fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "launches": kf[k][1]}
     doc = {"command": cmd, "copy_kernel": ck, "fetch_scale": f_scale, "write_scale": w_scale,
            "kernel_sources_sha256": kernel_sources_sha256(), "kernels": kernels}
+    if builds:
+        doc["builds"] = builds
     with open(out, "w") as f:
         json.dump(doc, f, indent=1, sort_keys=True)
     return doc
 
 
-def summarize_stats(stats_csv: str, out: str, cmd: str, title: str):
-    """Markdown table of a rocprofv3 --kernel-trace --stats kernel summary (average launch durations)."""
+def summarize_stats(stats_path: str, out: str, cmd: str, title: str, builds: int = 0):
+    """Markdown table of a rocprofv3 kernel summary: the --stats CSV (Name, Calls, AverageNs, TotalDurationNs,
+    Percentage) or, for the database format, the per-kernel aggregate of its dispatches.  builds > 0 adds the time
+    per Fock build (a class whose work list exceeds the per-launch cap runs as several dispatches per build)."""
     import csv
     rows = []
-    for r in csv.DictReader(open(stats_csv)):
-        k = r["Name"].split("(")[0].replace("void ", "").replace("uqc::", "")
-        rows.append((k, int(r["Calls"]), float(r["AverageNs"]) * 1e-6, float(r["TotalDurationNs"]) * 1e-6,
-                     float(r["Percentage"])))
+    if stats_path.endswith(".db"):
+        import sqlite3
+        con = sqlite3.connect(stats_path)
+        agg = {}
+        for name, dur in con.execute("select name, duration from kernels"):
+            v = agg.setdefault(name, [0, 0.0])
+            v[0] += 1
+            v[1] += float(dur)
+        tot = sum(v[1] for v in agg.values()) or 1.0
+        src = [(n, v[0], v[1] / v[0], v[1], 100.0 * v[1] / tot) for n, v in agg.items()]
+    else:
+        src = [(r["Name"], int(r["Calls"]), float(r["AverageNs"]), float(r["TotalDurationNs"]), float(r["Percentage"]))
+               for r in csv.DictReader(open(stats_path))]
+    for name, calls, avg_ns, tot_ns, pct in src:
+        k = name.split("(")[0].replace("void ", "").replace("uqc::", "")
+        rows.append((k, calls, avg_ns * 1e-6, tot_ns * 1e-6, pct) + ((tot_ns * 1e-6 / builds,) if builds else ()))
     rows.sort(key=lambda r: -r[3])
+    head = "| kernel | calls | avg ms | total ms | % |" + (" ms per build |" if builds else "")
     lines = ["# %s -- rocprofv3 kernel stats" % title, "", "Command (from the repository root):", "", "```", cmd,
-             "```", "", "kernel_sources_sha256: %s" % kernel_sources_sha256(), "",
-             "| kernel | calls | avg ms | total ms | % |", "|---|---|---|---|---|"]
-    lines += ["| %s | %d | %.3f | %.2f | %.1f |" % r for r in rows]
+             "```", "", "kernel_sources_sha256: %s" % kernel_sources_sha256(), ""]
+    if builds:
+        lines += ["Fock builds in the run: %d." % builds, ""]
+    lines += [head, "|---|---|---|---|---|" + ("---|" if builds else "")]
+    fmt = "| %s | %d | %.3f | %.2f | %.1f |" + (" %.2f |" if builds else "")
+    lines += [fmt % r for r in rows]
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
 
@@ -124,7 +146,9 @@ def traffic_for(kernel_key: str, path: str = None):
     k = doc["kernels"].get(kernel_key) or doc["kernels"].get(kernel_key.replace("k_digest<", "k_digest_team<"))
     if not k:
         return None
-    return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+    per_launch = k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
+    # per Fock build (the unit the achieved rate is measured in) when the counted run's build count is recorded
+    return per_launch * k["launches"] / doc["builds"] if doc.get("builds") else per_launch
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CUs x 2.4 GHz x 128 FP64 FLOP/clk/CU
 CLASS_NAME = "spd"
 
@@ -223,14 +247,16 @@ def main():
     ap.add_argument("--summarize-pmc", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
                                                          "COPY_WRITE_CSV", "CMD"),
                     help="write the per-kernel traffic summary from rocprofv3 counter CSVs and exit")
-    ap.add_argument("--summarize-stats", nargs=4, metavar=("STATS_CSV", "OUT_MD", "CMD", "TITLE"),
-                    help="write a markdown summary of a rocprofv3 kernel stats CSV and exit")
+    ap.add_argument("--summarize-stats", nargs=4, metavar=("STATS_CSV_OR_DB", "OUT_MD", "CMD", "TITLE"),
+                    help="write a markdown summary of a rocprofv3 kernel stats CSV (or results database) and exit")
+    ap.add_argument("--builds", type=int, default=0,
+                    help="--summarize-stats / --summarize-pmc: Fock builds in the profiled run")
     a = ap.parse_args()
     if a.summarize_stats:
-        summarize_stats(*a.summarize_stats)
+        summarize_stats(*a.summarize_stats, builds=a.builds)
         return
     if a.summarize_pmc:
-        summarize_pmc(*a.summarize_pmc[:4], a.traffic_out or TRAFFIC_FILE, a.summarize_pmc[4])
+        summarize_pmc(*a.summarize_pmc[:4], a.traffic_out or TRAFFIC_FILE, a.summarize_pmc[4], builds=a.builds)
         return
     if a.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the Fock build would shard by "
@@ -335,6 +361,7 @@ def fock_leg(B, Ds, tau, steps, warmup, streams, one_stream_builds, traffic_path
                      "traffic": traffic_for(dom_kernel_key(dom), traffic_path),
                      "kernel": "k_digest " + class_name(dom), "kernel_avg_ms": dom_avg_ms,
                      "kernel_flops_per_launch": cls_flops[dom],
+                     "per": "the class's work in one Fock build (time, FLOPs and traffic summed over its dispatches)",
                      "timed_in": "the one-stream pass of the same builds (each kernel alone on the chip)"},
         "classes": {class_name(k): {"ms": cls_ms[k] / n1, "quartets": cls_q[k],
                                     "tflops": cls_flops[k] / (cls_ms[k] / n1 * 1e-3) / 1e12}
