@@ -240,20 +240,26 @@ uqc_status uqc_scf_uhf(uqc_basis* b, int natom, const double* Z, const double* R
  * orbitals of which the first nfrozen are left out (frozen core, 0 <= nfrozen < nocc <= nbf):
  *   E2 = sum_{ijab} (ia|jb) [2 (ia|jb) - (ib|ja)] / (e_i + e_j - e_a - e_b),
  * i, j active occupied, a, b virtual.  The AO integrals are computed on the GPU (shell quartets with
- * Q_ab Q_cd >= tau; tau = 0: all) into an nbf^4 tensor in device memory and transformed to (ia|jb) by four GEMMs;
- * the call needs about 8 (nbf^4 + o nbf^3 + o v nbf^2) bytes of free device memory (o active occupied, v virtual
- * orbitals; e.g. 19 GB at nbf = 220) and fails with UQC_E_NOMEM otherwise.  `res` may be NULL.
- * Errors: UQC_E_ARG, UQC_E_NOMEM, UQC_E_DEVICE. */
+ * Q_ab Q_cd >= tau; tau = 0: all) in batches of ket index pairs, each batch transformed over its first index at once
+ * (the nbf^4 AO tensor is never held), then transformed to (ia|jb) by three more GEMMs; the call needs about
+ * 8 (o nbf^3 + o v nbf^2) bytes of free device memory plus one batch (o active occupied, v virtual orbitals; e.g.
+ * 14 GB at nbf = 440, o = 20) and fails with UQC_E_NOMEM otherwise.  batch_bytes > 0 caps the memory of one batch
+ * (more, smaller batches; it must hold the widest ket shell pair's columns, up to 72, of nbf^2 + o nbf doubles
+ * each, else UQC_E_NOMEM); 0: as much as free memory allows.  Every GEMM operand is kept below 2^31 doubles (one
+ * batch at most that much); when o v nbf^2 or o v^2 nbf reaches 2^31 (about nbf = 450 for a lattice with
+ * o = nbf / 22) the call fails with UQC_E_UNSUPPORTED.  `res` may be NULL.
+ * Errors: UQC_E_ARG, UQC_E_NOMEM, UQC_E_UNSUPPORTED, UQC_E_DEVICE. */
 typedef struct {
     double e2;               /* correlation energy (hartree) */
     double e_os, e_ss;       /* opposite-spin part sum (ia|jb)^2 / D and same-spin part, e2 = e_os + e_ss */
-    long long quartets;      /* canonical shell quartets computed for the AO tensor */
+    long long quartets;      /* shell quartets evaluated for the AO integrals (over all batches) */
     double ao_ms, transform_ms, energy_ms, ms;   /* wall time of the stages and of the call */
     double transform_flops;  /* 2 (o nbf^4 + o v nbf^3 + o v^2 nbf^2 + o^2 v^2 nbf) */
+    int batches;             /* ket-pair batches of the AO integrals */
 } uqc_mp2_result;
 
 uqc_status uqc_mp2(uqc_basis* b, const double* C, const double* eps, int nocc, int nfrozen, double tau,
-                   uqc_mp2_result* res);
+                   size_t batch_bytes, uqc_mp2_result* res);
 
 /* Device Boys function, for verification: F_0..F_mmax (mmax <= 8) at n arguments T (host arrays; out is
  * n*(mmax+1), row-major).  precision UQC_FP64: tabulated Taylor grid + downward recursion (asymptotic form with

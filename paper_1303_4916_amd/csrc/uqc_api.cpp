@@ -383,7 +383,7 @@ static uqc_status prim_schwarz(uqc_ctx* ctx, const Bin& bn, const int* didx, dou
         }
     uqc_status st = upload_bin(v);
     if (st != UQC_OK) return st;
-    ListDev L;
+    ListDev L{};
     L.bra = v.dev;
     L.ket = v.dev;
     L.bra_idx = didx;
@@ -599,7 +599,7 @@ uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* n
             st = uqc_fail(UQC_E_DEVICE, "basis: upload failed");
         for (size_t bi = 0; bi < B->bins.size() && st == UQC_OK; ++bi) {
             Bin& bn = B->bins[bi];
-            ListDev L;
+            ListDev L{};
             L.bra = bn.dev;
             L.ket = bn.dev;
             L.bra_idx = didx;
@@ -1101,7 +1101,7 @@ uqc_status uqc_eri_blocks(uqc_basis* B, int n, const int* q, int precision, doub
         st = uqc_fail(UQC_E_DEVICE, "uqc_eri_blocks: upload failed");
     for (auto& L : launches) {
         if (st != UQC_OK) break;
-        ListDev ld;
+        ListDev ld{};
         ld.bra = B->bins[L.bra_bin].dev;
         ld.ket = B->bins[L.ket_bin].dev;
         ld.bra_idx = didx + L.first;

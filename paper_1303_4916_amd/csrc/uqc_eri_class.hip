@@ -57,6 +57,9 @@ static hipError_t launch_list_cls(bool mixed, int mode, const ListDev& L, const 
     else if (mode == MODE_SCATTER)
         hipLaunchKernelGGL((k_list<UQC_LA, UQC_LB, UQC_LC, UQC_LD, false, MODE_SCATTER>), dim3(nblocks),
                            dim3(kBlock), 0, s, L, b64, b32);
+    else if (mode == MODE_BATCH)
+        hipLaunchKernelGGL((k_list<UQC_LA, UQC_LB, UQC_LC, UQC_LD, false, MODE_BATCH>), dim3(nblocks),
+                           dim3(kBlock), 0, s, L, b64, b32);
     else if (mixed)
         hipLaunchKernelGGL((k_list<UQC_LA, UQC_LB, UQC_LC, UQC_LD, true, MODE_STORE>), dim3(nblocks), dim3(kBlock), 0,
                            s, L, b64, b32);

@@ -569,6 +569,43 @@ __global__ __launch_bounds__(kBlock) void k_list(ListDev L, const double* __rest
                         T[((c * N + d) * N + b) * N + a] = v;
                         T[((d * N + c) * N + b) * N + a] = v;
                     }
+    } else if constexpr (MODE == MODE_BATCH) {
+        const int oa = L.bra.off_a[bra], ob = L.bra.off_b[bra], oc = L.ket.off_a[ket], od = L.ket.off_b[ket];
+        const bool sab = LA == LB && oa == ob, scd = LC == LD && oc == od;  // a pair of one shell: both orders
+        const size_t N = (size_t)L.nbf, W = (size_t)L.ncols;              // already among its components
+        const size_t col0 = (size_t)L.col[q];
+        double* T = L.out;
+#pragma unroll
+        for (int i = 0; i < C::NA; ++i)
+#pragma unroll
+            for (int j = 0; j < C::NB; ++j)
+#pragma unroll
+                for (int k = 0; k < C::NC; ++k)
+#pragma unroll
+                    for (int l = 0; l < C::ND; ++l) {
+                        const int x = ((i * C::NB + j) * C::NC + k) * C::ND + l;
+                        const double v = out[x] * (comp_factor(LA, i) * comp_factor(LB, j) * comp_factor(LC, k) *
+                                                   comp_factor(LD, l));
+                        if (!L.swap) {  // rows from the kernel's bra pair, columns from its ket pair
+                            const size_t r1 = (oa + i) * N + (ob + j), r2 = (ob + j) * N + (oa + i);
+                            const size_t c1 = col0 + k * C::ND + l, c2 = col0 + C::NC * C::ND + l * C::NC + k;
+                            T[r1 * W + c1] = v;
+                            if (!scd) T[r1 * W + c2] = v;
+                            if (!sab) {
+                                T[r2 * W + c1] = v;
+                                if (!scd) T[r2 * W + c2] = v;
+                            }
+                        } else {  // rows from the kernel's ket pair, columns from its bra pair
+                            const size_t r1 = (oc + k) * N + (od + l), r2 = (od + l) * N + (oc + k);
+                            const size_t c1 = col0 + i * C::NB + j, c2 = col0 + C::NA * C::NB + j * C::NA + i;
+                            T[r1 * W + c1] = v;
+                            if (!sab) T[r1 * W + c2] = v;
+                            if (!scd) {
+                                T[r2 * W + c1] = v;
+                                if (!sab) T[r2 * W + c2] = v;
+                            }
+                        }
+                    }
     } else if constexpr (MODE == MODE_STORE) {
         double* o = L.out + (size_t)q * NOUT;
 #pragma unroll

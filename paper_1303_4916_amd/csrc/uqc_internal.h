@@ -101,13 +101,19 @@ struct ListDev {
     const int* bra_idx;
     const int* ket_idx;
     int n;
-    double* out;               // STORE: [n][NA*NB*NC*ND]; SCHWARZ: [n]; SCATTER: the nbf^4 tensor (see Mode)
-    int nbf;                   // SCATTER only
+    double* out;               // STORE: [n][NA*NB*NC*ND]; SCHWARZ: [n]; SCATTER: the nbf^4 tensor; BATCH: see Mode
+    int nbf;                   // SCATTER and BATCH
+    const int* col;            // BATCH: [n] first column of the quartet's ket pair in the batch
+    int ncols;                 // BATCH: columns of the batch
+    int swap;                  // BATCH: 1 if the kernel's bra pair is the physical ket pair (class order)
 };
 
 // STORE: each quartet's block; SCHWARZ: sqrt of the largest diagonal element; SCATTER: every element of the block
-// written to the dense tensor out[((i nbf + j) nbf + k) nbf + l] at its eight permutationally equivalent places.
-enum Mode { MODE_STORE = 0, MODE_SCHWARZ = 1, MODE_SCATTER = 2 };
+// written to the dense tensor out[((i nbf + j) nbf + k) nbf + l] at its eight permutationally equivalent places;
+// BATCH: every element (mu nu|lam sig) written to out[(mu nbf + nu) ncols + col(lam sig)] for both orders of the bra
+// pair and both orders of the ket pair, where the ket pair's columns start at col[q]: (lam in c, sig in d) at
+// col + k n_d + l, then, for c != d, (lam in d, sig in c) at col + n_c n_d + l n_c + k.
+enum Mode { MODE_STORE = 0, MODE_SCHWARZ = 1, MODE_SCATTER = 2, MODE_BATCH = 3 };
 
 // Host launchers of one angular-momentum class (defined in uqc_eri_class.hip, one object per class).
 struct ClassLaunchers {

@@ -1,15 +1,19 @@
 // Closed-shell second-order Moller-Plesset energy over the Fock-build basis (the paper's MP2, spin-adapted form of
-// Szabo-Ostlund Sec. 6.5).  The AO integrals (mu nu|lam sig) are computed by the quartet kernels into a dense
-// nbf^4 tensor in HBM (canonical shell quartets, each element written to its eight equivalent places), then
-// transformed one index at a time by GEMMs on the matrix cores (rocBLAS; row-major tensors are handed over as
-// their column-major transposes):
-//   Q1  T1[i][nu lam sig] = sum_mu C[mu][i] T0[mu][nu lam sig]          one GEMM, m = nbf^3, n = o, k = nbf
+// Szabo-Ostlund Sec. 6.5).  The AO integrals are never held as one nbf^4 tensor: the ordered ket index pairs
+// (lam sig) are cut into batches along the canonical shell pairs, and for each batch the quartet kernels write
+// (mu nu|lam sig) for every (mu nu) and every (lam sig) of the batch into a dense buffer T0b[mu][nu][col] (each
+// canonical bra shell pair times each ket shell pair of the batch, both index orders of each pair, so a shell
+// quartet is evaluated once for each of its two pairs' batches); the first quarter transformation is applied to
+// the batch at once and its columns are put in place in T1.  Then the remaining transformations run as GEMMs on
+// the matrix cores (rocBLAS; row-major tensors are handed over as their column-major transposes):
+//   Q1  T1[i][nu lam sig] = sum_mu C[mu][i] T0[mu][nu lam sig]          per batch, m = nbf cols, n = o, k = nbf
 //   Q2  T2[i][a][lam sig] = sum_nu C[nu][a] T1[i][nu][lam sig]          batched over i, m = nbf^2, n = v, k = nbf
 //   Q3  Z[i a lam][b]     = sum_sig T2[i a lam][sig] C[sig][b]          one GEMM, m = v, n = o v nbf, k = nbf
 //   Q4  V[i][a][j][b]     = sum_lam C[lam][j] Z[i a][lam][b]           batched over (i a), m = v, n = o, k = nbf
 // and E2 = sum_{ijab} V_iajb (2 V_iajb - V_ibja) / (e_i + e_j - e_a - e_b), split into its opposite-spin part
 // sum V^2/D and same-spin part sum V (V - V_ibja)/D.  i, j run over the active occupied orbitals (frozen core
-// excluded), a, b over the virtual ones.
+// excluded), a, b over the virtual ones.  Peak memory: the o nbf^3 of T1 plus one batch (nbf^2 + o nbf doubles per
+// column), instead of nbf^4.
 #include "uqc_api_internal.h"
 #include "uqc_device_common.h"
 
@@ -55,6 +59,21 @@ struct DevBuf {
     ~DevBuf() { if (p) (void)hipFree(p); }
 };
 
+// Columns of a batch into their places in T1[i][nu][lam sig]: T1[i nbf^3 + nu nbf^2 + map[col]] = P[i R + nu ncols +
+// col], R = nbf ncols (P: the batch's first quarter transformation, column-major R x o).
+__global__ __launch_bounds__(kBlock) void k_mp2_place(const double* __restrict__ P, const int* __restrict__ map,
+                                                      int ncols, int nbf, int o, double* __restrict__ T1) {
+    const long long n = (long long)o * nbf * ncols;
+    const long long R = (long long)nbf * ncols;
+    const long long N2 = (long long)nbf * nbf, N3 = N2 * nbf;
+    for (long long x = (long long)blockIdx.x * kBlock + threadIdx.x; x < n; x += (long long)gridDim.x * kBlock) {
+        const int col = (int)(x % ncols);
+        const long long r = x / ncols;
+        const int nu = (int)(r % nbf), i = (int)(r / nbf);
+        T1[(long long)i * N3 + (long long)nu * N2 + map[col]] = P[(long long)i * R + (long long)nu * ncols + col];
+    }
+}
+
 }  // namespace
 
 #define UQC_BLAS_MP2(expr)                                                                               \
@@ -65,7 +84,7 @@ struct DevBuf {
     } while (0)
 
 uqc_status uqc_mp2(uqc_basis* B, const double* C, const double* eps, int nocc, int nfrozen, double tau,
-                   uqc_mp2_result* res) {
+                   size_t batch_bytes, uqc_mp2_result* res) {
     const auto t0 = std::chrono::steady_clock::now();
     if (!B || !C || !eps) return uqc_fail(UQC_E_ARG, "uqc_mp2: NULL argument");
     const int N = B->nbf;
@@ -80,113 +99,207 @@ uqc_status uqc_mp2(uqc_basis* B, const double* C, const double* eps, int nocc, i
     for (int i = nfrozen; i < nocc; ++i)
         for (int a = nocc; a < N; ++a)
             if (!(eps[a] > eps[i])) return uqc_fail(UQC_E_ARG, "uqc_mp2: a virtual orbital lies below an occupied one");
-    const double dN = N;
-    const double need = 8.0 * (dN * dN * dN * dN + (double)o * dN * dN * dN + (double)o * v * dN * dN +
-                               (double)o * v * v * dN + (double)o * o * v * v + dN * dN + dN + 8);
+    const size_t NN = (size_t)N * N, N3 = NN * N;
+    const size_t nT1 = (size_t)o * N3, nT2 = (size_t)o * v * NN, nZ = (size_t)o * v * v * N, nV = (size_t)o * v * o * v;
     uqc_ctx* ctx = B->ctx;
     UQC_HIP(hipSetDevice(ctx->device));
     size_t free_b = 0, total_b = 0;
     UQC_HIP(hipMemGetInfo(&free_b, &total_b));
-    if (need > 0.95 * (double)free_b) return uqc_fail(UQC_E_NOMEM, "uqc_mp2: the nbf^4 AO tensor and the transformed "
-                                                                  "intermediates do not fit in free device memory");
+    // memory: T1 through the first two stages, then T2 + Z + V; a batch takes (nbf^2 + o nbf) doubles per column
+    // plus its lists; the widest shell pair has 2 x 6 x 6 columns
+    const double avail = 0.9 * (double)free_b - 8.0 * ((double)NN + N + 64);
+    const double later = 8.0 * std::max((double)nT1 + (double)nT2, (double)nT2 + (double)nZ + (double)nV);
+    const double per_col = 8.0 * ((double)NN + (double)o * N) + 64.0 * N;
+    double for_batch = avail - 8.0 * (double)nT1;
+    if (batch_bytes > 0) for_batch = std::min(for_batch, (double)batch_bytes);
+    long long wmax = 1;  // columns of the widest ket shell pair (a batch holds at least one)
+    for (const Bin& by : B->bins) {
+        const long long w = (long long)((by.la + 1) * (by.la + 2) / 2) * ((by.lb + 1) * (by.lb + 2) / 2);
+        if (by.np > 0) wmax = std::max(wmax, 2 * w);  // both orders of a pair of two shells
+    }
+    // every GEMM operand stays below 2^31 doubles (a batch buffer, T2, Z): beyond that the transformations are not
+    // supported
+    if ((double)nT2 >= 2147483647.0 || (double)nZ >= 2147483647.0 || (double)N3 >= 2147483647.0)
+        return uqc_fail(UQC_E_UNSUPPORTED, "uqc_mp2: an intermediate of the transformation exceeds 2^31 doubles");
+    // a batch buffer, the first GEMM's operand, stays below 2^31 doubles
+    const long long max_cols =
+        (long long)std::min({for_batch / per_col, (double)NN, (double)(((1LL << 31) - 1) / (long long)NN)});
+    if (later > avail || max_cols < std::min<long long>(wmax, (long long)NN))
+        return uqc_fail(UQC_E_NOMEM, "uqc_mp2: the transformed intermediates (o nbf^3 doubles and more) do not fit "
+                                     "in free device memory");
     hipStream_t s = ctx->stream;
     rocblas_handle h = nullptr;
     uqc_status st = uqc::ensure_blas(ctx, &h);
     if (st != UQC_OK) return st;
-    const size_t NN = (size_t)N * N, N3 = NN * N, N4 = N3 * N;
-    DevBuf t0buf, cbuf, vbuf;
-    if (hipMalloc(&t0buf.p, N4 * sizeof(double)) != hipSuccess) return uqc_fail(UQC_E_NOMEM, "uqc_mp2: AO tensor");
+    DevBuf cbuf, vbuf;
     if (hipMalloc(&cbuf.p, (NN + N + 8) * sizeof(double)) != hipSuccess) return uqc_fail(UQC_E_NOMEM, "uqc_mp2: C");
-    double* T0 = (double*)t0buf.p;
     double* Cd = (double*)cbuf.p;
     double* ed = Cd + NN;
     double* acc = ed + N;
     UQC_HIP(hipMemcpyAsync(Cd, C, NN * sizeof(double), hipMemcpyHostToDevice, s));
     UQC_HIP(hipMemcpyAsync(ed, eps, N * sizeof(double), hipMemcpyHostToDevice, s));
     UQC_HIP(launch_zero(acc, 8, s));
-
-    // ---- AO tensor: every canonical shell quartet (bra bin >= ket bin; p >= q inside one bin) with Q Q >= tau
-    UQC_HIP(launch_zero(T0, N4, s));
-    long long quartets = 0;
-    {
-        // the lists of every bin pair in one host buffer and one upload; the class launches then run side by side on
-        // the context's stream and two more (the tensor positions they write are disjoint across canonical quartets)
-        struct Seg {
-            size_t X, Y, off;
-            int n;
-        };
-        std::vector<Seg> segs;
-        std::vector<int> hb, hk;
-        for (size_t X = 0; X < B->bins.size(); ++X)
-            for (size_t Y = 0; Y <= X; ++Y) {
-                const Bin &bx = B->bins[X], &by = B->bins[Y];
-                const size_t off = hb.size();
-                for (int p = 0; p < bx.np; ++p)
-                    for (int q = 0; q < (X == Y ? p + 1 : by.np); ++q)
-                        if (bx.Q[p] * by.Q[q] >= tau) {
-                            hb.push_back(p);
-                            hk.push_back(q);
-                        }
-                if (hb.size() > off) segs.push_back(Seg{X, Y, off, (int)(hb.size() - off)});
-            }
-        const size_t total = hb.size();
-        DevBuf ib;
-        if (hipMalloc(&ib.p, 2 * std::max<size_t>(total, 1) * sizeof(int)) != hipSuccess)
-            return uqc_fail(UQC_E_NOMEM, "uqc_mp2: quartet list");
-        int* dbra = (int*)ib.p;
-        int* dket = dbra + total;
-        if (total) {
-            UQC_HIP(hipMemcpyAsync(dbra, hb.data(), total * sizeof(int), hipMemcpyHostToDevice, s));
-            UQC_HIP(hipMemcpyAsync(dket, hk.data(), total * sizeof(int), hipMemcpyHostToDevice, s));
-        }
-        constexpr int kStreams = 3;
-        hipStream_t S[kStreams] = {s, nullptr, nullptr};
-        for (int k = 1; k < kStreams; ++k)
-            if (!(S[k] = ctx_stream(ctx, k))) return uqc_fail(UQC_E_DEVICE, "uqc_mp2: stream creation failed");
-        UQC_HIP(hipEventRecord(ctx->fork, s));
-        for (int k = 1; k < kStreams; ++k) UQC_HIP(hipStreamWaitEvent(S[k], ctx->fork, 0));
-        for (size_t i = 0; i < segs.size(); ++i) {
-            const Seg& g = segs[i];
-            const Bin &bx = B->bins[g.X], &by = B->bins[g.Y];
-            ListDev L;
-            L.bra = bx.dev;
-            L.ket = by.dev;
-            L.bra_idx = dbra + g.off;
-            L.ket_idx = dket + g.off;
-            L.n = g.n;
-            L.out = T0;
-            L.nbf = N;
-            UQC_HIP(launch_list(class_index(bx.la, bx.lb, by.la, by.lb), false, MODE_SCATTER, L, ctx->boys64,
-                                ctx->boys32, S[i % kStreams]));
-            quartets += g.n;
-        }
-        for (int k = 1; k < kStreams; ++k) {
-            UQC_HIP(hipEventRecord(ctx->join[k - 1], S[k]));
-            UQC_HIP(hipStreamWaitEvent(s, ctx->join[k - 1], 0));
-        }
-        UQC_HIP(hipStreamSynchronize(s));  // the index lists are freed at the end of this block
-    }
-    const auto t1 = std::chrono::steady_clock::now();
-
-    // ---- four quarter transformations
-    const double one = 1.0, zero = 0.0;
-    const double* Co = Cd + nfrozen;  // column-major (nbf_p x nbf_mu), ld nbf: rows p = nfrozen.. are the active occupied
-    const double* Cv = Cd + nocc;     // rows p = nocc.. are the virtuals
-    const size_t nT1 = (size_t)o * N3, nT2 = (size_t)o * v * NN, nZ = (size_t)o * v * v * N, nV = (size_t)o * v * o * v;
     if (hipMalloc(&vbuf.p, (nT1 + nT2) * sizeof(double)) != hipSuccess)
         return uqc_fail(UQC_E_NOMEM, "uqc_mp2: transformation buffers");
     double* T1 = (double*)vbuf.p;
     double* T2 = T1 + nT1;
-    // Q1: T1^T (N^3 x o) = T0^T (N^3 x N) * Co^T (N x o)
-    UQC_BLAS_MP2(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)N3, o, N, &one, T0,
-                               (rocblas_int)N3, Co, N, &zero, T1, (rocblas_int)N3));
+    const double one = 1.0, zero = 0.0;
+    const double* Co = Cd + nfrozen;  // column-major (nbf_p x nbf_mu), ld nbf: rows p = nfrozen.. are the active occupied
+    const double* Cv = Cd + nocc;     // rows p = nocc.. are the virtuals
+
+    // ---- AO integrals in ket-pair batches, each transformed over its first index at once
+    long long quartets = 0;
+    int nbatch = 0;
+    double q1_ms = 0;
+    {
+        struct KetPair {
+            int bin, pos, col;  // bin and position of the ket shell pair, first column in its batch
+        };
+        // batches of consecutive ket shell pairs (bin by bin) of at most max_cols columns
+        std::vector<std::vector<KetPair>> batches(1);
+        std::vector<long long> bcols(1, 0);
+        for (size_t Y = 0; Y < B->bins.size(); ++Y) {
+            const Bin& by = B->bins[Y];
+            const int nc = (by.la + 1) * (by.la + 2) / 2, nd = (by.lb + 1) * (by.lb + 2) / 2;
+            for (int q = 0; q < by.np; ++q) {
+                const bool same = by.la == by.lb && by.off_a[q] == by.off_b[q];
+                const int w = same ? nc * nd : 2 * nc * nd;
+                if (bcols.back() + w > max_cols) {
+                    batches.emplace_back();
+                    bcols.push_back(0);
+                }
+                batches.back().push_back(KetPair{(int)Y, q, (int)bcols.back()});
+                bcols.back() += w;
+            }
+        }
+        long long widest = 0;
+        for (long long c : bcols) widest = std::max(widest, c);
+        DevBuf tbuf, pbuf, mbuf;
+        if (hipMalloc(&tbuf.p, std::max<size_t>((size_t)(NN * widest), 1) * sizeof(double)) != hipSuccess ||
+            hipMalloc(&pbuf.p, std::max<size_t>((size_t)o * N * widest, 1) * sizeof(double)) != hipSuccess ||
+            hipMalloc(&mbuf.p, std::max<size_t>((size_t)widest, 1) * sizeof(int)) != hipSuccess)
+            return uqc_fail(UQC_E_NOMEM, "uqc_mp2: batch buffers");
+        double* T0b = (double*)tbuf.p;
+        double* P = (double*)pbuf.p;
+        int* dmap = (int*)mbuf.p;
+        UQC_HIP(launch_zero(T1, nT1, s));
+        constexpr int kStreams = 3;
+        hipStream_t S[kStreams] = {s, nullptr, nullptr};
+        for (int k = 1; k < kStreams; ++k)
+            if (!(S[k] = ctx_stream(ctx, k))) return uqc_fail(UQC_E_DEVICE, "uqc_mp2: stream creation failed");
+        for (size_t bi = 0; bi < batches.size(); ++bi) {
+            const auto& kp = batches[bi];
+            const int ncols = (int)bcols[bi];
+            if (ncols == 0) continue;
+            ++nbatch;
+            // columns -> (lam, sig) flat index
+            std::vector<int> map(ncols);
+            for (const KetPair& k : kp) {
+                const Bin& by = B->bins[k.bin];
+                const int nc = (by.la + 1) * (by.la + 2) / 2, nd = (by.lb + 1) * (by.lb + 2) / 2;
+                const int oc = by.off_a[k.pos], od = by.off_b[k.pos];
+                const bool same = by.la == by.lb && oc == od;
+                for (int x = 0; x < nc; ++x)
+                    for (int y = 0; y < nd; ++y) {
+                        map[k.col + x * nd + y] = (oc + x) * N + (od + y);
+                        if (!same) map[k.col + nc * nd + y * nc + x] = (od + y) * N + (oc + x);
+                    }
+            }
+            // quartets: every bra shell pair (all bins) x every ket shell pair of the batch, in the kernel's class
+            // order (swap: the kernel's bra is the ket pair); segments per (kernel bra bin, kernel ket bin, swap),
+            // lanes running along the batch's ket pairs for one bra pair so that their columns are adjacent
+            struct Seg {
+                int kb, kk, swap;
+                size_t off;
+                int n;
+            };
+            std::vector<Seg> segs;
+            std::vector<int> hb, hk, hc;
+            std::vector<std::vector<const KetPair*>> by_bin(B->bins.size());
+            for (const KetPair& k : kp) by_bin[k.bin].push_back(&k);
+            for (size_t X = 0; X < B->bins.size(); ++X) {
+                const Bin& bx = B->bins[X];
+                for (size_t Y = 0; Y < B->bins.size(); ++Y) {
+                    if (by_bin[Y].empty()) continue;
+                    const Bin& by = B->bins[Y];
+                    const int swap = class_index(bx.la, bx.lb, by.la, by.lb) < 0 ? 1 : 0;  // not in class order
+                    const size_t off = hb.size();
+                    for (int p = 0; p < bx.np; ++p)
+                        for (const KetPair* k : by_bin[Y])
+                            if (bx.Q[p] * by.Q[k->pos] >= tau) {
+                                hb.push_back(swap ? k->pos : p);
+                                hk.push_back(swap ? p : k->pos);
+                                hc.push_back(k->col);
+                            }
+                    if (hb.size() > off)
+                        segs.push_back(Seg{swap ? (int)Y : (int)X, swap ? (int)X : (int)Y, swap, off,
+                                           (int)(hb.size() - off)});
+                }
+            }
+            const size_t total = hb.size();
+            quartets += (long long)total;
+            DevBuf ib;
+            if (hipMalloc(&ib.p, 3 * std::max<size_t>(total, 1) * sizeof(int)) != hipSuccess)
+                return uqc_fail(UQC_E_NOMEM, "uqc_mp2: quartet list");
+            int* dbra = (int*)ib.p;
+            int* dket = dbra + total;
+            int* dcol = dket + total;
+            if (total) {
+                UQC_HIP(hipMemcpyAsync(dbra, hb.data(), total * sizeof(int), hipMemcpyHostToDevice, s));
+                UQC_HIP(hipMemcpyAsync(dket, hk.data(), total * sizeof(int), hipMemcpyHostToDevice, s));
+                UQC_HIP(hipMemcpyAsync(dcol, hc.data(), total * sizeof(int), hipMemcpyHostToDevice, s));
+            }
+            UQC_HIP(hipMemcpyAsync(dmap, map.data(), ncols * sizeof(int), hipMemcpyHostToDevice, s));
+            UQC_HIP(launch_zero(T0b, NN * (size_t)ncols, s));
+            // the class launches side by side (the batch positions they write are disjoint)
+            UQC_HIP(hipEventRecord(ctx->fork, s));
+            for (int k = 1; k < kStreams; ++k) UQC_HIP(hipStreamWaitEvent(S[k], ctx->fork, 0));
+            for (size_t i = 0; i < segs.size(); ++i) {
+                const Seg& g = segs[i];
+                const Bin &bb = B->bins[g.kb], &bk = B->bins[g.kk];
+                ListDev L{};
+                L.bra = bb.dev;
+                L.ket = bk.dev;
+                L.bra_idx = dbra + g.off;
+                L.ket_idx = dket + g.off;
+                L.col = dcol + g.off;
+                L.n = g.n;
+                L.out = T0b;
+                L.nbf = N;
+                L.ncols = ncols;
+                L.swap = g.swap;
+                UQC_HIP(launch_list(class_index(bb.la, bb.lb, bk.la, bk.lb), false, MODE_BATCH, L, ctx->boys64,
+                                    ctx->boys32, S[i % kStreams]));
+            }
+            for (int k = 1; k < kStreams; ++k) {
+                UQC_HIP(hipEventRecord(ctx->join[k - 1], S[k]));
+                UQC_HIP(hipStreamWaitEvent(s, ctx->join[k - 1], 0));
+            }
+            // Q1 of the batch: P (R x o) = T0b^T-view (R x N) * Co^T (N x o), R = nbf ncols; then into T1 (timed as
+            // part of the transformations once the batch's integrals are done)
+            const long long R = (long long)N * ncols;
+            UQC_HIP(hipStreamSynchronize(s));
+            const auto tq = std::chrono::steady_clock::now();
+            UQC_BLAS_MP2(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)R, o, N,
+                                       &one, T0b, (rocblas_int)R, Co, N, &zero, P, (rocblas_int)R));
+            {
+                const long long n = (long long)o * R;
+                const unsigned grid = (unsigned)std::min<long long>((n + kBlock - 1) / kBlock, 65536);
+                hipLaunchKernelGGL(k_mp2_place, dim3(grid), dim3(kBlock), 0, s, P, dmap, ncols, N, o, T1);
+                UQC_HIP(hipGetLastError());
+            }
+            UQC_HIP(hipStreamSynchronize(s));  // the batch's lists are freed at the end of this iteration
+            q1_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tq).count();
+        }
+    }
+    const auto t1 = std::chrono::steady_clock::now();
+
+    // ---- the other three quarter transformations
     // Q2: per i, T2_i^T (N^2 x v) = T1_i^T (N^2 x N) * Cv^T (N x v)
     UQC_BLAS_MP2(rocblas_dgemm_strided_batched(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)NN,
                                                v, N, &one, T1, (rocblas_int)NN, (rocblas_stride)N3, Cv, N, 0, &zero,
                                                T2, (rocblas_int)NN, (rocblas_stride)(v * NN), o));
     UQC_HIP(hipStreamSynchronize(s));
-    (void)hipFree(t0buf.p);  // the AO tensor is no longer needed
-    t0buf.p = nullptr;
     DevBuf zbuf;
     if (hipMalloc(&zbuf.p, (nZ + nV) * sizeof(double)) != hipSuccess)
         return uqc_fail(UQC_E_NOMEM, "uqc_mp2: transformation buffers");
@@ -221,11 +334,12 @@ uqc_status uqc_mp2(uqc_basis* B, const double* C, const double* eps, int nocc, i
         res->e_ss = h_acc[1];
         res->e2 = h_acc[0] + h_acc[1];
         res->quartets = quartets;
-        res->ao_ms = ms(t0, t1);
-        res->transform_ms = ms(t1, t2);
+        res->ao_ms = ms(t0, t1) - q1_ms;
+        res->transform_ms = ms(t1, t2) + q1_ms;
+        res->batches = nbatch;
         res->energy_ms = ms(t2, t3);
         res->ms = ms(t0, t3);
-        res->transform_flops = 2.0 * ((double)o * N4 + (double)o * v * N3 + (double)o * v * v * NN +
+        res->transform_flops = 2.0 * ((double)o * N3 * N + (double)o * v * N3 + (double)o * v * v * NN +
                                       (double)o * o * v * v * N);
     }
     return UQC_OK;

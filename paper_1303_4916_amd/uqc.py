@@ -64,7 +64,8 @@ class ScfResult(ctypes.Structure):
 class Mp2Result(ctypes.Structure):
     _fields_ = [("e2", ctypes.c_double), ("e_os", ctypes.c_double), ("e_ss", ctypes.c_double),
                 ("quartets", ctypes.c_longlong), ("ao_ms", ctypes.c_double), ("transform_ms", ctypes.c_double),
-                ("energy_ms", ctypes.c_double), ("ms", ctypes.c_double), ("transform_flops", ctypes.c_double)]
+                ("energy_ms", ctypes.c_double), ("ms", ctypes.c_double), ("transform_flops", ctypes.c_double),
+                ("batches", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -167,7 +168,8 @@ def load(build_if_missing: bool = True):
                                          ctypes.POINTER(Stats)]
         L.uqc_scf_uhf.argtypes = [vp, ctypes.c_int, _D, _D, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ScfOpts), _D,
                                   _D, _D, _D, ctypes.POINTER(ScfResult)]
-        L.uqc_mp2.argtypes = [vp, _D, _D, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.POINTER(Mp2Result)]
+        L.uqc_mp2.argtypes = [vp, _D, _D, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_size_t,
+                              ctypes.POINTER(Mp2Result)]
         for name in EXPORTED:
             if name not in ("uqc_fock_opts_default", "uqc_last_error", "uqc_scf_opts_default"):
                 getattr(L, name).restype = ctypes.c_int
@@ -454,16 +456,18 @@ class Basis:
                 "converged": bool(res.converged), "error": res.error, "ms": res.ms, "fock_ms": res.fock_ms,
                 "quartets": res.quartets, "P": P, "eps": eps}
 
-    def mp2(self, C, eps, nocc: int, nfrozen: int = 0, tau: float = 0.0):
+    def mp2(self, C, eps, nocc: int, nfrozen: int = 0, tau: float = 0.0, batch_bytes: int = 0):
         """Closed-shell MP2 correlation energy for canonical orbitals C[mu, p] and energies eps (host arrays);
-        returns a dict with e2, e_os, e_ss, the AO quartet count, stage timings and the transformation FLOPs."""
+        returns a dict with e2, e_os, e_ss, the AO quartet count, stage timings, the transformation FLOPs and the
+        number of AO batches.  batch_bytes > 0 caps the device memory of one AO batch (0: free memory decides)."""
         N = self.nbf
         C = np.ascontiguousarray(C, dtype=np.float64)
         eps = np.ascontiguousarray(eps, dtype=np.float64).reshape(-1)
         if C.shape != (N, N) or eps.shape[0] != N:
             raise ValueError("C must be %dx%d and eps of length %d" % (N, N, N))
         r = Mp2Result()
-        _check(load().uqc_mp2(self.h, _dp(C), _dp(eps), int(nocc), int(nfrozen), float(tau), ctypes.byref(r)))
+        _check(load().uqc_mp2(self.h, _dp(C), _dp(eps), int(nocc), int(nfrozen), float(tau),
+                              ctypes.c_size_t(int(batch_bytes)), ctypes.byref(r)))
         return {k: getattr(r, k) for k, _ in Mp2Result._fields_}
 
     def scf_uhf(self, Z, R, nalpha: int, nbeta: int, opts: ScfOpts = None):

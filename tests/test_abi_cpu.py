@@ -52,7 +52,7 @@ def test_null_arguments_rejected_before_device_use():
     assert L.uqc_scf_rhf(None, 0, None, None, 1, None, None, None, None) == uqc.UQC_E_ARG
     assert L.uqc_fock_build_uhf(None, None, None, None, None, None, None, None, None, None) == uqc.UQC_E_ARG
     assert L.uqc_scf_uhf(None, 0, None, None, 1, 0, None, None, None, None, None, None) == uqc.UQC_E_ARG
-    assert L.uqc_mp2(None, None, None, 1, 0, 0.0, None) == uqc.UQC_E_ARG
+    assert L.uqc_mp2(None, None, None, 1, 0, 0.0, 0, None) == uqc.UQC_E_ARG
     assert L.uqc_fock_build_noalloc(None, None, None, None, None, None, None) == uqc.UQC_E_ARG
     o = uqc.scf_opts()
     assert o.max_iter == 100 and o.e_conv == 1e-10 and o.d_conv == 1e-8 and o.diis_size == 8
