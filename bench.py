@@ -240,6 +240,8 @@ def main():
                     help="serve: mean arrival rate in requests/s (the stream's 200, or a sustainable rate)")
     ap.add_argument("--oracle-quartets", type=int, default=2000,
                     help="ERI sample size of the accuracy legs (oracle against both precisions)")
+    ap.add_argument("--fp64-bound", type=float, default=None,
+                    help="mixed150/large400: the mixed leg's FP64 routing bound (default: the library's 1e-8)")
     ap.add_argument("--streams", type=int, default=None,
                     help="HIP streams the class launches of one Fock build are spread over (default: the library's)")
     ap.add_argument("--fp64-only", action="store_true",
@@ -522,7 +524,8 @@ def bench_mixed(a):
         print("    class %s: %d of %d work items" % (class_name(cid), done, total), file=sys.stderr, flush=True)
 
     legs = [("fp64", uqc.default_opts(tau=w.tau, timing=True, progress=report)),
-            ("mixed", uqc.default_opts(tau=w.tau, precision=uqc.MIXED, timing=True, progress=report))]
+            ("mixed", uqc.default_opts(tau=w.tau, precision=uqc.MIXED, timing=True, progress=report,
+                                       fp64_bound=a.fp64_bound if a.fp64_bound is not None else 1e-8))]
     for name, opts in legs[:1] if a.fp64_only else legs:
         times = []
         for rep in range(max(1, a.steps)):
@@ -557,7 +560,9 @@ def bench_mixed(a):
                                          "large400": ": 400 atoms, N=4400, K=3 on every shell, tau=1e-11",
                                          "large400kd1": ": 400 atoms, N=4400, K=3 on s and p, K=1 on d, "
                                                         "tau=1e-11"}[a.workload],
-                   "nbf": N, "tau": w.tau, "fp64_bound": uqc.default_opts().fp64_bound if mixed else None},
+                   "nbf": N, "tau": w.tau,
+                   "fp64_bound": (a.fp64_bound if a.fp64_bound is not None else uqc.default_opts().fp64_bound)
+                   if mixed else None},
         "plan_ms": plan_ms,
         "fp64_build_ms": res["fp64"]["ms"],
         "quartets_per_build": res["fp64"]["quartets"],

@@ -260,11 +260,15 @@ void uqc::free_plan(Plan& p) {
 }
 
 // Device arrays of a bin in one allocation: prim [kNumFields*K*np], AB [3*np], sdeg [np], Q [np], rec
-// [np*K*kRec], hdr [np*kHdr], off_a [np], off_b [np].
+// [np*K*kRec], hdr [np*kHdr], cq [ceil(np/64)*K], off_a [np], off_b [np], kp [np].  Before the primitive bounds are
+// known, the record slot of Q_e and cq hold a huge value (nothing is screened by them).
 static uqc_status upload_bin(Bin& b) {
     const size_t np = b.np, K = b.K;
-    const size_t n_prim = kNumFields * K * np, n_rec = np * K * kRec, n_hdr = np * kHdr;
-    const size_t nd = n_prim + 3 * np + 2 * np + n_rec + n_hdr;
+    const size_t nchunk = (np + kWave - 1) / kWave;
+    const size_t n_prim = kNumFields * K * np, n_rec = np * K * kRec, n_hdr = np * kHdr, n_cq = nchunk * K;
+    const size_t nd = n_prim + 3 * np + 2 * np + n_rec + n_hdr + n_cq;
+    const bool have_q = b.qprim.size() == K * np;
+    constexpr double kUnknown = 1e300;
     const size_t bytes = nd * sizeof(double) + 3 * np * sizeof(int);
     if (!b.d_mem) {
         if (hipMalloc(&b.d_mem, bytes) != hipSuccess) return uqc_fail(UQC_E_NOMEM, "basis: bin allocation failed");
@@ -279,8 +283,10 @@ static uqc_status upload_bin(Bin& b) {
     double* rec = hd + n_prim + 5 * np;
     double* hdr = rec + n_rec;
     for (size_t i = 0; i < np; ++i) {
-        for (size_t k = 0; k < K; ++k)
+        for (size_t k = 0; k < K; ++k) {
             for (size_t f = 0; f < (size_t)kNumFields; ++f) rec[(i * K + k) * kRec + f] = b.prim[(f * K + k) * np + i];
+            rec[(i * K + k) * kRec + kRecQ] = have_q ? b.qprim[k * np + i] : kUnknown;
+        }
         double* h = hdr + i * kHdr;
         h[0] = b.AB[i];
         h[1] = b.AB[np + i];
@@ -291,6 +297,14 @@ static uqc_status upload_bin(Bin& b) {
         o[0] = b.off_a[i];
         o[1] = b.off_b[i];
     }
+    double* cq = hdr + n_hdr;
+    for (size_t c = 0; c < nchunk; ++c)
+        for (size_t k = 0; k < K; ++k) {
+            double m = have_q ? 0.0 : kUnknown;
+            if (have_q)
+                for (size_t i = c * kWave; i < std::min(np, (c + 1) * kWave); ++i) m = std::max(m, b.qprim[k * np + i]);
+            cq[c * K + k] = m;
+        }
     int* hi = (int*)(hd + nd);
     std::memcpy(hi, b.off_a.data(), np * sizeof(int));
     std::memcpy(hi + np, b.off_b.data(), np * sizeof(int));
@@ -304,6 +318,7 @@ static uqc_status upload_bin(Bin& b) {
     b.dev.Q = dd + n_prim + 4 * np;
     b.dev.rec = dd + n_prim + 5 * np;
     b.dev.hdr = b.dev.rec + n_rec;
+    b.dev.cq = b.dev.hdr + n_hdr;
     b.dev.off_a = di;
     b.dev.off_b = di + np;
     b.dev.kp = di + 2 * np;
@@ -334,9 +349,12 @@ static void permute_bin(Bin& b, const std::vector<int>& perm) {
     const size_t np = b.np, K = b.K;
     std::vector<double> prim(b.prim.size()), AB(b.AB.size()), sdeg(np), Q(np);
     std::vector<int> oa(np), ob(np), sa(np), sb(np), kp(np);
+    std::vector<double> qprim(b.qprim.size());
     for (size_t i = 0; i < np; ++i) {
         const size_t o = perm[i];
         kp[i] = b.kp[o];
+        if (!qprim.empty())
+            for (size_t k = 0; k < K; ++k) qprim[k * np + i] = b.qprim[k * np + o];
         for (size_t f = 0; f < (size_t)kNumFields; ++f)
             for (size_t k = 0; k < K; ++k) prim[(f * K + k) * np + i] = b.prim[(f * K + k) * np + o];
         for (int x = 0; x < 3; ++x) AB[x * np + i] = b.AB[x * np + o];
@@ -356,6 +374,7 @@ static void permute_bin(Bin& b, const std::vector<int>& perm) {
     b.sa.swap(sa);
     b.sb.swap(sb);
     b.kp.swap(kp);
+    b.qprim.swap(qprim);
 }
 
 // Bounds Q_e = sqrt(max_ij (e|e)_ij) of every primitive pair e of a bin (entry e = k * np + i for primitive pair k
@@ -406,6 +425,7 @@ static void order_primitives(std::vector<Bin>& bins, const std::vector<std::vect
     for (size_t b = 0; b < bins.size(); ++b) {
         Bin& bn = bins[b];
         const size_t np = bn.np, K = bn.K;
+        bn.qprim.assign(K * np, 0.0);
         std::vector<int> ord(K);
         std::vector<double> rec(kNumFields * K);
         for (size_t i = 0; i < np; ++i) {
@@ -416,6 +436,7 @@ static void order_primitives(std::vector<Bin>& bins, const std::vector<std::vect
             for (size_t k = 0; k < K; ++k)
                 if (qp[b][(size_t)ord[k] * np + i] * qmax > kPrimEps) ++keep;
             bn.kp[i] = std::max(keep, 1);
+            for (size_t k = 0; k < K; ++k) bn.qprim[k * np + i] = qp[b][(size_t)ord[k] * np + i];
             for (size_t f = 0; f < (size_t)kNumFields; ++f)
                 for (size_t k = 0; k < K; ++k) rec[f * K + k] = bn.prim[(f * K + ord[k]) * np + i];
             for (size_t f = 0; f < (size_t)kNumFields; ++f)

@@ -53,6 +53,8 @@ struct Bin {
     std::vector<double> prim, AB, sdeg, Q;
     std::vector<int> off_a, off_b, sa, sb;
     std::vector<int> kp;                       // [np] leading primitive pairs above the primitive bound
+    std::vector<double> qprim;                 // [K][np] primitive-pair bounds Q_e, in the order of prim (empty
+                                               // until the bounds are known)
     std::vector<int> bucket;                   // [np] decade of Q (floor(log10 Q)), non-increasing along the bin
     std::vector<std::pair<int, int>> bstart;   // (decade, first index) for every decade present, in bin order
     int first_below(int dec) const;            // first index whose decade is < dec (np if none)

@@ -33,10 +33,16 @@ struct EriClass;
 // wavefront-uniform scalar loads; the next one is requested before the current quartet is evaluated, which costs
 // scalar registers only.  Ket fields are read through 32-bit offsets from the bin's base.
 // BLDS: the Boys rows come from the LDS copy `btab` of the order-L slice instead of the global table.
-template <class C, bool BLDS>
-__device__ __forceinline__ void accumulate64(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
+// SCR (Fock builds): cqk is the ket chunk's row of Kt.cq.  At ket primitive position kk, the bra primitive pairs e
+// with Q_e * cqk[kk] <= kPrimEps are left out: by the Cauchy-Schwarz inequality each such primitive quartet is at
+// most kPrimEps for every ket of the chunk, the same per-quartet bound as the basis-wide cut (Q_e * Q_max).  Both
+// sides are ordered by decreasing bound, so the bra count only shrinks as kk grows, and the loop ends when it
+// reaches zero.  (cqk is wavefront-uniform: were it not, the whole loop would turn into per-lane control flow.)
+// Returns the primitive quartets evaluated per lane (wavefront-uniform).
+template <class C, bool BLDS, bool SCR>
+__device__ __forceinline__ int accumulate64(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
                                              const double* __restrict__ boys64tab, const double2* btab,
-                                             double* __restrict__ acc) {
+                                             double* __restrict__ acc, cdptr cqk) {
     const unsigned npk = (unsigned)Kt.np, fsk = (unsigned)Kt.K * npk;
     const cdptr kbase = as_const(Kt.prim);
     const cdptr brec = as_const(B.rec) + (size_t)bra * B.K * kRec;  // wavefront-uniform: scalar loads
@@ -45,9 +51,15 @@ __device__ __forceinline__ void accumulate64(const BinDev& B, int bra, int kbn, 
     double b[kNumFields];
 #pragma unroll
     for (int f = 0; f < kNumFields; ++f) b[f] = brec[f];
-    int kb = 0, kk = 0;
+    int kb = 0, kk = 0, nb = KB, done = 0;
     for (int p = 0; p < NPQ; ++p) {
         if (kb == 0) {  // wavefront-uniform: next ket primitive
+            if constexpr (SCR) {
+                const double qf = cqk[kk];
+                while (nb > 0 && brec[(nb - 1) * kRec + kRecQ] * qf <= kPrimEps) --nb;
+                if (nb == 0) break;
+            }
+            done += nb;
             const unsigned o = (unsigned)kk * npk + (unsigned)ket;
             eta = kbase[o + F_Z * fsk];
             Qx = kbase[o + F_PX * fsk];
@@ -59,7 +71,7 @@ __device__ __forceinline__ void accumulate64(const BinDev& B, int bra, int kbn, 
             prefk = kbase[o + F_PREF * fsk];
             o2e = kbase[o + F_O2Z * fsk];
         }
-        const int kbn = kb + 1 == KB ? 0 : kb + 1;
+        const int kbn = kb + 1 == nb ? 0 : kb + 1;
         double bn[kNumFields];
         const cdptr bp = brec + kbn * kRec;
 #pragma unroll
@@ -90,29 +102,38 @@ __device__ __forceinline__ void accumulate64(const BinDev& B, int bra, int kbn, 
 #pragma unroll
         for (int f = 0; f < kNumFields; ++f) b[f] = bn[f];
         kb = kbn;
-        if (kb == 0) ++kk;
+        if (kb == 0 && ++kk == kkn) break;
     }
+    return done;
 }
 
-template <class C, bool MIXED, bool BLDS = false>
-__device__ __forceinline__ void accumulate(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
-                                           const double* __restrict__ boys64tab, const float* __restrict__ boys32tab,
-                                           double* __restrict__ acc, const double2* btab = nullptr) {
-    if constexpr (!MIXED) {
-        accumulate64<C, BLDS>(B, bra, kbn, Kt, ket, kkn, boys64tab, btab, acc);
-        return;
-    }
+
+// accumulate64, or for MIXED the same loops with FP32 recursions (and the same SCR screen); returns the primitive
+// quartets evaluated per lane (wavefront-uniform).
+template <class C, bool MIXED, bool BLDS = false, bool SCR = false>
+__device__ __forceinline__ int accumulate(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
+                                          const double* __restrict__ boys64tab, const float* __restrict__ boys32tab,
+                                          double* __restrict__ acc, const double2* btab = nullptr,
+                                          cdptr cqk = nullptr) {
+    if constexpr (!MIXED) return accumulate64<C, BLDS, SCR>(B, bra, kbn, Kt, ket, kkn, boys64tab, btab, acc, cqk);
     const size_t npk = (size_t)Kt.np;
     const size_t fsk = (size_t)Kt.K * npk;
     const cdptr brec = as_const(B.rec) + (size_t)bra * B.K * kRec;  // wavefront-uniform: scalar loads
+    int nb = kbn, done = 0;
     for (int kk = 0; kk < kkn; ++kk) {
+        if constexpr (SCR) {
+            const double qf = cqk[kk];
+            while (nb > 0 && brec[(nb - 1) * kRec + kRecQ] * qf <= kPrimEps) --nb;
+            if (nb == 0) break;
+        }
+        done += nb;
         const double* kp = Kt.prim + (size_t)kk * npk + ket;
         const double eta = kp[F_Z * fsk];
         const double Qx = kp[F_PX * fsk], Qy = kp[F_PY * fsk], Qz = kp[F_PZ * fsk];
         const double QCx = kp[F_PAX * fsk], QCy = kp[F_PAY * fsk], QCz = kp[F_PAZ * fsk];
         const double prefk = kp[F_PREF * fsk];
         const double o2e = kp[F_O2Z * fsk];
-        for (int kb = 0; kb < kbn; ++kb) {
+        for (int kb = 0; kb < nb; ++kb) {
             const cdptr bp = brec + kb * kRec;
             const double zeta = bp[F_Z];
             const double Px = bp[F_PX], Py = bp[F_PY], Pz = bp[F_PZ];
@@ -128,17 +149,7 @@ __device__ __forceinline__ void accumulate(const BinDev& B, int bra, int kbn, co
             const double T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
             const double roz = eta * inv, roe = zeta * inv;
             const double pref = prefb * prefk * rz;
-            if constexpr (!MIXED) {
-                PrimGeom<double> g;
-                g.PA[0] = PAx; g.PA[1] = PAy; g.PA[2] = PAz;
-                g.WP[0] = -roz * PQx; g.WP[1] = -roz * PQy; g.WP[2] = -roz * PQz;
-                g.QC[0] = QCx; g.QC[1] = QCy; g.QC[2] = QCz;
-                g.WQ[0] = roe * PQx; g.WQ[1] = roe * PQy; g.WQ[2] = roe * PQz;
-                g.o2z = o2z; g.roz = roz; g.o2e = o2e; g.roe = roe; g.o2ze = 0.5 * inv;
-                double F[C::L + 1];
-                boys64<C::L>(T, pref, boys64tab, F);
-                C::template vrr<double>(F, g, acc);
-            } else {
+            {
                 PrimGeom<float> g;
                 g.PA[0] = (float)PAx; g.PA[1] = (float)PAy; g.PA[2] = (float)PAz;
                 g.WP[0] = (float)(-roz * PQx); g.WP[1] = (float)(-roz * PQy); g.WP[2] = (float)(-roz * PQz);
@@ -162,6 +173,7 @@ __device__ __forceinline__ void accumulate(const BinDev& B, int bra, int kbn, co
             }
         }
     }
+    return done;
 }
 
 // Segmented inclusive sum across the wavefront: lanes with equal keys form contiguous runs; inseg[s] tells whether
@@ -306,6 +318,8 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
     const double qk = Kt.Q[kc];
     // ket primitive pairs evaluated: the most any lane's ket needs (the kets stay for the whole item)
     const int kkn = wave_max_int(ket_ok ? Kt.kp[kc] : 1);
+    // the chunk's largest primitive bounds (it.y is loaded through a generic pointer: made wavefront-uniform)
+    const cdptr cqk = as_const(Kt.cq) + (size_t)__builtin_amdgcn_readfirstlane(it.y) * Kt.K;
     const bool redir = NSPIN == 1 && wr.J != nullptr;  // kernel argument: wavefront-uniform
     const double* __restrict__ D = redir ? wr.D : tk.D;
     // D is read-only while the kernel runs: read through the constant address space with 32-bit offsets (N < 2^16)
@@ -404,7 +418,6 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
         if (live == 0ULL) continue;  // uniform: no quartet of this bra pair survives in the chunk
         const int kbn = as_const(B.kp)[bra];
         cnt += (unsigned long long)__popcll(live);
-        pcnt += (unsigned long long)__popcll(live) * (unsigned long long)(kbn * kkn);
         const int oa = ((ciptr)(bh + 5))[0], ob = ((ciptr)(bh + 5))[1];
         if (oa != cur_a) {
             if (cur_a >= 0) flush_a();
@@ -416,7 +429,9 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
             double acc[C::NACC];
 #pragma unroll
             for (int x = 0; x < C::NACC; ++x) acc[x] = 0.0;
-            accumulate<C, MIXED, BLDS>(B, bra, kbn, Kt, kl, kkn, boys64tab, boys32tab, acc, btab);
+            const int done = accumulate<C, MIXED, BLDS, true>(B, bra, kbn, Kt, kl, kkn, boys64tab, boys32tab, acc,
+                                                              btab, cqk);
+            pcnt += (unsigned long long)__popcll(live) * (unsigned long long)done;
             C::hrr(acc, bh[0], bh[1], bh[2], Kt.AB[kl], Kt.AB[Kt.np + kl],
                    Kt.AB[2 * Kt.np + kl], out);
         }

@@ -30,15 +30,25 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Contracted representative accumulators of one lane: the recursion of class TC with the geometry relabelled by
-// the axis permutation (q0, q1, q2).
+// the axis permutation (q0, q1, q2).  The primitive screen of accumulate64 (SCR) with the ket bound at position kk
+// taken as the larger of the rows cq0, cq1 of Kt.cq (the 64-pair chunks that hold the item's ten kets).  Returns
+// the primitive quartets evaluated per lane (wavefront-uniform).
 template <class TC, bool MIXED>
-__device__ __forceinline__ void team_accumulate(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
-                                                int q0, int q1, int q2, const double* __restrict__ boys64tab,
-                                                const float* __restrict__ boys32tab, double* __restrict__ acc) {
+__device__ __forceinline__ int team_accumulate(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
+                                               int q0, int q1, int q2, const double* __restrict__ boys64tab,
+                                               const float* __restrict__ boys32tab, double* __restrict__ acc,
+                                               cdptr cq0, cdptr cq1) {
     const size_t npk = (size_t)Kt.np;
     const size_t fsk = (size_t)Kt.K * npk;
     const cdptr brec = as_const(B.rec) + (size_t)bra * B.K * kRec;  // wavefront-uniform: scalar loads
+    int nb = kbn, done = 0;
     for (int kk = 0; kk < kkn; ++kk) {
+        {
+            const double qf = fmax(cq0[kk], cq1[kk]);
+            while (nb > 0 && brec[(nb - 1) * kRec + kRecQ] * qf <= kPrimEps) --nb;
+            if (nb == 0) break;
+        }
+        done += nb;
         const double* kp = Kt.prim + (size_t)kk * npk + ket;
         const double eta = kp[F_Z * fsk];
         const double Qx = kp[F_PX * fsk], Qy = kp[F_PY * fsk], Qz = kp[F_PZ * fsk];
@@ -46,7 +56,7 @@ __device__ __forceinline__ void team_accumulate(const BinDev& B, int bra, int kb
         const double QCx = sel3(QC0, QC1, QC2, q0), QCy = sel3(QC0, QC1, QC2, q1), QCz = sel3(QC0, QC1, QC2, q2);
         const double prefk = kp[F_PREF * fsk];
         const double o2e = kp[F_O2Z * fsk];
-        for (int kb = 0; kb < kbn; ++kb) {
+        for (int kb = 0; kb < nb; ++kb) {
             const cdptr bp = brec + kb * kRec;
             const double zeta = bp[F_Z];
             const double Px = bp[F_PX], Py = bp[F_PY], Pz = bp[F_PZ];
@@ -98,6 +108,7 @@ __device__ __forceinline__ void team_accumulate(const BinDev& B, int bra, int kb
             }
         }
     }
+    return done;
 }
 
 // Streaming digest of one lane (classes with too many outputs to hold): all six density slices gathered in the
@@ -223,6 +234,10 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
     const double qk = Kt.Q[kc];
     // ket primitive pairs evaluated: the most any team's ket needs (the kets stay for the whole item)
     const int kkn = wave_max_int(ket_ok ? Kt.kp[kc] : 1);
+    // largest primitive bounds of the 64-pair chunks that hold the item's kets (one or two)
+    const int kfirst = __builtin_amdgcn_readfirstlane(it.y) * kTeamsPerWave, klast = min(kfirst + kTeamsPerWave, Kt.np) - 1;
+    const cdptr cq0 = as_const(Kt.cq) + (size_t)(kfirst / kWave) * Kt.K;
+    const cdptr cq1 = as_const(Kt.cq) + (size_t)(klast / kWave) * Kt.K;
     const bool redir = NSPIN == 1 && wr.J != nullptr;  // kernel argument: wavefront-uniform
     const double* __restrict__ D = redir ? wr.D : tk.D;
     // D is read-only while the kernel runs: read through the constant address space with 32-bit offsets (N < 2^16)
@@ -278,7 +293,6 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
         if (live == 0ULL) continue;
         const int kbn = as_const(B.kp)[bra];
         cnt += (unsigned long long)(__popcll(live) / kTeam);
-        pcnt += (unsigned long long)(__popcll(live) / kTeam) * (unsigned long long)(kbn * kkn);
         const int oa = ((ciptr)(bh + 5))[0], ob = ((ciptr)(bh + 5))[1];
         if (oa != cur_a) {
             if (cur_a >= 0) {
@@ -294,7 +308,9 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
         double acc[TC::NREP];
 #pragma unroll
         for (int x = 0; x < TC::NREP; ++x) acc[x] = 0.0;
-        team_accumulate<TC, MIXED>(B, bra, kbn, Kt, kl, kkn, q0, q1, q2, boys64tab, boys32tab, acc);
+        const int done = team_accumulate<TC, MIXED>(B, bra, kbn, Kt, kl, kkn, q0, q1, q2, boys64tab, boys32tab, acc,
+                                                    cq0, cq1);
+        pcnt += (unsigned long long)(__popcll(live) / kTeam) * (unsigned long long)done;
 
         int src[kTeam];
 #pragma unroll

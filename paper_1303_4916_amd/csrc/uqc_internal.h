@@ -34,7 +34,8 @@ constexpr long long kMaxItemsPerLaunch = 1LL << 20;  // work items per class-ker
 // Primitive-pair fields, stored field-major: prim[field][k][np] (consecutive pairs contiguous; the ket side, one
 // pair per lane), and again pair-major: rec[np][k][kRec] (the bra side, one pair per wavefront, scalar loads)
 enum PrimField { F_Z = 0, F_PX, F_PY, F_PZ, F_PAX, F_PAY, F_PAZ, F_PREF, F_O2Z, kNumFields };
-constexpr int kRec = 10;               // doubles per pair-major primitive record (kNumFields + 1 pad)
+constexpr int kRec = 10;               // doubles per pair-major primitive record: the fields, then Q_e
+constexpr int kRecQ = kNumFields;      // record slot of the primitive pair's bound Q_e
 constexpr int kHdr = 8;                // doubles per pair header: A-B (3), sdeg, Q, {off_a, off_b} (two ints), pad
 
 // One bin of shell pairs with the same (l_a, l_b, K_a, K_b).  Pairs are ordered by decade of their Schwarz bound
@@ -51,6 +52,8 @@ struct BinDev {
     const double* Q;      // [np] Schwarz bound of the pair
     const int* kp;        // [np] primitive pairs evaluated by the Fock build: the leading kp of the pair's K, which
                           // are ordered by decreasing bound (the rest fall under kPrimEps)
+    const double* cq;     // [ceil(np / 64)][K] for each chunk of 64 consecutive pairs and each primitive position k,
+                          // the largest bound Q_e of the chunk's k-th primitive pairs (non-increasing in k)
     int np;
     int K;                // primitive pairs per shell pair (K_a * K_b)
 };
