@@ -16,16 +16,35 @@
 
 namespace uqc {
 
+// Workgroups of a digest kernel that fit on the current device at once (occupancy x compute units, rounded down to
+// a multiple of the die count), found once per kernel; 0 if the runtime cannot tell.
+static long long resident_blocks(const void* fn) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, 0) != hipSuccess)
+        return 0;
+    return (long long)cus * per_cu / kXcds * kXcds;
+}
+
 template <bool MIXED, int NSPIN>
-static void launch_digest_one(unsigned nblocks, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
-                              long long item0, long long nitems, const double* b64, const float* b32,
+static void launch_digest_one(long long nitems_blocks, const TaskDev* d_tasks, const long long* d_task_begin,
+                              int ntask, long long item0, long long nitems, const double* b64, const float* b32,
                               const WorkRedirect& wr, hipStream_t s) {
 #if UQC_TEAM
-    hipLaunchKernelGGL((k_digest_team<UQC_LA, UQC_LB, UQC_LC, UQC_LD, MIXED, NSPIN>), dim3(nblocks), dim3(kBlock), 0,
-                       s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr);
+    const void* fn = reinterpret_cast<const void*>(&k_digest_team<UQC_LA, UQC_LB, UQC_LC, UQC_LD, MIXED, NSPIN>);
 #else
-    hipLaunchKernelGGL((k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, MIXED, NSPIN>), dim3(nblocks), dim3(kBlock), 0, s,
-                       d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr);
+    const void* fn = reinterpret_cast<const void*>(&k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, MIXED, NSPIN>);
+#endif
+    // one workgroup per four items, at most as many as are resident at once (the wavefronts then loop over items)
+    static const long long resident = resident_blocks(fn);
+    const long long nb = resident > 0 && nitems_blocks > resident ? resident : nitems_blocks;
+#if UQC_TEAM
+    hipLaunchKernelGGL((k_digest_team<UQC_LA, UQC_LB, UQC_LC, UQC_LD, MIXED, NSPIN>), dim3((unsigned)nb),
+                       dim3(kBlock), 0, s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr);
+#else
+    hipLaunchKernelGGL((k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, MIXED, NSPIN>), dim3((unsigned)nb), dim3(kBlock), 0,
+                       s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr);
 #endif
 }
 
@@ -36,13 +55,12 @@ static hipError_t launch_digest_cls(bool mixed, int nspin, const TaskDev* d_task
     const long long nblocks = (nitems + waves_per_block - 1) / waves_per_block;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    const unsigned nb = (unsigned)nblocks;
     if (nspin == 2) {
-        if (mixed) launch_digest_one<true, 2>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
-        else launch_digest_one<false, 2>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
+        if (mixed) launch_digest_one<true, 2>(nblocks, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
+        else launch_digest_one<false, 2>(nblocks, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
     } else {
-        if (mixed) launch_digest_one<true, 1>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
-        else launch_digest_one<false, 1>(nb, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
+        if (mixed) launch_digest_one<true, 1>(nblocks, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
+        else launch_digest_one<false, 1>(nblocks, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
     }
     return hipGetLastError();
 }

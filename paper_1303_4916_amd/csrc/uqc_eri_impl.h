@@ -224,14 +224,31 @@ __device__ __forceinline__ void contract_pair(const double* __restrict__ v, cons
                 }
 }
 
-// The wavefront of this lane's work item.  Workgroups are dealt to the kXcds dies round-robin (workgroup b runs on
-// die b mod kXcds); workgroup b is mapped to the (b / kXcds)-th workgroup of a contiguous share of the item list
-// owned by die b mod kXcds, so items that read the same ket chunk share one die's L2.
-__device__ __forceinline__ long long wave_item() {
+// Work items of this lane's wavefront in a launch of nitems items.  Workgroups are dealt to the kXcds dies
+// round-robin (workgroup b runs on die b mod kXcds).  The item list is cut into segments of kSegItems consecutive
+// items, dealt to the dies round-robin too, so items that read the same ket chunk mostly share one die's L2 while
+// every die gets a like mix of cheap and costly items (item costs drift along the list: a die owning one contiguous
+// share of it finished long before the others).  The wavefronts of a die's workgroups take its items in turn:
+// wavefront w of W takes local items w, w + W, w + 2W, ...  The host sizes the launch to the workgroups that fit on
+// the chip at once, so every wavefront runs many items; a workgroup keeps its LDS until its last wavefront ends,
+// and with one item per wavefront the uneven item costs left most of the LDS held by finished wavefronts.
+constexpr long long kSegItems = 256;
+struct WaveItems {
+    long long first, end, stride;  // local item range of the die and this wavefront's stride in it
+    long long die, dies;           // local item i is global item ((i / kSegItems) dies + die) kSegItems + i % kSegItems
+};
+__device__ __forceinline__ WaveItems wave_items(long long nitems) {
     const long long nb = gridDim.x, b = blockIdx.x;
-    const long long per = nb / kXcds, rem = nb % kXcds, x = b % kXcds, k = b / kXcds;
-    const long long blk = x * per + (x < rem ? x : rem) + k;
-    return blk * (kBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const long long dies = nb < kXcds ? nb : kXcds;   // dies holding workgroups
+    const long long x = b % kXcds, k = b / kXcds;
+    const long long nbx = nb / kXcds + (x < nb % kXcds ? 1 : 0);  // workgroups on die x (at least this one)
+    const long long full = nitems / kSegItems, tail = nitems % kSegItems;
+    const long long nx = (full / dies + (x < full % dies ? 1 : 0)) * kSegItems + (x == full % dies ? tail : 0);
+    const long long w = k * (kBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    return {w, nx, nbx * (kBlock / kWave), x, dies};
+}
+__device__ __forceinline__ long long global_item(const WaveItems& wi, long long i) {
+    return ((i / kSegItems) * wi.dies + wi.die) * kSegItems + i % kSegItems;
 }
 
 // Task holding launch-wide item `item` (task_begin ascending, task_begin[0] == 0).
@@ -302,246 +319,247 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
         for (int i = (int)threadIdx.x; i < BROWS * (kBoysRow / 2); i += kBlock) btab[i] = src[i];
         __syncthreads();
     }
-    const long long local = wave_item();
-    if (local >= nitems) return;
-    const long long item = item0 + local;
-    const TaskDev& tk = tasks[find_task(task_begin, ntask, item)];
-    const long long li = item - tk.item_begin;
-    const int2 it = tk.items[li];
-    const int gend = tk.items[li + 1].x;
-    const BinDev& B = tk.bra;
-    const BinDev& Kt = tk.ket;
-    const int lane = (int)(threadIdx.x % kWave);
-    const int ket = it.y * kWave + lane;
-    const bool ket_ok = ket < Kt.np;
-    const int kc = ket_ok ? ket : Kt.np - 1;
-    const double qk = Kt.Q[kc];
-    // ket primitive pairs evaluated: the most any lane's ket needs (the kets stay for the whole item)
-    const int kkn = wave_max_int(ket_ok ? Kt.kp[kc] : 1);
-    // the chunk's largest primitive bounds (it.y is loaded through a generic pointer: made wavefront-uniform)
-    const cdptr cqk = as_const(Kt.cq) + (size_t)__builtin_amdgcn_readfirstlane(it.y) * Kt.K;
-    const bool redir = NSPIN == 1 && wr.J != nullptr;  // kernel argument: wavefront-uniform
-    const double* __restrict__ D = redir ? wr.D : tk.D;
-    // D is read-only while the kernel runs: read through the constant address space with 32-bit offsets (N < 2^16)
-    const cdptr Dc = as_const(D);
-    const cdptr Dj = NSPIN == 2 ? as_const(tk.DJ) : Dc;  // density of the J pass
-    double* __restrict__ J = redir ? wr.J : tk.J;
-    double* __restrict__ K0 = redir ? wr.K : tk.K;
-    const int N = tk.nbf;
-    auto Dk = [&](int sp) { return sp == 0 ? Dc : as_const(tk.D2); };  // density of spin sp's K passes
-    auto Kp = [&](int sp) { return sp == 0 ? K0 : tk.K2; };             // its accumulator
-    // Only the ket index, its bound and the kept sums live across the loop; everything else about the ket is
-    // re-read (from cache) through an index the compiler cannot see through, which keeps register use low.
-    auto opaque = [](int x) {
-        asm volatile("" : "+v"(x));
-        return x;
-    };
-    // runs of adjacent lanes with equal first ket shell; the same shell may recur in a later, separate run (a
-    // chunk can span two decades of the ket order), so runs are told apart by their index, not by the shell
-    auto runs = [&](int oc, bool* inseg, bool& run_last) {
-        const int kprev = __shfl_up(oc, 1, kWave);
-        const bool head = lane == 0 || kprev != oc;
-        const unsigned long long heads = __ballot(head);
-        const unsigned long long upto = lane == kWave - 1 ? ~0ULL : ((1ULL << (lane + 1)) - 1ULL);
-        const int run = __popcll(heads & upto);
-#pragma unroll
-        for (int st = 0; st < 6; ++st) {
-            const int ro = __shfl_up(run, 1 << st, kWave);
-            inseg[st] = lane >= (1 << st) && ro == run;
-        }
-        run_last = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ULL);
-    };
+    const WaveItems wi = wave_items(nitems);
+    for (long long i = wi.first; i < wi.end; i += wi.stride) {
+        const long long item = item0 + global_item(wi, i);
+        const TaskDev& tk = tasks[find_task(task_begin, ntask, item)];
+        const long long li = item - tk.item_begin;
+        const int2 it = tk.items[li];
+        const int gend = tk.items[li + 1].x;
+        const BinDev& B = tk.bra;
+        const BinDev& Kt = tk.ket;
+        const int lane = (int)(threadIdx.x % kWave);
+        const int ket = it.y * kWave + lane;
+        const bool ket_ok = ket < Kt.np;
+        const int kc = ket_ok ? ket : Kt.np - 1;
+        const double qk = Kt.Q[kc];
+        // ket primitive pairs evaluated: the most any lane's ket needs (the kets stay for the whole item)
+        const int kkn = wave_max_int(ket_ok ? Kt.kp[kc] : 1);
+        // the chunk's largest primitive bounds (it.y is loaded through a generic pointer: made wavefront-uniform)
+        const cdptr cqk = as_const(Kt.cq) + (size_t)__builtin_amdgcn_readfirstlane(it.y) * Kt.K;
+        const bool redir = NSPIN == 1 && wr.J != nullptr;  // kernel argument: wavefront-uniform
+        const double* __restrict__ D = redir ? wr.D : tk.D;
+        // D is read-only while the kernel runs: read through the constant address space with 32-bit offsets (N < 2^16)
+        const cdptr Dc = as_const(D);
+        const cdptr Dj = NSPIN == 2 ? as_const(tk.DJ) : Dc;  // density of the J pass
+        double* __restrict__ J = redir ? wr.J : tk.J;
+        double* __restrict__ K0 = redir ? wr.K : tk.K;
+        const int N = tk.nbf;
+        auto Dk = [&](int sp) { return sp == 0 ? Dc : as_const(tk.D2); };  // density of spin sp's K passes
+        auto Kp = [&](int sp) { return sp == 0 ? K0 : tk.K2; };             // its accumulator
+        // Only the ket index, its bound and the kept sums live across the loop; everything else about the ket is
+        // re-read (from cache) through an index the compiler cannot see through, which keeps register use low.
+        auto opaque = [](int x) {
+            asm volatile("" : "+v"(x));
+            return x;
+        };
+        // runs of adjacent lanes with equal first ket shell; the same shell may recur in a later, separate run (a
+        // chunk can span two decades of the ket order), so runs are told apart by their index, not by the shell
+        auto runs = [&](int oc, bool* inseg, bool& run_last) {
+            const int kprev = __shfl_up(oc, 1, kWave);
+            const bool head = lane == 0 || kprev != oc;
+            const unsigned long long heads = __ballot(head);
+            const unsigned long long upto = lane == kWave - 1 ? ~0ULL : ((1ULL << (lane + 1)) - 1ULL);
+            const int run = __popcll(heads & upto);
+    #pragma unroll
+            for (int st = 0; st < 6; ++st) {
+                const int ro = __shfl_up(run, 1 << st, kWave);
+                inseg[st] = lane >= (1 << st) && ro == run;
+            }
+            run_last = lane == kWave - 1 || ((heads >> (lane + 1)) & 1ULL);
+        };
 
-    double jcd_s[NCD], kad_s[NSPIN][KAD_MODE == 1 ? NA * ND : 1], kac_s[NSPIN][KAC_MODE == 1 ? NA * NC : 1];
-#pragma unroll
-    for (int x = 0; x < NCD; ++x) jcd_s[x] = 0.0;
-#pragma unroll
-    for (int sp = 0; sp < NSPIN; ++sp) {
-#pragma unroll
-        for (int x = 0; x < (KAD_MODE == 1 ? NA * ND : 1); ++x) kad_s[sp][x] = 0.0;
-#pragma unroll
-        for (int x = 0; x < (KAC_MODE == 1 ? NA * NC : 1); ++x) kac_s[sp][x] = 0.0;
-    }
-    // LDS slots of this lane: slot x at kept[x * kWave] (lane-contiguous, no bank conflicts, private to the lane),
-    // spin sp's slots after those of the spins before it
-    double* kept0 = &slots[threadIdx.x / kWave][lane];
-#pragma unroll
-    for (int x = 0; x < SLOTS; ++x) kept0[x * kWave] = 0.0;
-    auto kad_get = [&](int sp, int x) -> double& {
-        if constexpr (KAD_MODE == 2) return kept0[(sp * SLOTS1 + x) * kWave]; else return kad_s[sp][x];
-    };
-    auto kac_get = [&](int sp, int x) -> double& {
-        if constexpr (KAC_MODE == 2) return kept0[(sp * SLOTS1 + (KAD_MODE == 2 ? NA * ND : 0) + x) * kWave];
-        else return kac_s[sp][x];
-    };
-    int cur_a = -1;  // wavefront-uniform: first shell of the bra pairs whose K_ad / K_ac sums are held
-    auto flush_a = [&]() {
-        const int kl = opaque(kc);
-        const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
-        bool inseg[6], run_last;
-        if constexpr (KEEP_KAC) runs(oc, inseg, run_last);
-#pragma unroll
+        double jcd_s[NCD], kad_s[NSPIN][KAD_MODE == 1 ? NA * ND : 1], kac_s[NSPIN][KAC_MODE == 1 ? NA * NC : 1];
+    #pragma unroll
+        for (int x = 0; x < NCD; ++x) jcd_s[x] = 0.0;
+    #pragma unroll
         for (int sp = 0; sp < NSPIN; ++sp) {
-            double* __restrict__ K = Kp(sp);
-            if constexpr (KEEP_KAD) {
-#pragma unroll
-                for (int i = 0; i < NA; ++i)
-#pragma unroll
-                    for (int l = 0; l < ND; ++l) {
-                        double& r = kad_get(sp, i * ND + l);
-                        const double s = r;
-                        r = 0.0;
-                        if (s != 0.0) atomic_add(K + (size_t)(cur_a + i) * N + od + l, s);
-                    }
-            }
-            if constexpr (KEEP_KAC) {
-#pragma unroll
-                for (int i = 0; i < NA; ++i)
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) {
-                        double& r = kac_get(sp, i * NC + k);
-                        const double s = seg_scan(r, inseg);
-                        r = 0.0;
-                        if (run_last && s != 0.0) atomic_add(K + (size_t)(cur_a + i) * N + oc + k, s);
-                    }
-            }
+    #pragma unroll
+            for (int x = 0; x < (KAD_MODE == 1 ? NA * ND : 1); ++x) kad_s[sp][x] = 0.0;
+    #pragma unroll
+            for (int x = 0; x < (KAC_MODE == 1 ? NA * NC : 1); ++x) kac_s[sp][x] = 0.0;
         }
-    };
-    unsigned long long cnt = 0, pcnt = 0;
-    for (int e = it.x; e < gend; ++e) {
-        const int bra = __builtin_amdgcn_readfirstlane(as_const(tk.blist)[e]);  // wavefront-uniform
-        const cdptr bh = as_const(B.hdr) + (size_t)bra * kHdr;  // AB, sdeg, Q, offsets of the bra pair
-        const double q = bh[4] * qk;
-        const bool act = ket_ok && ket >= as_const(tk.lo)[bra] && ket < as_const(tk.hi)[bra] && q >= tk.tau &&
-                         q > tk.lo_excl && q <= tk.hi_incl;
-        const unsigned long long live = __ballot(act);
-        if (live == 0ULL) continue;  // uniform: no quartet of this bra pair survives in the chunk
-        const int kbn = as_const(B.kp)[bra];
-        cnt += (unsigned long long)__popcll(live);
-        const int oa = ((ciptr)(bh + 5))[0], ob = ((ciptr)(bh + 5))[1];
-        if (oa != cur_a) {
-            if (cur_a >= 0) flush_a();
-            cur_a = oa;
-        }
-        const int kl = opaque(kc);
-        double out[NAB * NCD];
-        {
-            double acc[C::NACC];
-#pragma unroll
-            for (int x = 0; x < C::NACC; ++x) acc[x] = 0.0;
-            const int done = accumulate<C, MIXED, BLDS, true>(B, bra, kbn, Kt, kl, kkn, boys64tab, boys32tab, acc,
-                                                              btab, cqk);
-            pcnt += (unsigned long long)__popcll(live) * (unsigned long long)done;
-            C::hrr(acc, bh[0], bh[1], bh[2], Kt.AB[kl], Kt.AB[Kt.np + kl],
-                   Kt.AB[2 * Kt.np + kl], out);
-        }
-        const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
-        double w = act ? bh[3] * Kt.sdeg[kl] : 0.0;
-        if (tk.same && ket == bra) w *= 0.5;
-        // Digest in three passes over the block (J; K_ac with K_bd; K_ad with K_bc), so that only two density
-        // slices and two partial blocks are live at a time.
-        const double w2 = 2.0 * w;
-        {
-            double dab[NAB], dcd[NCD], jab[NAB], jcd[NCD];
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int j = 0; j < NB; ++j) dab[i * NB + j] = Dj[(unsigned)(oa + i) * (unsigned)N + (unsigned)(ob + j)];
-#pragma unroll
-            for (int k = 0; k < NC; ++k)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) dcd[k * ND + l] = Dj[(unsigned)(oc + k) * (unsigned)N + (unsigned)(od + l)];
-            contract_pair<NA, NB, NC, ND, 0>(out, dcd, dab, jab, jcd);
-#pragma unroll
-            for (int x = 0; x < NAB; ++x) {
-                const double s = wave_sum(w2 * jab[x]);
-                if (lane == 0) atomic_add(J + (size_t)(oa + x / NB) * N + ob + x % NB, s);
-            }
-#pragma unroll
-            for (int x = 0; x < NCD; ++x) jcd_s[x] = fma(w2, jcd[x], jcd_s[x]);
-        }
-        bool inseg[6], run_last;
-        runs(oc, inseg, run_last);
-#pragma unroll
-        for (int sp = 0; sp < NSPIN; ++sp) {
-            const cdptr Ds = Dk(sp);
-            double* __restrict__ K = Kp(sp);
-            {
-                double dbd[NB * ND], dac[NA * NC], kac[NA * NC], kbd[NB * ND];
-#pragma unroll
-                for (int j = 0; j < NB; ++j)
-#pragma unroll
-                    for (int l = 0; l < ND; ++l) dbd[j * ND + l] = Ds[(unsigned)(ob + j) * (unsigned)N + (unsigned)(od + l)];
-#pragma unroll
-                for (int i = 0; i < NA; ++i)
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) dac[i * NC + k] = Ds[(unsigned)(oa + i) * (unsigned)N + (unsigned)(oc + k)];
-                contract_pair<NA, NB, NC, ND, 1>(out, dbd, dac, kac, kbd);
-                if constexpr (KEEP_KAC) {
-#pragma unroll
-                    for (int x = 0; x < NA * NC; ++x) kac_get(sp, x) += w * kac[x];
-                } else {
-#pragma unroll
+        // LDS slots of this lane: slot x at kept[x * kWave] (lane-contiguous, no bank conflicts, private to the lane),
+        // spin sp's slots after those of the spins before it
+        double* kept0 = &slots[threadIdx.x / kWave][lane];
+    #pragma unroll
+        for (int x = 0; x < SLOTS; ++x) kept0[x * kWave] = 0.0;
+        auto kad_get = [&](int sp, int x) -> double& {
+            if constexpr (KAD_MODE == 2) return kept0[(sp * SLOTS1 + x) * kWave]; else return kad_s[sp][x];
+        };
+        auto kac_get = [&](int sp, int x) -> double& {
+            if constexpr (KAC_MODE == 2) return kept0[(sp * SLOTS1 + (KAD_MODE == 2 ? NA * ND : 0) + x) * kWave];
+            else return kac_s[sp][x];
+        };
+        int cur_a = -1;  // wavefront-uniform: first shell of the bra pairs whose K_ad / K_ac sums are held
+        auto flush_a = [&]() {
+            const int kl = opaque(kc);
+            const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
+            bool inseg[6], run_last;
+            if constexpr (KEEP_KAC) runs(oc, inseg, run_last);
+    #pragma unroll
+            for (int sp = 0; sp < NSPIN; ++sp) {
+                double* __restrict__ K = Kp(sp);
+                if constexpr (KEEP_KAD) {
+    #pragma unroll
                     for (int i = 0; i < NA; ++i)
-#pragma unroll
-                        for (int k = 0; k < NC; ++k) {
-                            const double s = seg_scan(w * kac[i * NC + k], inseg);
-                            if (run_last && s != 0.0) atomic_add(K + (size_t)(oa + i) * N + oc + k, s);
+    #pragma unroll
+                        for (int l = 0; l < ND; ++l) {
+                            double& r = kad_get(sp, i * ND + l);
+                            const double s = r;
+                            r = 0.0;
+                            if (s != 0.0) atomic_add(K + (size_t)(cur_a + i) * N + od + l, s);
                         }
                 }
-                if (act) {
-#pragma unroll
-                    for (int j = 0; j < NB; ++j)
-#pragma unroll
-                        for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(ob + j) * N + od + l, w * kbd[j * ND + l]);
-                }
-            }
-            {
-                double dbc[NB * NC], dad[NA * ND], kad[NA * ND], kbc[NB * NC];
-#pragma unroll
-                for (int j = 0; j < NB; ++j)
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) dbc[j * NC + k] = Ds[(unsigned)(ob + j) * (unsigned)N + (unsigned)(oc + k)];
-#pragma unroll
-                for (int i = 0; i < NA; ++i)
-#pragma unroll
-                    for (int l = 0; l < ND; ++l) dad[i * ND + l] = Ds[(unsigned)(oa + i) * (unsigned)N + (unsigned)(od + l)];
-                contract_pair<NA, NB, NC, ND, 2>(out, dbc, dad, kad, kbc);
-#pragma unroll
-                for (int j = 0; j < NB; ++j)
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) {
-                        const double s = seg_scan(w * kbc[j * NC + k], inseg);
-                        if (run_last && s != 0.0) atomic_add(K + (size_t)(ob + j) * N + oc + k, s);
-                    }
-                if constexpr (KEEP_KAD) {
-#pragma unroll
-                    for (int x = 0; x < NA * ND; ++x) kad_get(sp, x) += w * kad[x];
-                } else if (act) {
-#pragma unroll
+                if constexpr (KEEP_KAC) {
+    #pragma unroll
                     for (int i = 0; i < NA; ++i)
-#pragma unroll
-                        for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(oa + i) * N + od + l, w * kad[i * ND + l]);
+    #pragma unroll
+                        for (int k = 0; k < NC; ++k) {
+                            double& r = kac_get(sp, i * NC + k);
+                            const double s = seg_scan(r, inseg);
+                            r = 0.0;
+                            if (run_last && s != 0.0) atomic_add(K + (size_t)(cur_a + i) * N + oc + k, s);
+                        }
                 }
             }
-        }  // spins
-    }
-    if (cur_a >= 0) flush_a();
-    {
-        const int kl = opaque(kc);
-        const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
-#pragma unroll
-        for (int k = 0; k < NC; ++k)
-#pragma unroll
-            for (int l = 0; l < ND; ++l) {
-                const double s = jcd_s[k * ND + l];
-                if (s != 0.0) atomic_add(J + (size_t)(oc + k) * N + od + l, s);
+        };
+        unsigned long long cnt = 0, pcnt = 0;
+        for (int e = it.x; e < gend; ++e) {
+            const int bra = __builtin_amdgcn_readfirstlane(as_const(tk.blist)[e]);  // wavefront-uniform
+            const cdptr bh = as_const(B.hdr) + (size_t)bra * kHdr;  // AB, sdeg, Q, offsets of the bra pair
+            const double q = bh[4] * qk;
+            const bool act = ket_ok && ket >= as_const(tk.lo)[bra] && ket < as_const(tk.hi)[bra] && q >= tk.tau &&
+                             q > tk.lo_excl && q <= tk.hi_incl;
+            const unsigned long long live = __ballot(act);
+            if (live == 0ULL) continue;  // uniform: no quartet of this bra pair survives in the chunk
+            const int kbn = as_const(B.kp)[bra];
+            cnt += (unsigned long long)__popcll(live);
+            const int oa = ((ciptr)(bh + 5))[0], ob = ((ciptr)(bh + 5))[1];
+            if (oa != cur_a) {
+                if (cur_a >= 0) flush_a();
+                cur_a = oa;
             }
-    }
-    if (lane == 0 && cnt) {
-        atomicAdd(redir ? wr.count + tk.cidx : tk.count, cnt);
-        atomicAdd(redir ? wr.count + wr.ncount + tk.cidx : tk.pcount, pcnt);
-    }
+            const int kl = opaque(kc);
+            double out[NAB * NCD];
+            {
+                double acc[C::NACC];
+    #pragma unroll
+                for (int x = 0; x < C::NACC; ++x) acc[x] = 0.0;
+                const int done = accumulate<C, MIXED, BLDS, true>(B, bra, kbn, Kt, kl, kkn, boys64tab, boys32tab, acc,
+                                                                  btab, cqk);
+                pcnt += (unsigned long long)__popcll(live) * (unsigned long long)done;
+                C::hrr(acc, bh[0], bh[1], bh[2], Kt.AB[kl], Kt.AB[Kt.np + kl],
+                       Kt.AB[2 * Kt.np + kl], out);
+            }
+            const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
+            double w = act ? bh[3] * Kt.sdeg[kl] : 0.0;
+            if (tk.same && ket == bra) w *= 0.5;
+            // Digest in three passes over the block (J; K_ac with K_bd; K_ad with K_bc), so that only two density
+            // slices and two partial blocks are live at a time.
+            const double w2 = 2.0 * w;
+            {
+                double dab[NAB], dcd[NCD], jab[NAB], jcd[NCD];
+    #pragma unroll
+                for (int i = 0; i < NA; ++i)
+    #pragma unroll
+                    for (int j = 0; j < NB; ++j) dab[i * NB + j] = Dj[(unsigned)(oa + i) * (unsigned)N + (unsigned)(ob + j)];
+    #pragma unroll
+                for (int k = 0; k < NC; ++k)
+    #pragma unroll
+                    for (int l = 0; l < ND; ++l) dcd[k * ND + l] = Dj[(unsigned)(oc + k) * (unsigned)N + (unsigned)(od + l)];
+                contract_pair<NA, NB, NC, ND, 0>(out, dcd, dab, jab, jcd);
+    #pragma unroll
+                for (int x = 0; x < NAB; ++x) {
+                    const double s = wave_sum(w2 * jab[x]);
+                    if (lane == 0) atomic_add(J + (size_t)(oa + x / NB) * N + ob + x % NB, s);
+                }
+    #pragma unroll
+                for (int x = 0; x < NCD; ++x) jcd_s[x] = fma(w2, jcd[x], jcd_s[x]);
+            }
+            bool inseg[6], run_last;
+            runs(oc, inseg, run_last);
+    #pragma unroll
+            for (int sp = 0; sp < NSPIN; ++sp) {
+                const cdptr Ds = Dk(sp);
+                double* __restrict__ K = Kp(sp);
+                {
+                    double dbd[NB * ND], dac[NA * NC], kac[NA * NC], kbd[NB * ND];
+    #pragma unroll
+                    for (int j = 0; j < NB; ++j)
+    #pragma unroll
+                        for (int l = 0; l < ND; ++l) dbd[j * ND + l] = Ds[(unsigned)(ob + j) * (unsigned)N + (unsigned)(od + l)];
+    #pragma unroll
+                    for (int i = 0; i < NA; ++i)
+    #pragma unroll
+                        for (int k = 0; k < NC; ++k) dac[i * NC + k] = Ds[(unsigned)(oa + i) * (unsigned)N + (unsigned)(oc + k)];
+                    contract_pair<NA, NB, NC, ND, 1>(out, dbd, dac, kac, kbd);
+                    if constexpr (KEEP_KAC) {
+    #pragma unroll
+                        for (int x = 0; x < NA * NC; ++x) kac_get(sp, x) += w * kac[x];
+                    } else {
+    #pragma unroll
+                        for (int i = 0; i < NA; ++i)
+    #pragma unroll
+                            for (int k = 0; k < NC; ++k) {
+                                const double s = seg_scan(w * kac[i * NC + k], inseg);
+                                if (run_last && s != 0.0) atomic_add(K + (size_t)(oa + i) * N + oc + k, s);
+                            }
+                    }
+                    if (act) {
+    #pragma unroll
+                        for (int j = 0; j < NB; ++j)
+    #pragma unroll
+                            for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(ob + j) * N + od + l, w * kbd[j * ND + l]);
+                    }
+                }
+                {
+                    double dbc[NB * NC], dad[NA * ND], kad[NA * ND], kbc[NB * NC];
+    #pragma unroll
+                    for (int j = 0; j < NB; ++j)
+    #pragma unroll
+                        for (int k = 0; k < NC; ++k) dbc[j * NC + k] = Ds[(unsigned)(ob + j) * (unsigned)N + (unsigned)(oc + k)];
+    #pragma unroll
+                    for (int i = 0; i < NA; ++i)
+    #pragma unroll
+                        for (int l = 0; l < ND; ++l) dad[i * ND + l] = Ds[(unsigned)(oa + i) * (unsigned)N + (unsigned)(od + l)];
+                    contract_pair<NA, NB, NC, ND, 2>(out, dbc, dad, kad, kbc);
+    #pragma unroll
+                    for (int j = 0; j < NB; ++j)
+    #pragma unroll
+                        for (int k = 0; k < NC; ++k) {
+                            const double s = seg_scan(w * kbc[j * NC + k], inseg);
+                            if (run_last && s != 0.0) atomic_add(K + (size_t)(ob + j) * N + oc + k, s);
+                        }
+                    if constexpr (KEEP_KAD) {
+    #pragma unroll
+                        for (int x = 0; x < NA * ND; ++x) kad_get(sp, x) += w * kad[x];
+                    } else if (act) {
+    #pragma unroll
+                        for (int i = 0; i < NA; ++i)
+    #pragma unroll
+                            for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(oa + i) * N + od + l, w * kad[i * ND + l]);
+                    }
+                }
+            }  // spins
+        }
+        if (cur_a >= 0) flush_a();
+        {
+            const int kl = opaque(kc);
+            const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
+    #pragma unroll
+            for (int k = 0; k < NC; ++k)
+    #pragma unroll
+                for (int l = 0; l < ND; ++l) {
+                    const double s = jcd_s[k * ND + l];
+                    if (s != 0.0) atomic_add(J + (size_t)(oc + k) * N + od + l, s);
+                }
+        }
+        if (lane == 0 && cnt) {
+            atomicAdd(redir ? wr.count + tk.cidx : tk.count, cnt);
+            atomicAdd(redir ? wr.count + wr.ncount + tk.cidx : tk.pcount, pcnt);
+        }
+    }  // items
 }
 
 template <int LA, int LB, int LC, int LD, bool MIXED, int MODE>

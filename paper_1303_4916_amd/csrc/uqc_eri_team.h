@@ -216,232 +216,234 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
     constexpr int WAVE_LDS = (kTeamsPerWave + 1) * RS;
     __shared__ double lds[kBlock / kWave][WAVE_LDS];
 
-    const long long local = wave_item();
-    if (local >= nitems) return;
-    const long long item = item0 + local;
-    const int wid = (int)(threadIdx.x / kWave);
-    const int lane = (int)(threadIdx.x % kWave);
-    const TaskDev& tk = tasks[find_task(task_begin, ntask, item)];
-    const long long li = item - tk.item_begin;
-    const int2 it = tk.items[li];
-    const int gend = tk.items[li + 1].x;
-    const BinDev& B = tk.bra;
-    const BinDev& Kt = tk.ket;
-    const int team = lane / kTeam;
-    const int ket = it.y * kTeamsPerWave + team;
-    const bool ket_ok = team < kTeamsPerWave && ket < Kt.np;
-    const int kc = ket_ok ? ket : Kt.np - 1;  // idle teams compute a valid quartet with weight 0
-    const double qk = Kt.Q[kc];
-    // ket primitive pairs evaluated: the most any team's ket needs (the kets stay for the whole item)
-    const int kkn = wave_max_int(ket_ok ? Kt.kp[kc] : 1);
-    // largest primitive bounds of the 64-pair chunks that hold the item's kets (one or two)
-    const int kfirst = __builtin_amdgcn_readfirstlane(it.y) * kTeamsPerWave, klast = min(kfirst + kTeamsPerWave, Kt.np) - 1;
-    const cdptr cq0 = as_const(Kt.cq) + (size_t)(kfirst / kWave) * Kt.K;
-    const cdptr cq1 = as_const(Kt.cq) + (size_t)(klast / kWave) * Kt.K;
-    const bool redir = NSPIN == 1 && wr.J != nullptr;  // kernel argument: wavefront-uniform
-    const double* __restrict__ D = redir ? wr.D : tk.D;
-    // D is read-only while the kernel runs: read through the constant address space with 32-bit offsets (N < 2^16)
-    const cdptr Dc = as_const(D);
-    const cdptr Dj = NSPIN == 2 ? as_const(tk.DJ) : Dc;  // density of the J pass
-    double* __restrict__ J = redir ? wr.J : tk.J;
-    double* __restrict__ K0 = redir ? wr.K : tk.K;
-    const int N = tk.nbf;
-    auto Dk = [&](int sp) { return sp == 0 ? Dc : as_const(tk.D2); };  // density of spin sp's K passes
-    auto Kp = [&](int sp) { return sp == 0 ? K0 : tk.K2; };             // its accumulator
-    // Only the ket index and its bound live across the loop; the ket's data, the lane's permutation tables and
-    // the density blocks are re-read per bra pair through values the compiler cannot see through, which keeps
-    // register use (and spills) down.
-    auto opaque = [](int x) {
-        asm volatile("" : "+v"(x));
-        return x;
-    };
+    const WaveItems wi = wave_items(nitems);
+    for (long long i = wi.first; i < wi.end; i += wi.stride) {
+        const long long item = item0 + global_item(wi, i);
+        const int wid = (int)(threadIdx.x / kWave);
+        const int lane = (int)(threadIdx.x % kWave);
+        const TaskDev& tk = tasks[find_task(task_begin, ntask, item)];
+        const long long li = item - tk.item_begin;
+        const int2 it = tk.items[li];
+        const int gend = tk.items[li + 1].x;
+        const BinDev& B = tk.bra;
+        const BinDev& Kt = tk.ket;
+        const int team = lane / kTeam;
+        const int ket = it.y * kTeamsPerWave + team;
+        const bool ket_ok = team < kTeamsPerWave && ket < Kt.np;
+        const int kc = ket_ok ? ket : Kt.np - 1;  // idle teams compute a valid quartet with weight 0
+        const double qk = Kt.Q[kc];
+        // ket primitive pairs evaluated: the most any team's ket needs (the kets stay for the whole item)
+        const int kkn = wave_max_int(ket_ok ? Kt.kp[kc] : 1);
+        // largest primitive bounds of the 64-pair chunks that hold the item's kets (one or two)
+        const int kfirst = __builtin_amdgcn_readfirstlane(it.y) * kTeamsPerWave, klast = min(kfirst + kTeamsPerWave, Kt.np) - 1;
+        const cdptr cq0 = as_const(Kt.cq) + (size_t)(kfirst / kWave) * Kt.K;
+        const cdptr cq1 = as_const(Kt.cq) + (size_t)(klast / kWave) * Kt.K;
+        const bool redir = NSPIN == 1 && wr.J != nullptr;  // kernel argument: wavefront-uniform
+        const double* __restrict__ D = redir ? wr.D : tk.D;
+        // D is read-only while the kernel runs: read through the constant address space with 32-bit offsets (N < 2^16)
+        const cdptr Dc = as_const(D);
+        const cdptr Dj = NSPIN == 2 ? as_const(tk.DJ) : Dc;  // density of the J pass
+        double* __restrict__ J = redir ? wr.J : tk.J;
+        double* __restrict__ K0 = redir ? wr.K : tk.K;
+        const int N = tk.nbf;
+        auto Dk = [&](int sp) { return sp == 0 ? Dc : as_const(tk.D2); };  // density of spin sp's K passes
+        auto Kp = [&](int sp) { return sp == 0 ? K0 : tk.K2; };             // its accumulator
+        // Only the ket index and its bound live across the loop; the ket's data, the lane's permutation tables and
+        // the density blocks are re-read per bra pair through values the compiler cannot see through, which keeps
+        // register use (and spills) down.
+        auto opaque = [](int x) {
+            asm volatile("" : "+v"(x));
+            return x;
+        };
 
-    double* my = &lds[wid][0];
-    for (int x = lane; x < WAVE_LDS; x += kWave) my[x] = 0.0;
-    wave_lds_sync();
-    double* tm = my + team * RS;
-    // flush of the team's partial sums in [e0, e1) of its LDS block (each entry by one lane of the team), then zero;
-    // the range lies inside J_cd or inside one spin's K blocks (spin sp: offsets shifted by sp * KSZ)
-    auto flush = [&](int e0, int e1, int oa, int ob, int sp) {
-        const int kl = opaque(kc);
-        const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
-        double* __restrict__ K = Kp(sp);
-        const int sh = sp * KSZ;
-        if (team < kTeamsPerWave) {
-            for (int e = e0 + lane - team * kTeam; e < e1; e += kTeam) {
-                const double s = tm[e];
-                tm[e] = 0.0;
-                if (s == 0.0) continue;
-                const int u = e - sh;
-                if (e < R_KAC) atomic_add(J + (size_t)(oc + e / ND) * N + od + e % ND, 2.0 * s);
-                else if (u < R_KAD) atomic_add(K + (size_t)(oa + (u - R_KAC) / NC) * N + oc + (u - R_KAC) % NC, s);
-                else if (u < R_KBC) atomic_add(K + (size_t)(oa + (u - R_KAD) / ND) * N + od + (u - R_KAD) % ND, s);
-                else if (u < R_KBD) atomic_add(K + (size_t)(ob + (u - R_KBC) / NC) * N + oc + (u - R_KBC) % NC, s);
-                else atomic_add(K + (size_t)(ob + (u - R_KBD) / ND) * N + od + (u - R_KBD) % ND, s);
-            }
-        }
-    };
-    int cur_a = -1;  // wavefront-uniform: first shell of the bra pairs whose K_ac / K_ad sums are held in LDS
-    unsigned long long cnt = 0, pcnt = 0;
-    for (int e = it.x; e < gend; ++e) {
-        const int bra = __builtin_amdgcn_readfirstlane(as_const(tk.blist)[e]);  // wavefront-uniform
-        const cdptr bh = as_const(B.hdr) + (size_t)bra * kHdr;  // AB, sdeg, Q, offsets of the bra pair
-        const double q = bh[4] * qk;
-        const bool act = ket_ok && ket >= as_const(tk.lo)[bra] && ket < as_const(tk.hi)[bra] && q >= tk.tau &&
-                         q > tk.lo_excl && q <= tk.hi_incl;
-        const unsigned long long live = __ballot(act);
-        if (live == 0ULL) continue;
-        const int kbn = as_const(B.kp)[bra];
-        cnt += (unsigned long long)(__popcll(live) / kTeam);
-        const int oa = ((ciptr)(bh + 5))[0], ob = ((ciptr)(bh + 5))[1];
-        if (oa != cur_a) {
-            if (cur_a >= 0) {
-#pragma unroll
-                for (int sp = 0; sp < NSPIN; ++sp) flush(R_KAC + sp * KSZ, R_KBC + sp * KSZ, cur_a, 0, sp);
-                wave_lds_sync();
-            }
-            cur_a = oa;
-        }
-        const int kl = opaque(kc);
-        const int pidx = opaque(lane - team * kTeam);
-        const int q0 = kPermAxes[pidx][0], q1 = kPermAxes[pidx][1], q2 = kPermAxes[pidx][2];
-        double acc[TC::NREP];
-#pragma unroll
-        for (int x = 0; x < TC::NREP; ++x) acc[x] = 0.0;
-        const int done = team_accumulate<TC, MIXED>(B, bra, kbn, Kt, kl, kkn, q0, q1, q2, boys64tab, boys32tab, acc,
-                                                    cq0, cq1);
-        pcnt += (unsigned long long)(__popcll(live) / kTeam) * (unsigned long long)done;
-
-        int src[kTeam];
-#pragma unroll
-        for (int x = 0; x < kTeam; ++x) src[x] = team * kTeam + kPermCompose[pidx][x];
-        int pcA[NA], pcB[NB], pcC[NC], pcD[ND];
-#pragma unroll
-        for (int k = 0; k < NA; ++k) pcA[k] = kPermComp[LA][pidx][k];
-#pragma unroll
-        for (int k = 0; k < NB; ++k) pcB[k] = kPermComp[LB][pidx][k];
-#pragma unroll
-        for (int k = 0; k < NC; ++k) pcC[k] = kPermComp[LC][pidx][k];
-#pragma unroll
-        for (int k = 0; k < ND; ++k) pcD[k] = kPermComp[LD][pidx][k];
-        const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
-        double w = act ? bh[3] * Kt.sdeg[kl] : 0.0;
-        if (tk.same && ket == bra) w *= 0.5;
-        if constexpr (TC::STREAM) {
-            team_digest_stream<TC, LA, LB, LC, LD, true>(acc, src, pidx, w, bh, Kt, kl, q0, q1, q2, Dj, Dc, N, oa, ob,
-                                                         oc, od, pcA, pcB, pcC, pcD, tm + R_JAB, tm + R_JCD,
-                                                         tm + R_KAC, tm + R_KAD, tm + R_KBC, tm + R_KBD);
-            if constexpr (NSPIN == 2)
-                team_digest_stream<TC, LA, LB, LC, LD, false>(acc, src, pidx, w, bh, Kt, kl, q0, q1, q2, Dj,
-                                                              as_const(tk.D2), N, oa, ob, oc, od, pcA, pcB, pcC, pcD,
-                                                              tm + R_JAB, tm + R_JCD, tm + R_KAC + KSZ,
-                                                              tm + R_KAD + KSZ, tm + R_KBC + KSZ, tm + R_KBD + KSZ);
-        } else {
-        double out[TC::NOUT];
-        {
-            const double ABx = sel3(bh[0], bh[1], bh[2], q0);
-            const double ABy = sel3(bh[0], bh[1], bh[2], q1);
-            const double ABz = sel3(bh[0], bh[1], bh[2], q2);
-            const double CDx = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q0);
-            const double CDy = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q1);
-            const double CDz = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q2);
-            TC::hrr(acc, src, pidx, w, ABx, ABy, ABz, CDx, CDy, CDz, out);
-        }
-        // Digest in three passes (J_ab with J_cd; K_ac with K_bd; K_ad with K_bc), each gathering its two density
-        // slices in the lane's frame and adding its two partial blocks into LDS at the true component indices.
-        auto Dq = [&](int r, int c) { return Dj[(unsigned)r * (unsigned)N + (unsigned)c]; };
-        {
-            double d1[NCD], d2[NAB], x[NAB], y[NCD];
-#pragma unroll
-            for (int k = 0; k < NC; ++k)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) d1[k * ND + l] = Dq(oc + pcC[k], od + pcD[l]);
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int j = 0; j < NB; ++j) d2[i * NB + j] = Dq(oa + pcA[i], ob + pcB[j]);
-            TC::digest0(out, d1, d2, x, y);
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int j = 0; j < NB; ++j) atomic_add_lds(tm + R_JAB + pcA[i] * NB + pcB[j], x[i * NB + j]);
-#pragma unroll
-            for (int k = 0; k < NC; ++k)
-#pragma unroll
-                for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_JCD + pcC[k] * ND + pcD[l], y[k * ND + l]);
-        }
-#pragma unroll
-        for (int sp = 0; sp < NSPIN; ++sp) {
-            const cdptr Dsp = Dk(sp);
-            auto Ds = [&](int r, int c) { return Dsp[(unsigned)r * (unsigned)N + (unsigned)c]; };
+        double* my = &lds[wid][0];
+        for (int x = lane; x < WAVE_LDS; x += kWave) my[x] = 0.0;
+        wave_lds_sync();
+        double* tm = my + team * RS;
+        // flush of the team's partial sums in [e0, e1) of its LDS block (each entry by one lane of the team), then zero;
+        // the range lies inside J_cd or inside one spin's K blocks (spin sp: offsets shifted by sp * KSZ)
+        auto flush = [&](int e0, int e1, int oa, int ob, int sp) {
+            const int kl = opaque(kc);
+            const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
+            double* __restrict__ K = Kp(sp);
             const int sh = sp * KSZ;
+            if (team < kTeamsPerWave) {
+                for (int e = e0 + lane - team * kTeam; e < e1; e += kTeam) {
+                    const double s = tm[e];
+                    tm[e] = 0.0;
+                    if (s == 0.0) continue;
+                    const int u = e - sh;
+                    if (e < R_KAC) atomic_add(J + (size_t)(oc + e / ND) * N + od + e % ND, 2.0 * s);
+                    else if (u < R_KAD) atomic_add(K + (size_t)(oa + (u - R_KAC) / NC) * N + oc + (u - R_KAC) % NC, s);
+                    else if (u < R_KBC) atomic_add(K + (size_t)(oa + (u - R_KAD) / ND) * N + od + (u - R_KAD) % ND, s);
+                    else if (u < R_KBD) atomic_add(K + (size_t)(ob + (u - R_KBC) / NC) * N + oc + (u - R_KBC) % NC, s);
+                    else atomic_add(K + (size_t)(ob + (u - R_KBD) / ND) * N + od + (u - R_KBD) % ND, s);
+                }
+            }
+        };
+        int cur_a = -1;  // wavefront-uniform: first shell of the bra pairs whose K_ac / K_ad sums are held in LDS
+        unsigned long long cnt = 0, pcnt = 0;
+        for (int e = it.x; e < gend; ++e) {
+            const int bra = __builtin_amdgcn_readfirstlane(as_const(tk.blist)[e]);  // wavefront-uniform
+            const cdptr bh = as_const(B.hdr) + (size_t)bra * kHdr;  // AB, sdeg, Q, offsets of the bra pair
+            const double q = bh[4] * qk;
+            const bool act = ket_ok && ket >= as_const(tk.lo)[bra] && ket < as_const(tk.hi)[bra] && q >= tk.tau &&
+                             q > tk.lo_excl && q <= tk.hi_incl;
+            const unsigned long long live = __ballot(act);
+            if (live == 0ULL) continue;
+            const int kbn = as_const(B.kp)[bra];
+            cnt += (unsigned long long)(__popcll(live) / kTeam);
+            const int oa = ((ciptr)(bh + 5))[0], ob = ((ciptr)(bh + 5))[1];
+            if (oa != cur_a) {
+                if (cur_a >= 0) {
+    #pragma unroll
+                    for (int sp = 0; sp < NSPIN; ++sp) flush(R_KAC + sp * KSZ, R_KBC + sp * KSZ, cur_a, 0, sp);
+                    wave_lds_sync();
+                }
+                cur_a = oa;
+            }
+            const int kl = opaque(kc);
+            const int pidx = opaque(lane - team * kTeam);
+            const int q0 = kPermAxes[pidx][0], q1 = kPermAxes[pidx][1], q2 = kPermAxes[pidx][2];
+            double acc[TC::NREP];
+    #pragma unroll
+            for (int x = 0; x < TC::NREP; ++x) acc[x] = 0.0;
+            const int done = team_accumulate<TC, MIXED>(B, bra, kbn, Kt, kl, kkn, q0, q1, q2, boys64tab, boys32tab, acc,
+                                                        cq0, cq1);
+            pcnt += (unsigned long long)(__popcll(live) / kTeam) * (unsigned long long)done;
+
+            int src[kTeam];
+    #pragma unroll
+            for (int x = 0; x < kTeam; ++x) src[x] = team * kTeam + kPermCompose[pidx][x];
+            int pcA[NA], pcB[NB], pcC[NC], pcD[ND];
+    #pragma unroll
+            for (int k = 0; k < NA; ++k) pcA[k] = kPermComp[LA][pidx][k];
+    #pragma unroll
+            for (int k = 0; k < NB; ++k) pcB[k] = kPermComp[LB][pidx][k];
+    #pragma unroll
+            for (int k = 0; k < NC; ++k) pcC[k] = kPermComp[LC][pidx][k];
+    #pragma unroll
+            for (int k = 0; k < ND; ++k) pcD[k] = kPermComp[LD][pidx][k];
+            const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
+            double w = act ? bh[3] * Kt.sdeg[kl] : 0.0;
+            if (tk.same && ket == bra) w *= 0.5;
+            if constexpr (TC::STREAM) {
+                team_digest_stream<TC, LA, LB, LC, LD, true>(acc, src, pidx, w, bh, Kt, kl, q0, q1, q2, Dj, Dc, N, oa, ob,
+                                                             oc, od, pcA, pcB, pcC, pcD, tm + R_JAB, tm + R_JCD,
+                                                             tm + R_KAC, tm + R_KAD, tm + R_KBC, tm + R_KBD);
+                if constexpr (NSPIN == 2)
+                    team_digest_stream<TC, LA, LB, LC, LD, false>(acc, src, pidx, w, bh, Kt, kl, q0, q1, q2, Dj,
+                                                                  as_const(tk.D2), N, oa, ob, oc, od, pcA, pcB, pcC, pcD,
+                                                                  tm + R_JAB, tm + R_JCD, tm + R_KAC + KSZ,
+                                                                  tm + R_KAD + KSZ, tm + R_KBC + KSZ, tm + R_KBD + KSZ);
+            } else {
+            double out[TC::NOUT];
             {
-                double d1[NB * ND], d2[NA * NC], x[NA * NC], y[NB * ND];
-#pragma unroll
-                for (int j = 0; j < NB; ++j)
-#pragma unroll
-                    for (int l = 0; l < ND; ++l) d1[j * ND + l] = Ds(ob + pcB[j], od + pcD[l]);
-#pragma unroll
-                for (int i = 0; i < NA; ++i)
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) d2[i * NC + k] = Ds(oa + pcA[i], oc + pcC[k]);
-                TC::digest1(out, d1, d2, x, y);
-#pragma unroll
-                for (int i = 0; i < NA; ++i)
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KAC + sh + pcA[i] * NC + pcC[k], x[i * NC + k]);
-#pragma unroll
-                for (int j = 0; j < NB; ++j)
-#pragma unroll
-                    for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KBD + sh + pcB[j] * ND + pcD[l], y[j * ND + l]);
+                const double ABx = sel3(bh[0], bh[1], bh[2], q0);
+                const double ABy = sel3(bh[0], bh[1], bh[2], q1);
+                const double ABz = sel3(bh[0], bh[1], bh[2], q2);
+                const double CDx = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q0);
+                const double CDy = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q1);
+                const double CDz = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q2);
+                TC::hrr(acc, src, pidx, w, ABx, ABy, ABz, CDx, CDy, CDz, out);
             }
+            // Digest in three passes (J_ab with J_cd; K_ac with K_bd; K_ad with K_bc), each gathering its two density
+            // slices in the lane's frame and adding its two partial blocks into LDS at the true component indices.
+            auto Dq = [&](int r, int c) { return Dj[(unsigned)r * (unsigned)N + (unsigned)c]; };
             {
-                double d1[NB * NC], d2[NA * ND], x[NA * ND], y[NB * NC];
-#pragma unroll
-                for (int j = 0; j < NB; ++j)
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) d1[j * NC + k] = Ds(ob + pcB[j], oc + pcC[k]);
-#pragma unroll
+                double d1[NCD], d2[NAB], x[NAB], y[NCD];
+    #pragma unroll
+                for (int k = 0; k < NC; ++k)
+    #pragma unroll
+                    for (int l = 0; l < ND; ++l) d1[k * ND + l] = Dq(oc + pcC[k], od + pcD[l]);
+    #pragma unroll
                 for (int i = 0; i < NA; ++i)
-#pragma unroll
-                    for (int l = 0; l < ND; ++l) d2[i * ND + l] = Ds(oa + pcA[i], od + pcD[l]);
-                TC::digest2(out, d1, d2, x, y);
-#pragma unroll
+    #pragma unroll
+                    for (int j = 0; j < NB; ++j) d2[i * NB + j] = Dq(oa + pcA[i], ob + pcB[j]);
+                TC::digest0(out, d1, d2, x, y);
+    #pragma unroll
                 for (int i = 0; i < NA; ++i)
-#pragma unroll
-                    for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KAD + sh + pcA[i] * ND + pcD[l], x[i * ND + l]);
-#pragma unroll
-                for (int j = 0; j < NB; ++j)
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KBC + sh + pcB[j] * NC + pcC[k], y[j * NC + k]);
+    #pragma unroll
+                    for (int j = 0; j < NB; ++j) atomic_add_lds(tm + R_JAB + pcA[i] * NB + pcB[j], x[i * NB + j]);
+    #pragma unroll
+                for (int k = 0; k < NC; ++k)
+    #pragma unroll
+                    for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_JCD + pcC[k] * ND + pcD[l], y[k * ND + l]);
             }
-        }  // spins
-        }
-        wave_lds_sync();
-        // J_ab by the wavefront and the K_bc / K_bd blocks of this bra pair by each team, then cleared
-        if (lane < NAB) {
-            double s = 0.0;
-#pragma unroll
-            for (int t = 0; t < kTeamsPerWave; ++t) {
-                s += my[t * RS + R_JAB + lane];
-                my[t * RS + R_JAB + lane] = 0.0;
+    #pragma unroll
+            for (int sp = 0; sp < NSPIN; ++sp) {
+                const cdptr Dsp = Dk(sp);
+                auto Ds = [&](int r, int c) { return Dsp[(unsigned)r * (unsigned)N + (unsigned)c]; };
+                const int sh = sp * KSZ;
+                {
+                    double d1[NB * ND], d2[NA * NC], x[NA * NC], y[NB * ND];
+    #pragma unroll
+                    for (int j = 0; j < NB; ++j)
+    #pragma unroll
+                        for (int l = 0; l < ND; ++l) d1[j * ND + l] = Ds(ob + pcB[j], od + pcD[l]);
+    #pragma unroll
+                    for (int i = 0; i < NA; ++i)
+    #pragma unroll
+                        for (int k = 0; k < NC; ++k) d2[i * NC + k] = Ds(oa + pcA[i], oc + pcC[k]);
+                    TC::digest1(out, d1, d2, x, y);
+    #pragma unroll
+                    for (int i = 0; i < NA; ++i)
+    #pragma unroll
+                        for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KAC + sh + pcA[i] * NC + pcC[k], x[i * NC + k]);
+    #pragma unroll
+                    for (int j = 0; j < NB; ++j)
+    #pragma unroll
+                        for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KBD + sh + pcB[j] * ND + pcD[l], y[j * ND + l]);
+                }
+                {
+                    double d1[NB * NC], d2[NA * ND], x[NA * ND], y[NB * NC];
+    #pragma unroll
+                    for (int j = 0; j < NB; ++j)
+    #pragma unroll
+                        for (int k = 0; k < NC; ++k) d1[j * NC + k] = Ds(ob + pcB[j], oc + pcC[k]);
+    #pragma unroll
+                    for (int i = 0; i < NA; ++i)
+    #pragma unroll
+                        for (int l = 0; l < ND; ++l) d2[i * ND + l] = Ds(oa + pcA[i], od + pcD[l]);
+                    TC::digest2(out, d1, d2, x, y);
+    #pragma unroll
+                    for (int i = 0; i < NA; ++i)
+    #pragma unroll
+                        for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KAD + sh + pcA[i] * ND + pcD[l], x[i * ND + l]);
+    #pragma unroll
+                    for (int j = 0; j < NB; ++j)
+    #pragma unroll
+                        for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KBC + sh + pcB[j] * NC + pcC[k], y[j * NC + k]);
+                }
+            }  // spins
             }
-            if (s != 0.0) atomic_add(J + (size_t)(oa + lane / NB) * N + ob + lane % NB, 2.0 * s);
+            wave_lds_sync();
+            // J_ab by the wavefront and the K_bc / K_bd blocks of this bra pair by each team, then cleared
+            if (lane < NAB) {
+                double s = 0.0;
+    #pragma unroll
+                for (int t = 0; t < kTeamsPerWave; ++t) {
+                    s += my[t * RS + R_JAB + lane];
+                    my[t * RS + R_JAB + lane] = 0.0;
+                }
+                if (s != 0.0) atomic_add(J + (size_t)(oa + lane / NB) * N + ob + lane % NB, 2.0 * s);
+            }
+    #pragma unroll
+            for (int sp = 0; sp < NSPIN; ++sp)
+                flush(R_KBC + sp * KSZ, R_KBC + sp * KSZ + NB * NC + NB * ND, oa, ob, sp);
+            wave_lds_sync();
         }
-#pragma unroll
-        for (int sp = 0; sp < NSPIN; ++sp)
-            flush(R_KBC + sp * KSZ, R_KBC + sp * KSZ + NB * NC + NB * ND, oa, ob, sp);
-        wave_lds_sync();
-    }
-    if (cur_a >= 0) {
-        flush(R_JCD, R_KAC, cur_a, 0, 0);
-#pragma unroll
-        for (int sp = 0; sp < NSPIN; ++sp) flush(R_KAC + sp * KSZ, R_KBC + sp * KSZ, cur_a, 0, sp);
-    }
-    if (lane == 0 && cnt) {
-        atomicAdd(redir ? wr.count + tk.cidx : tk.count, cnt);
-        atomicAdd(redir ? wr.count + wr.ncount + tk.cidx : tk.pcount, pcnt);
-    }
+        if (cur_a >= 0) {
+            flush(R_JCD, R_KAC, cur_a, 0, 0);
+    #pragma unroll
+            for (int sp = 0; sp < NSPIN; ++sp) flush(R_KAC + sp * KSZ, R_KBC + sp * KSZ, cur_a, 0, sp);
+        }
+        if (lane == 0 && cnt) {
+            atomicAdd(redir ? wr.count + tk.cidx : tk.count, cnt);
+            atomicAdd(redir ? wr.count + wr.ncount + tk.cidx : tk.pcount, pcnt);
+        }
+        wave_lds_sync();  // the next item clears the wavefront's LDS blocks
+    }  // items
 }
 
 }  // namespace uqc
