@@ -158,8 +158,9 @@ uqc_status uqc_fock_build(uqc_basis* b, const double* D, double* J, double* K, d
  * into a HIP graph, tight serving loops, harnesses that forbid allocation).  Same arguments, results and errors as
  * uqc_fock_build for a closed-shell build, with these limits:
  *   - D, J, K, G are device pointers on the context's device (host pointers: UQC_E_ARG);
- *   - the scaled density, the J and K accumulators, the scalars and the per-task counters live in a fixed device
- *     array of the library (25.7 MB per device, held until the process ends) instead of the basis's workspace, so
+ *   - the scaled density, the J and K accumulators, the scalars, the per-task counters and the item counters of the
+ *     class launches live in a fixed device array of the library (25.7 MB per device, held until the process ends)
+ *     instead of the basis's workspace and plan, so
  *     the basis has at most 1024 basis functions (else UQC_E_ARG);
  *   - the screening plan for (opts->schwarz_tau, opts->precision, opts->fp64_bound) must already exist on this
  *     basis: an earlier uqc_fock_build with the same three options makes it (else UQC_E_ARG);

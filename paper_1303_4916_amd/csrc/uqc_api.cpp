@@ -924,6 +924,7 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
     size_t bytes = 0;
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     bytes += align(2 * tasks.size() * sizeof(unsigned long long));
+    bytes += align(gkeys.size() * kQueueWords * sizeof(unsigned));
     for (auto& t : tasks) {
         const size_t n = B->bins[t.X].np;
         bytes += align(n * sizeof(int)) * 2 + align(t.blist.size() * sizeof(int)) + align(t.items.size() * sizeof(int));
@@ -940,6 +941,8 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
     plan.d_count = (unsigned long long*)dbase;  // [ntasks] quartets, then [ntasks] primitive quartets
     plan.h_count.assign(2 * tasks.size(), 0);
     pos += align(2 * tasks.size() * sizeof(unsigned long long));
+    plan.d_queue = (unsigned*)(dbase + pos);  // [groups][kQueueWords] item counters of each group's launches
+    pos += align(gkeys.size() * kQueueWords * sizeof(unsigned));
     std::vector<TaskDev> tdev(tasks.size());
     for (size_t oi = 0; oi < order.size(); ++oi) {
         const int ti = order[oi];
@@ -1308,8 +1311,10 @@ uqc_status uqc::fock_run(uqc_basis* B, int nspin, const double* const* Din, doub
             const int cid = la * 1000 + lb * 100 + lc * 10 + ld + (g.mixed ? 10000 : 0);
             for (long long i0 = 0; i0 < g.nitems; i0 += max_items) {
                 const long long n = std::min(max_items, g.nitems - i0);
+                // a group's launches share its queue (they run in order on one stream)
+                unsigned* q = ws ? ws->queue : plan->d_queue + gi * kQueueWords;
                 UQC_HIP(launch_digest(g.cls, g.mixed, nspin, g.d_tasks, g.d_begin, g.ntask, i0, n, ctx->boys64,
-                                      ctx->boys32, wr, gs));
+                                      ctx->boys32, wr, q, gs));
                 if (o.progress && nst == 1) {
                     UQC_HIP(hipStreamSynchronize(gs));
                     o.progress(o.progress_user, cid, i0 + n, g.nitems);

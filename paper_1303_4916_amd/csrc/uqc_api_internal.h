@@ -90,6 +90,7 @@ struct Plan {
     double flops = 0;
     int ntasks = 0;
     unsigned long long* d_count = nullptr;         // [2 ntasks] per-task quartet, then primitive-quartet counters
+    unsigned* d_queue = nullptr;                   // [groups][kQueueWords] item counters of each group's launches
     std::vector<unsigned long long> h_count;
     void* d_mem = nullptr;
     size_t bytes = 0;                              // device bytes of d_mem
@@ -141,7 +142,8 @@ uqc::Plan* find_plan(uqc_basis* B, double tau, int prec, double bound);
 
 namespace uqc {
 // A caller-chosen device workspace for a closed-shell Fock build: D' (nbf^2), the J and K accumulators (nbf^2 each),
-// 8 scalars and 2 max_tasks counters.
+// 8 scalars, 2 max_tasks counters and the kQueueWords item counters of the class launches (which run one after
+// another).
 struct FockWorkspace {
     double* Dp;
     double* J;
@@ -149,6 +151,7 @@ struct FockWorkspace {
     double* scal;
     unsigned long long* count;
     int max_tasks;
+    unsigned* queue;
 };
 // The Fock build behind uqc_fock_build (nspin = 1: Din = {D}, out = {J, K, G}) and uqc_fock_build_uhf (nspin = 2:
 // Din = {Da, Db}, out = {J, Ka, Kb, Ga, Gb}).  ws == nullptr: the basis's workspace, the plan made on first use.

@@ -30,7 +30,7 @@ static long long resident_blocks(const void* fn) {
 template <bool MIXED, int NSPIN>
 static void launch_digest_one(long long nitems_blocks, const TaskDev* d_tasks, const long long* d_task_begin,
                               int ntask, long long item0, long long nitems, const double* b64, const float* b32,
-                              const WorkRedirect& wr, hipStream_t s) {
+                              const WorkRedirect& wr, unsigned* queue, hipStream_t s) {
 #if UQC_TEAM
     const void* fn = reinterpret_cast<const void*>(&k_digest_team<UQC_LA, UQC_LB, UQC_LC, UQC_LD, MIXED, NSPIN>);
 #else
@@ -41,26 +41,30 @@ static void launch_digest_one(long long nitems_blocks, const TaskDev* d_tasks, c
     const long long nb = resident > 0 && nitems_blocks > resident ? resident : nitems_blocks;
 #if UQC_TEAM
     hipLaunchKernelGGL((k_digest_team<UQC_LA, UQC_LB, UQC_LC, UQC_LD, MIXED, NSPIN>), dim3((unsigned)nb),
-                       dim3(kBlock), 0, s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr);
+                       dim3(kBlock), 0, s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, queue);
 #else
     hipLaunchKernelGGL((k_digest<UQC_LA, UQC_LB, UQC_LC, UQC_LD, MIXED, NSPIN>), dim3((unsigned)nb), dim3(kBlock), 0,
-                       s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr);
+                       s, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, queue);
 #endif
 }
 
 static hipError_t launch_digest_cls(bool mixed, int nspin, const TaskDev* d_tasks, const long long* d_task_begin,
                                     int ntask, long long item0, long long nitems, const double* b64, const float* b32,
-                                    const WorkRedirect& wr, hipStream_t s) {
+                                    const WorkRedirect& wr, unsigned* queue, hipStream_t s) {
     const long long waves_per_block = kBlock / kWave;
     const long long nblocks = (nitems + waves_per_block - 1) / waves_per_block;
     if (nblocks <= 0) return hipSuccess;
     if (nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
     if (nspin == 2) {
-        if (mixed) launch_digest_one<true, 2>(nblocks, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
-        else launch_digest_one<false, 2>(nblocks, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
+        if (mixed) launch_digest_one<true, 2>(nblocks, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, queue,
+                                               s);
+        else launch_digest_one<false, 2>(nblocks, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, queue,
+                                          s);
     } else {
-        if (mixed) launch_digest_one<true, 1>(nblocks, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
-        else launch_digest_one<false, 1>(nblocks, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, s);
+        if (mixed) launch_digest_one<true, 1>(nblocks, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, queue,
+                                               s);
+        else launch_digest_one<false, 1>(nblocks, d_tasks, d_task_begin, ntask, item0, nitems, b64, b32, wr, queue,
+                                          s);
     }
     return hipGetLastError();
 }

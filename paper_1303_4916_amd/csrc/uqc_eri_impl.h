@@ -224,31 +224,38 @@ __device__ __forceinline__ void contract_pair(const double* __restrict__ v, cons
                 }
 }
 
-// Work items of this lane's wavefront in a launch of nitems items.  Workgroups are dealt to the kXcds dies
-// round-robin (workgroup b runs on die b mod kXcds).  The item list is cut into segments of kSegItems consecutive
-// items, dealt to the dies round-robin too, so items that read the same ket chunk mostly share one die's L2 while
-// every die gets a like mix of cheap and costly items (item costs drift along the list: a die owning one contiguous
-// share of it finished long before the others).  The wavefronts of a die's workgroups take its items in turn:
-// wavefront w of W takes local items w, w + W, w + 2W, ...  The host sizes the launch to the workgroups that fit on
-// the chip at once, so every wavefront runs many items; a workgroup keeps its LDS until its last wavefront ends,
-// and with one item per wavefront the uneven item costs left most of the LDS held by finished wavefronts.
+// Work items of a launch of nitems items.  Workgroups are dealt to the kXcds dies round-robin (workgroup b runs on
+// die b mod kXcds).  The item list is cut into segments of kSegItems consecutive items, also dealt to the dies
+// round-robin, so items that read the same ket chunk mostly share one die's L2 while every die gets a like mix of
+// cheap and costly items (item costs drift along the list: a die owning one contiguous share of it finished long
+// before the others).  Inside a die the items are handed out one at a time from the die's counter in the launch's
+// queue (cleared before the launch), so a wavefront takes its next item when it finishes one: item costs are too
+// uneven for a fixed share per wavefront.  The host sizes the launch to the workgroups that fit on the chip at
+// once; a workgroup keeps its LDS until its last wavefront ends, which with one item per wavefront left most of the
+// LDS held by finished wavefronts.
 constexpr long long kSegItems = 256;
-struct WaveItems {
-    long long first, end, stride;  // local item range of the die and this wavefront's stride in it
-    long long die, dies;           // local item i is global item ((i / kSegItems) dies + die) kSegItems + i % kSegItems
+struct DieItems {
+    long long n;           // items of this die; its local item i is global item ((i / kSegItems) dies + die)
+    long long die, dies;   //   kSegItems + i % kSegItems
+    unsigned* counter;     // the die's counter in the launch's queue
 };
-__device__ __forceinline__ WaveItems wave_items(long long nitems) {
-    const long long nb = gridDim.x, b = blockIdx.x;
-    const long long dies = nb < kXcds ? nb : kXcds;   // dies holding workgroups
-    const long long x = b % kXcds, k = b / kXcds;
-    const long long nbx = nb / kXcds + (x < nb % kXcds ? 1 : 0);  // workgroups on die x (at least this one)
+__device__ __forceinline__ DieItems die_items(long long nitems, unsigned* queue) {
+    const long long nb = gridDim.x;
+    const long long dies = nb < kXcds ? nb : kXcds;  // dies holding workgroups
+    const long long x = blockIdx.x % kXcds;
     const long long full = nitems / kSegItems, tail = nitems % kSegItems;
-    const long long nx = (full / dies + (x < full % dies ? 1 : 0)) * kSegItems + (x == full % dies ? tail : 0);
-    const long long w = k * (kBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    return {w, nx, nbx * (kBlock / kWave), x, dies};
+    const long long n = (full / dies + (x < full % dies ? 1 : 0)) * kSegItems + (x == full % dies ? tail : 0);
+    return {n, x, dies, queue + x};
 }
-__device__ __forceinline__ long long global_item(const WaveItems& wi, long long i) {
-    return ((i / kSegItems) * wi.dies + wi.die) * kSegItems + i % kSegItems;
+// The wavefront's next local item (every lane gets the same value; n or more once the die's items are gone).
+__device__ __forceinline__ long long next_item(const DieItems& di) {
+    unsigned t = 0;
+    if (threadIdx.x % kWave == 0)
+        t = __hip_atomic_fetch_add(di.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (long long)(unsigned)__builtin_amdgcn_readfirstlane((int)t);
+}
+__device__ __forceinline__ long long global_item(const DieItems& di, long long i) {
+    return ((i / kSegItems) * di.dies + di.die) * kSegItems + i % kSegItems;
 }
 
 // Task holding launch-wide item `item` (task_begin ascending, task_begin[0] == 0).
@@ -294,7 +301,8 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
                                                    const long long* __restrict__ task_begin, int ntask,
                                                    long long item0, long long nitems,
                                                    const double* __restrict__ boys64tab,
-                                                   const float* __restrict__ boys32tab, const WorkRedirect wr) {
+                                                   const float* __restrict__ boys32tab, const WorkRedirect wr,
+                                                   unsigned* __restrict__ queue) {
     using C = EriClass<LA, LB, LC, LD>;
     constexpr int NA = C::NA, NB = C::NB, NC = C::NC, ND = C::ND;
     constexpr int NAB = NA * NB, NCD = NC * ND;
@@ -319,9 +327,9 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
         for (int i = (int)threadIdx.x; i < BROWS * (kBoysRow / 2); i += kBlock) btab[i] = src[i];
         __syncthreads();
     }
-    const WaveItems wi = wave_items(nitems);
-    for (long long i = wi.first; i < wi.end; i += wi.stride) {
-        const long long item = item0 + global_item(wi, i);
+    const DieItems di = die_items(nitems, queue);
+    for (long long i = next_item(di); i < di.n; i = next_item(di)) {
+        const long long item = item0 + global_item(di, i);
         const TaskDev& tk = tasks[find_task(task_begin, ntask, item)];
         const long long li = item - tk.item_begin;
         const int2 it = tk.items[li];

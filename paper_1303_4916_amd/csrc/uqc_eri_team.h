@@ -201,7 +201,8 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
                                                         const long long* __restrict__ task_begin, int ntask,
                                                         long long item0, long long nitems,
                                                    const double* __restrict__ boys64tab,
-                                                        const float* __restrict__ boys32tab, const WorkRedirect wr) {
+                                                        const float* __restrict__ boys32tab, const WorkRedirect wr,
+                                                        unsigned* __restrict__ queue) {
     using TC = TeamClass<LA, LB, LC, LD>;
     constexpr int NA = TC::NA, NB = TC::NB, NC = TC::NC, ND = TC::ND;
     constexpr int NAB = NA * NB, NCD = NC * ND;
@@ -216,9 +217,9 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
     constexpr int WAVE_LDS = (kTeamsPerWave + 1) * RS;
     __shared__ double lds[kBlock / kWave][WAVE_LDS];
 
-    const WaveItems wi = wave_items(nitems);
-    for (long long i = wi.first; i < wi.end; i += wi.stride) {
-        const long long item = item0 + global_item(wi, i);
+    const DieItems di = die_items(nitems, queue);
+    for (long long i = next_item(di); i < di.n; i = next_item(di)) {
+        const long long item = item0 + global_item(di, i);
         const int wid = (int)(threadIdx.x / kWave);
         const int lane = (int)(threadIdx.x % kWave);
         const TaskDev& tk = tasks[find_task(task_begin, ntask, item)];

@@ -30,6 +30,7 @@ constexpr int kGroupBras = 8;          // bra pairs per work item (one wavefront
 constexpr int kTeamGroupBras = 4;      // bra pairs per work item, team kernels
 constexpr int kXcds = 8;               // accelerator complex dies; workgroups are dealt to them round-robin
 constexpr long long kMaxItemsPerLaunch = 1LL << 20;  // work items per class-kernel launch (longer classes split)
+constexpr int kQueueWords = 16;        // item counters of one class-kernel launch: one per die, padded to 64 bytes
 
 // Primitive-pair fields, stored field-major: prim[field][k][np] (consecutive pairs contiguous; the ket side, one
 // pair per lane), and again pair-major: rec[np][k][kRec] (the bra side, one pair per wavefront, scalar loads)
@@ -122,7 +123,7 @@ enum Mode { MODE_STORE = 0, MODE_SCHWARZ = 1, MODE_SCATTER = 2, MODE_BATCH = 3 }
 struct ClassLaunchers {
     hipError_t (*digest)(bool mixed, int nspin, const TaskDev* d_tasks, const long long* d_task_begin, int ntask,
                          long long item0, long long nitems, const double* boys64, const float* boys32,
-                         const WorkRedirect& wr, hipStream_t s);
+                         const WorkRedirect& wr, unsigned* queue, hipStream_t s);
     hipError_t (*list)(bool mixed, int mode, const ListDev& list, const double* boys64, const float* boys32,
                        hipStream_t s);
     hipError_t (*list_rys)(const ListDev& list, const double* rystab, hipStream_t s);  // MODE_STORE by Rys quadrature
@@ -134,9 +135,11 @@ void class_ls(int idx, int* la, int* lb, int* lc, int* ld);
 // Work items [item0, item0 + nitems) of one (class, precision) launch group.
 // nspin = 1: J and K of D; nspin = 2: J of DJ, K of D into K and of D2 into K2, each integral evaluated once.
 // wr.J non-null (nspin = 1 only): D, J, K and the counters are taken from wr instead of the task descriptors.
+// queue: kQueueWords device words the launch hands its items out from (one counter per die), cleared by this call
+// on stream s; launches that can run at the same time need distinct queues.
 hipError_t launch_digest(int cls, bool mixed, int nspin, const TaskDev* d_tasks, const long long* d_task_begin,
                          int ntask, long long item0, long long nitems, const double* boys64, const float* boys32,
-                         const WorkRedirect& wr, hipStream_t s);
+                         const WorkRedirect& wr, unsigned* queue, hipStream_t s);
 hipError_t launch_list(int cls, bool mixed, int mode, const ListDev& list, const double* boys64,
                        const float* boys32, hipStream_t s);
 hipError_t launch_list_rys(int cls, const ListDev& list, const double* rystab, hipStream_t s);

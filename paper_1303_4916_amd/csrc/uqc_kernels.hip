@@ -46,12 +46,16 @@ double class_flops_contr(int cls) { return kClassFlopsContr[cls]; }
 
 hipError_t launch_digest(int cls, bool mixed, int nspin, const TaskDev* d_tasks, const long long* d_task_begin,
                          int ntask, long long item0, long long nitems, const double* boys64tab,
-                         const float* boys32tab, const WorkRedirect& wr, hipStream_t s) {
+                         const float* boys32tab, const WorkRedirect& wr, unsigned* queue, hipStream_t s) {
     if (nitems <= 0) return hipSuccess;
-    if (cls < 0 || cls >= kNumClasses || item0 < 0 || (nspin != 1 && nspin != 2)) return hipErrorInvalidValue;
+    if (cls < 0 || cls >= kNumClasses || item0 < 0 || (nspin != 1 && nspin != 2) || !queue)
+        return hipErrorInvalidValue;
     if (wr.J && (nspin != 1 || !wr.D || !wr.K || !wr.count)) return hipErrorInvalidValue;
+    static_assert(kQueueWords % 2 == 0 && kQueueWords >= 2 * kXcds, "queue: whole doubles, one counter per die");
+    const hipError_t e = launch_zero(reinterpret_cast<double*>(queue), kQueueWords / 2, s);
+    if (e != hipSuccess) return e;
     return launchers(cls).digest(mixed, nspin, d_tasks, d_task_begin, ntask, item0, nitems, boys64tab, boys32tab,
-                                 wr, s);
+                                 wr, queue, s);
 }
 
 hipError_t launch_list_rys(int cls, const ListDev& list, const double* rystab, hipStream_t s) {

@@ -1,6 +1,7 @@
 // uqc_fock_build_noalloc: the closed-shell Fock build of uqc_fock_build with everything it writes besides its
-// outputs (the scaled density D', the J and K accumulators, the scalars and the per-task quartet counters) in one
-// fixed device array of this file instead of the basis's workspace, for callers that cannot allocate device memory.
+// outputs (the scaled density D', the J and K accumulators, the scalars, the per-task quartet counters and the item
+// counters of the class launches) in one fixed device array of this file instead of the basis's workspace, for
+// callers that cannot allocate device memory.
 // Each device the library runs on holds its own copy of the array until the process ends; its address on a device
 // is taken once, by uqc_init, with that device current.
 #include "uqc_api_internal.h"
@@ -11,7 +12,9 @@ namespace {
 
 constexpr size_t kScratchMaxNbf = 1024;     // largest basis: 3 nbf^2 doubles of D', J and K accumulators
 constexpr size_t kScratchMaxTasks = 32768;  // largest screening plan (tasks = pairs of pair bins and precisions)
-constexpr size_t kScratchDoubles = 3 * kScratchMaxNbf * kScratchMaxNbf + 8 + 2 * kScratchMaxTasks;  // 25.7 MB
+constexpr size_t kScratchQueue = uqc::kQueueWords / 2;  // the item counters of a class launch, in doubles
+constexpr size_t kScratchDoubles =
+    3 * kScratchMaxNbf * kScratchMaxNbf + 8 + 2 * kScratchMaxTasks + kScratchQueue;  // 25.7 MB
 
 static __device__ __align__(256) double scratch[kScratchDoubles];
 
@@ -56,6 +59,7 @@ extern "C" uqc_status uqc_fock_build_noalloc(uqc_basis* B, const double* D, doub
     ws.scal = base + 3 * NN;
     ws.count = reinterpret_cast<unsigned long long*>(base + 3 * NN + 8);
     ws.max_tasks = (int)kScratchMaxTasks;
+    ws.queue = reinterpret_cast<unsigned*>(base + 3 * NN + 8 + 2 * kScratchMaxTasks);
     const double* Din[1] = {D};
     double* out[3] = {J, K, G};
     return uqc::fock_run(B, 1, Din, out, opts, stats, "uqc_fock_build_noalloc", &ws);

@@ -318,7 +318,7 @@ bool uqc_server::queue_step(Step& f) {
         }
     }
     size_t bytes = 0;
-    for (auto& g : groups) bytes += g.tasks.size() * (sizeof(TaskDev) + sizeof(long long)) + 512;
+    for (auto& g : groups) bytes += g.tasks.size() * (sizeof(TaskDev) + sizeof(long long)) + 512 + 256;
     if (bytes > f.d_bytes) {
         if (f.d_tasks) (void)hipFree(f.d_tasks);
         if (f.h_tasks) (void)hipHostFree(f.h_tasks);
@@ -341,7 +341,12 @@ bool uqc_server::queue_step(Step& f) {
         pos += g.begin.size() * sizeof(long long);
         ptrs.push_back({dt, db});
     }
+    // item counters of each group's launches (device only: cleared by each launch), after the uploaded part
+    pos = (pos + 255) & ~(size_t)255;
+    unsigned* d_queue = (unsigned*)((char*)f.d_tasks + pos);
+    static_assert(kQueueWords * sizeof(unsigned) <= 256, "a group's item counters fit its 256 reserved bytes");
     if (pos && hipMemcpyAsync(f.d_tasks, f.h_tasks, pos, hipMemcpyHostToDevice, s) != hipSuccess) return false;
+    pos += groups.size() * kQueueWords * sizeof(unsigned);
     // classes side by side on several streams, as in a single build (the most any admitted request asks for):
     // largest first, each to the least-loaded stream, queued alternately from the large and the small end
     int kStreams = 1;
@@ -368,7 +373,8 @@ bool uqc_server::queue_step(Step& f) {
         for (long long i0 = 0; i0 < groups[gi].items; i0 += kMaxItemsPerLaunch)
             if (launch_digest(groups[gi].cls, groups[gi].mixed, 1, ptrs[gi].first, ptrs[gi].second,
                               (int)groups[gi].tasks.size(), i0, std::min(kMaxItemsPerLaunch, groups[gi].items - i0),
-                              ctx->boys64, ctx->boys32, WorkRedirect{}, S[k]) != hipSuccess)
+                              ctx->boys64, ctx->boys32, WorkRedirect{}, d_queue + gi * kQueueWords, S[k]) !=
+                hipSuccess)
                 return false;
     }
     for (int k = 1; k < kStreams; ++k)
