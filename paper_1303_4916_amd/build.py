@@ -37,9 +37,11 @@ WAVES_PER_EU = {(2, 0, 1, 1): 2, (2, 1, 2, 1): 2, (2, 2, 1, 1): 2, (1, 1, 0, 0):
 # classes that do not keep their K_ac sums in LDS (the slots would cost them a wavefront per SIMD)
 KAC_NOT_IN_LDS = {(2, 1, 1, 0)}
 # classes whose FP64 Fock-build kernel reads the Boys rows from an LDS copy of its slice (measured per class: every
-# plain class gains or breaks even except (ds|ps) and (ds|pp), which run more wavefronts per SIMD and lose)
+# plain class gains or breaks even except (ds|ps), (ds|pp) and (ds|ds), which run more wavefronts per SIMD without
+# the rows' LDS and lose with it; (ds|ds): one workgroup per CU with the rows, two without, 132 vs 98.5 ms at 150
+# atoms)
 BOYS_LDS = {(0, 0, 0, 0), (1, 0, 0, 0), (1, 0, 1, 0), (1, 1, 0, 0), (2, 0, 0, 0), (1, 1, 1, 0), (2, 1, 0, 0),
-            (2, 2, 0, 0), (1, 1, 1, 1), (2, 0, 2, 0), (2, 1, 1, 0), (2, 1, 1, 1), (2, 1, 2, 0), (2, 2, 1, 0)}
+            (2, 2, 0, 0), (1, 1, 1, 1), (2, 1, 1, 0), (2, 1, 1, 1), (2, 1, 2, 0), (2, 2, 1, 0)}
 
 
 def classes():

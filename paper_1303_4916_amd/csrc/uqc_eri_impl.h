@@ -369,7 +369,7 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
             const unsigned long long heads = __ballot(head);
             const unsigned long long upto = lane == kWave - 1 ? ~0ULL : ((1ULL << (lane + 1)) - 1ULL);
             const int run = __popcll(heads & upto);
-    #pragma unroll
+#pragma unroll
             for (int st = 0; st < 6; ++st) {
                 const int ro = __shfl_up(run, 1 << st, kWave);
                 inseg[st] = lane >= (1 << st) && ro == run;
@@ -378,19 +378,19 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
         };
 
         double jcd_s[NCD], kad_s[NSPIN][KAD_MODE == 1 ? NA * ND : 1], kac_s[NSPIN][KAC_MODE == 1 ? NA * NC : 1];
-    #pragma unroll
+#pragma unroll
         for (int x = 0; x < NCD; ++x) jcd_s[x] = 0.0;
-    #pragma unroll
+#pragma unroll
         for (int sp = 0; sp < NSPIN; ++sp) {
-    #pragma unroll
+#pragma unroll
             for (int x = 0; x < (KAD_MODE == 1 ? NA * ND : 1); ++x) kad_s[sp][x] = 0.0;
-    #pragma unroll
+#pragma unroll
             for (int x = 0; x < (KAC_MODE == 1 ? NA * NC : 1); ++x) kac_s[sp][x] = 0.0;
         }
         // LDS slots of this lane: slot x at kept[x * kWave] (lane-contiguous, no bank conflicts, private to the lane),
         // spin sp's slots after those of the spins before it
         double* kept0 = &slots[threadIdx.x / kWave][lane];
-    #pragma unroll
+#pragma unroll
         for (int x = 0; x < SLOTS; ++x) kept0[x * kWave] = 0.0;
         auto kad_get = [&](int sp, int x) -> double& {
             if constexpr (KAD_MODE == 2) return kept0[(sp * SLOTS1 + x) * kWave]; else return kad_s[sp][x];
@@ -405,13 +405,13 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
             const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
             bool inseg[6], run_last;
             if constexpr (KEEP_KAC) runs(oc, inseg, run_last);
-    #pragma unroll
+#pragma unroll
             for (int sp = 0; sp < NSPIN; ++sp) {
                 double* __restrict__ K = Kp(sp);
                 if constexpr (KEEP_KAD) {
-    #pragma unroll
+#pragma unroll
                     for (int i = 0; i < NA; ++i)
-    #pragma unroll
+#pragma unroll
                         for (int l = 0; l < ND; ++l) {
                             double& r = kad_get(sp, i * ND + l);
                             const double s = r;
@@ -420,9 +420,9 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
                         }
                 }
                 if constexpr (KEEP_KAC) {
-    #pragma unroll
+#pragma unroll
                     for (int i = 0; i < NA; ++i)
-    #pragma unroll
+#pragma unroll
                         for (int k = 0; k < NC; ++k) {
                             double& r = kac_get(sp, i * NC + k);
                             const double s = seg_scan(r, inseg);
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
             double out[NAB * NCD];
             {
                 double acc[C::NACC];
-    #pragma unroll
+#pragma unroll
                 for (int x = 0; x < C::NACC; ++x) acc[x] = 0.0;
                 const int done = accumulate<C, MIXED, BLDS, true>(B, bra, kbn, Kt, kl, kkn, boys64tab, boys32tab, acc,
                                                                   btab, cqk);
@@ -468,84 +468,84 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
             const double w2 = 2.0 * w;
             {
                 double dab[NAB], dcd[NCD], jab[NAB], jcd[NCD];
-    #pragma unroll
+#pragma unroll
                 for (int i = 0; i < NA; ++i)
-    #pragma unroll
+#pragma unroll
                     for (int j = 0; j < NB; ++j) dab[i * NB + j] = Dj[(unsigned)(oa + i) * (unsigned)N + (unsigned)(ob + j)];
-    #pragma unroll
+#pragma unroll
                 for (int k = 0; k < NC; ++k)
-    #pragma unroll
+#pragma unroll
                     for (int l = 0; l < ND; ++l) dcd[k * ND + l] = Dj[(unsigned)(oc + k) * (unsigned)N + (unsigned)(od + l)];
                 contract_pair<NA, NB, NC, ND, 0>(out, dcd, dab, jab, jcd);
-    #pragma unroll
+#pragma unroll
                 for (int x = 0; x < NAB; ++x) {
                     const double s = wave_sum(w2 * jab[x]);
                     if (lane == 0) atomic_add(J + (size_t)(oa + x / NB) * N + ob + x % NB, s);
                 }
-    #pragma unroll
+#pragma unroll
                 for (int x = 0; x < NCD; ++x) jcd_s[x] = fma(w2, jcd[x], jcd_s[x]);
             }
             bool inseg[6], run_last;
             runs(oc, inseg, run_last);
-    #pragma unroll
+#pragma unroll
             for (int sp = 0; sp < NSPIN; ++sp) {
                 const cdptr Ds = Dk(sp);
                 double* __restrict__ K = Kp(sp);
                 {
                     double dbd[NB * ND], dac[NA * NC], kac[NA * NC], kbd[NB * ND];
-    #pragma unroll
+#pragma unroll
                     for (int j = 0; j < NB; ++j)
-    #pragma unroll
+#pragma unroll
                         for (int l = 0; l < ND; ++l) dbd[j * ND + l] = Ds[(unsigned)(ob + j) * (unsigned)N + (unsigned)(od + l)];
-    #pragma unroll
+#pragma unroll
                     for (int i = 0; i < NA; ++i)
-    #pragma unroll
+#pragma unroll
                         for (int k = 0; k < NC; ++k) dac[i * NC + k] = Ds[(unsigned)(oa + i) * (unsigned)N + (unsigned)(oc + k)];
                     contract_pair<NA, NB, NC, ND, 1>(out, dbd, dac, kac, kbd);
                     if constexpr (KEEP_KAC) {
-    #pragma unroll
+#pragma unroll
                         for (int x = 0; x < NA * NC; ++x) kac_get(sp, x) += w * kac[x];
                     } else {
-    #pragma unroll
+#pragma unroll
                         for (int i = 0; i < NA; ++i)
-    #pragma unroll
+#pragma unroll
                             for (int k = 0; k < NC; ++k) {
                                 const double s = seg_scan(w * kac[i * NC + k], inseg);
                                 if (run_last && s != 0.0) atomic_add(K + (size_t)(oa + i) * N + oc + k, s);
                             }
                     }
                     if (act) {
-    #pragma unroll
+#pragma unroll
                         for (int j = 0; j < NB; ++j)
-    #pragma unroll
+#pragma unroll
                             for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(ob + j) * N + od + l, w * kbd[j * ND + l]);
                     }
                 }
                 {
                     double dbc[NB * NC], dad[NA * ND], kad[NA * ND], kbc[NB * NC];
-    #pragma unroll
+#pragma unroll
                     for (int j = 0; j < NB; ++j)
-    #pragma unroll
+#pragma unroll
                         for (int k = 0; k < NC; ++k) dbc[j * NC + k] = Ds[(unsigned)(ob + j) * (unsigned)N + (unsigned)(oc + k)];
-    #pragma unroll
+#pragma unroll
                     for (int i = 0; i < NA; ++i)
-    #pragma unroll
+#pragma unroll
                         for (int l = 0; l < ND; ++l) dad[i * ND + l] = Ds[(unsigned)(oa + i) * (unsigned)N + (unsigned)(od + l)];
                     contract_pair<NA, NB, NC, ND, 2>(out, dbc, dad, kad, kbc);
-    #pragma unroll
+#pragma unroll
                     for (int j = 0; j < NB; ++j)
-    #pragma unroll
+#pragma unroll
                         for (int k = 0; k < NC; ++k) {
                             const double s = seg_scan(w * kbc[j * NC + k], inseg);
                             if (run_last && s != 0.0) atomic_add(K + (size_t)(ob + j) * N + oc + k, s);
                         }
                     if constexpr (KEEP_KAD) {
-    #pragma unroll
+#pragma unroll
                         for (int x = 0; x < NA * ND; ++x) kad_get(sp, x) += w * kad[x];
                     } else if (act) {
-    #pragma unroll
+#pragma unroll
                         for (int i = 0; i < NA; ++i)
-    #pragma unroll
+#pragma unroll
                             for (int l = 0; l < ND; ++l) atomic_add(K + (size_t)(oa + i) * N + od + l, w * kad[i * ND + l]);
                     }
                 }
@@ -555,9 +555,9 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
         {
             const int kl = opaque(kc);
             const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < NC; ++k)
-    #pragma unroll
+#pragma unroll
                 for (int l = 0; l < ND; ++l) {
                     const double s = jcd_s[k * ND + l];
                     if (s != 0.0) atomic_add(J + (size_t)(oc + k) * N + od + l, s);

@@ -297,7 +297,7 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
             const int oa = ((ciptr)(bh + 5))[0], ob = ((ciptr)(bh + 5))[1];
             if (oa != cur_a) {
                 if (cur_a >= 0) {
-    #pragma unroll
+#pragma unroll
                     for (int sp = 0; sp < NSPIN; ++sp) flush(R_KAC + sp * KSZ, R_KBC + sp * KSZ, cur_a, 0, sp);
                     wave_lds_sync();
                 }
@@ -307,23 +307,23 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
             const int pidx = opaque(lane - team * kTeam);
             const int q0 = kPermAxes[pidx][0], q1 = kPermAxes[pidx][1], q2 = kPermAxes[pidx][2];
             double acc[TC::NREP];
-    #pragma unroll
+#pragma unroll
             for (int x = 0; x < TC::NREP; ++x) acc[x] = 0.0;
             const int done = team_accumulate<TC, MIXED>(B, bra, kbn, Kt, kl, kkn, q0, q1, q2, boys64tab, boys32tab, acc,
                                                         cq0, cq1);
             pcnt += (unsigned long long)(__popcll(live) / kTeam) * (unsigned long long)done;
 
             int src[kTeam];
-    #pragma unroll
+#pragma unroll
             for (int x = 0; x < kTeam; ++x) src[x] = team * kTeam + kPermCompose[pidx][x];
             int pcA[NA], pcB[NB], pcC[NC], pcD[ND];
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < NA; ++k) pcA[k] = kPermComp[LA][pidx][k];
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < NB; ++k) pcB[k] = kPermComp[LB][pidx][k];
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < NC; ++k) pcC[k] = kPermComp[LC][pidx][k];
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < ND; ++k) pcD[k] = kPermComp[LD][pidx][k];
             const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
             double w = act ? bh[3] * Kt.sdeg[kl] : 0.0;
@@ -353,67 +353,67 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
             auto Dq = [&](int r, int c) { return Dj[(unsigned)r * (unsigned)N + (unsigned)c]; };
             {
                 double d1[NCD], d2[NAB], x[NAB], y[NCD];
-    #pragma unroll
+#pragma unroll
                 for (int k = 0; k < NC; ++k)
-    #pragma unroll
+#pragma unroll
                     for (int l = 0; l < ND; ++l) d1[k * ND + l] = Dq(oc + pcC[k], od + pcD[l]);
-    #pragma unroll
+#pragma unroll
                 for (int i = 0; i < NA; ++i)
-    #pragma unroll
+#pragma unroll
                     for (int j = 0; j < NB; ++j) d2[i * NB + j] = Dq(oa + pcA[i], ob + pcB[j]);
                 TC::digest0(out, d1, d2, x, y);
-    #pragma unroll
+#pragma unroll
                 for (int i = 0; i < NA; ++i)
-    #pragma unroll
+#pragma unroll
                     for (int j = 0; j < NB; ++j) atomic_add_lds(tm + R_JAB + pcA[i] * NB + pcB[j], x[i * NB + j]);
-    #pragma unroll
+#pragma unroll
                 for (int k = 0; k < NC; ++k)
-    #pragma unroll
+#pragma unroll
                     for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_JCD + pcC[k] * ND + pcD[l], y[k * ND + l]);
             }
-    #pragma unroll
+#pragma unroll
             for (int sp = 0; sp < NSPIN; ++sp) {
                 const cdptr Dsp = Dk(sp);
                 auto Ds = [&](int r, int c) { return Dsp[(unsigned)r * (unsigned)N + (unsigned)c]; };
                 const int sh = sp * KSZ;
                 {
                     double d1[NB * ND], d2[NA * NC], x[NA * NC], y[NB * ND];
-    #pragma unroll
+#pragma unroll
                     for (int j = 0; j < NB; ++j)
-    #pragma unroll
+#pragma unroll
                         for (int l = 0; l < ND; ++l) d1[j * ND + l] = Ds(ob + pcB[j], od + pcD[l]);
-    #pragma unroll
+#pragma unroll
                     for (int i = 0; i < NA; ++i)
-    #pragma unroll
+#pragma unroll
                         for (int k = 0; k < NC; ++k) d2[i * NC + k] = Ds(oa + pcA[i], oc + pcC[k]);
                     TC::digest1(out, d1, d2, x, y);
-    #pragma unroll
+#pragma unroll
                     for (int i = 0; i < NA; ++i)
-    #pragma unroll
+#pragma unroll
                         for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KAC + sh + pcA[i] * NC + pcC[k], x[i * NC + k]);
-    #pragma unroll
+#pragma unroll
                     for (int j = 0; j < NB; ++j)
-    #pragma unroll
+#pragma unroll
                         for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KBD + sh + pcB[j] * ND + pcD[l], y[j * ND + l]);
                 }
                 {
                     double d1[NB * NC], d2[NA * ND], x[NA * ND], y[NB * NC];
-    #pragma unroll
+#pragma unroll
                     for (int j = 0; j < NB; ++j)
-    #pragma unroll
+#pragma unroll
                         for (int k = 0; k < NC; ++k) d1[j * NC + k] = Ds(ob + pcB[j], oc + pcC[k]);
-    #pragma unroll
+#pragma unroll
                     for (int i = 0; i < NA; ++i)
-    #pragma unroll
+#pragma unroll
                         for (int l = 0; l < ND; ++l) d2[i * ND + l] = Ds(oa + pcA[i], od + pcD[l]);
                     TC::digest2(out, d1, d2, x, y);
-    #pragma unroll
+#pragma unroll
                     for (int i = 0; i < NA; ++i)
-    #pragma unroll
+#pragma unroll
                         for (int l = 0; l < ND; ++l) atomic_add_lds(tm + R_KAD + sh + pcA[i] * ND + pcD[l], x[i * ND + l]);
-    #pragma unroll
+#pragma unroll
                     for (int j = 0; j < NB; ++j)
-    #pragma unroll
+#pragma unroll
                         for (int k = 0; k < NC; ++k) atomic_add_lds(tm + R_KBC + sh + pcB[j] * NC + pcC[k], y[j * NC + k]);
                 }
             }  // spins
@@ -422,21 +422,21 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
             // J_ab by the wavefront and the K_bc / K_bd blocks of this bra pair by each team, then cleared
             if (lane < NAB) {
                 double s = 0.0;
-    #pragma unroll
+#pragma unroll
                 for (int t = 0; t < kTeamsPerWave; ++t) {
                     s += my[t * RS + R_JAB + lane];
                     my[t * RS + R_JAB + lane] = 0.0;
                 }
                 if (s != 0.0) atomic_add(J + (size_t)(oa + lane / NB) * N + ob + lane % NB, 2.0 * s);
             }
-    #pragma unroll
+#pragma unroll
             for (int sp = 0; sp < NSPIN; ++sp)
                 flush(R_KBC + sp * KSZ, R_KBC + sp * KSZ + NB * NC + NB * ND, oa, ob, sp);
             wave_lds_sync();
         }
         if (cur_a >= 0) {
             flush(R_JCD, R_KAC, cur_a, 0, 0);
-    #pragma unroll
+#pragma unroll
             for (int sp = 0; sp < NSPIN; ++sp) flush(R_KAC + sp * KSZ, R_KBC + sp * KSZ, cur_a, 0, sp);
         }
         if (lane == 0 && cnt) {
