@@ -395,6 +395,7 @@ def gen_team(c):
     ia, ib, ic, idd = ({t: i for i, t in enumerate(x)} for x in (ca, cb, cc, cd))
     masks = []
     stream = []   # the same outputs, each digested at once into all six partial blocks (streaming form)
+    stream_lds = []  # streaming form against the team's LDS copies of the density slices and partial blocks
     for o in out_reps:
         a, b, cx, d = o
         terms = []
@@ -431,6 +432,16 @@ def gen_team(c):
                       % (i * nc + k, j * nd + l, i * nc + k, i * nd + l, j * nc + k, i * nd + l))
         stream.append("  kbc[%d] = fma(x, dad[%d], kbc[%d]); kbd[%d] = fma(x, dac[%d], kbd[%d]); }"
                       % (j * nc + k, i * nd + l, j * nc + k, j * nd + l, i * nc + k, j * nd + l))
+        # true-index offsets from the lane's component maps pA..pD (frame component -> true component)
+        stream_lds.append("{ const double x = (%s) * %s;" % (expr, wexpr))
+        stream_lds.append("  const int ij = pA[%d] * %d + pB[%d], kl = pC[%d] * %d + pD[%d], "
+                          "ik = pA[%d] * %d + pC[%d], il = pA[%d] * %d + pD[%d], "
+                          "jk = pB[%d] * %d + pC[%d], jl = pB[%d] * %d + pD[%d];"
+                          % (i, nb, j, k, nd, l, i, nc, k, i, nd, l, j, nc, k, j, nd, l))
+        stream_lds.append("  if constexpr (WITH_J) { atomic_add_lds(t_jab + ij, x * s_cd[kl]); "
+                          "atomic_add_lds(t_jcd + kl, x * s_ab[ij]); }")
+        stream_lds.append("  atomic_add_lds(t_kac + ik, x * s_bd[jl]); atomic_add_lds(t_kad + il, x * s_bc[jk]); "
+                          "atomic_add_lds(t_kbc + jk, x * s_ad[il]); atomic_add_lds(t_kbd + jl, x * s_ac[ik]); }")
     # Digest passes over the lane's weighted outputs, two partial blocks each (the same pairing as the 64-ket
     # kernels): P = 0: x = out.D_cd -> J_ab, y = out.D_ab -> J_cd; P = 1: x = out.D_bd -> K_ac, y = out.D_ac -> K_bd;
     # P = 2: x = out.D_bc -> K_ad, y = out.D_ad -> K_bc.  D slices and partials are in the lane's own frame; every
@@ -462,15 +473,18 @@ def gen_team(c):
     # the streaming form shares the memoised intermediate lines of the horizontal recursion
     hrr_stream = [x for x in hl if not x.startswith("out[")]
     pos = 0
-    merged = []
+    merged, merged_lds = [], []
     for x in hl:
         if x.startswith("out["):
             merged += stream[4 * pos:4 * pos + 4]
+            merged_lds += stream_lds[4 * pos:4 * pos + 4]
             pos += 1
         else:
             merged.append(x)
+            merged_lds.append(x)
     return {"vrr": vrr_lines, "nrep": len(reps), "reps": reps, "out_reps": out_reps, "hrr": hl,
-            "digest": digest, "hrr_digest": merged, "masks": masks, "v": v, "hrr_flops": flops[0]}
+            "digest": digest, "hrr_digest": merged, "hrr_digest_lds": merged_lds, "masks": masks, "v": v,
+            "hrr_flops": flops[0]}
 
 
 def perm_comp_table():
@@ -644,6 +658,19 @@ def main(outdir):
                       "double* __restrict__ kac, double* __restrict__ kad, double* __restrict__ kbc, "
                       "double* __restrict__ kbd) {")
             for line in t["hrr_digest"]:
+                th.append("    " + line)
+            th.append("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz; (void)src; (void)pidx;")
+            th.append("  }")
+            # the same, with the density slices read from and the partial blocks added into the team's LDS copies
+            # (true component order; pA..pD: the lane's maps from frame to true components)
+            th.append("  template <bool WITH_J>")
+            th.append("  __device__ static __forceinline__ void hrr_digest_lds(const double* __restrict__ acc, "
+                      "const int* __restrict__ src, int pidx, double w, double ABx, double ABy, double ABz, "
+                      "double CDx, double CDy, double CDz, const double* s_ab, const double* s_cd, "
+                      "const double* s_ac, const double* s_ad, const double* s_bc, const double* s_bd, "
+                      "double* t_jab, double* t_jcd, double* t_kac, double* t_kad, double* t_kbc, double* t_kbd, "
+                      "const int* pA, const int* pB, const int* pC, const int* pD) {")
+            for line in t["hrr_digest_lds"]:
                 th.append("    " + line)
             th.append("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz; (void)src; (void)pidx;")
             th.append("  }")

@@ -194,6 +194,56 @@ __device__ __forceinline__ void team_digest_stream(const double* acc, const int*
     }
 }
 
+// Entries pidx, pidx + kTeam, ... of the R x Cn density block D[r0 + r][c0 + c] into dst (row-major).
+template <int R, int Cn>
+__device__ __forceinline__ void gather_slice(double* dst, cdptr Dm, int N, int r0, int c0, int pidx) {
+    for (int x = pidx; x < R * Cn; x += kTeam)
+        dst[x] = Dm[(unsigned)(r0 + x / Cn) * (unsigned)N + (unsigned)(c0 + x % Cn)];
+}
+
+// Doubles of a team's six density slices in LDS (D_ab, D_cd, D_ac, D_ad, D_bc, D_bd, true component order).
+template <class TC>
+__host__ __device__ constexpr int team_slices() {
+    return TC::NA * TC::NB + TC::NC * TC::ND + TC::NA * TC::NC + TC::NA * TC::ND + TC::NB * TC::NC + TC::NB * TC::ND;
+}
+
+// team_digest_stream with the density slices and the partial blocks in LDS instead of registers, for classes whose
+// accumulators alone take most of a lane's registers ((dd|dd): 185 accumulators, and six 36-element slices plus six
+// 36-element partial blocks would need 617 doubles per lane).  The team's six lanes gather the slices into the
+// team's slice block `sl` (true component order), then every output adds its six contributions into the team's
+// partial blocks with LDS atomics.  The slices are rewritten for every quartet: the calls begin and end with a
+// wavefront LDS barrier.
+template <class TC, int LA, int LB, int LC, int LD, bool WITH_J>
+__device__ __forceinline__ void team_digest_stream_lds(const double* acc, const int* src, int pidx, double w, cdptr bh,
+                                                       const BinDev& Kt, int kl, int q0, int q1, int q2, cdptr DjC,
+                                                       cdptr DkC, int N, int oa, int ob, int oc, int od,
+                                                       const int* pcA, const int* pcB, const int* pcC, const int* pcD,
+                                                       double* sl, double* t_jab, double* t_jcd, double* t_kac,
+                                                       double* t_kad, double* t_kbc, double* t_kbd) {
+    constexpr int NA = TC::NA, NB = TC::NB, NC = TC::NC, ND = TC::ND;
+    constexpr int S_AB = 0, S_CD = S_AB + NA * NB, S_AC = S_CD + NC * ND, S_AD = S_AC + NA * NC;
+    constexpr int S_BC = S_AD + NA * ND, S_BD = S_BC + NB * NC;
+    wave_lds_sync();  // the previous quartet's reads of the slices are done
+    if constexpr (WITH_J) {
+        gather_slice<NA, NB>(sl + S_AB, DjC, N, oa, ob, pidx);
+        gather_slice<NC, ND>(sl + S_CD, DjC, N, oc, od, pidx);
+    }
+    gather_slice<NA, NC>(sl + S_AC, DkC, N, oa, oc, pidx);
+    gather_slice<NA, ND>(sl + S_AD, DkC, N, oa, od, pidx);
+    gather_slice<NB, NC>(sl + S_BC, DkC, N, ob, oc, pidx);
+    gather_slice<NB, ND>(sl + S_BD, DkC, N, ob, od, pidx);
+    wave_lds_sync();
+    const double ABx = sel3(bh[0], bh[1], bh[2], q0), ABy = sel3(bh[0], bh[1], bh[2], q1);
+    const double ABz = sel3(bh[0], bh[1], bh[2], q2);
+    const double CDx = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q0);
+    const double CDy = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q1);
+    const double CDz = sel3(Kt.AB[kl], Kt.AB[Kt.np + kl], Kt.AB[2 * Kt.np + kl], q2);
+    TC::template hrr_digest_lds<WITH_J>(acc, src, pidx, w, ABx, ABy, ABz, CDx, CDy, CDz, sl + S_AB, sl + S_CD,
+                                        sl + S_AC, sl + S_AD, sl + S_BC, sl + S_BD, t_jab, t_jcd, t_kac, t_kad, t_kbc,
+                                        t_kbd, pcA, pcB, pcC, pcD);
+    wave_lds_sync();  // the blocks are complete before anyone flushes them
+}
+
 // NSPIN = 2 (spin densities): J from the total density, K_ac, K_ad, K_bc, K_bd once per spin density into its
 // own LDS blocks and accumulator.
 template <int LA, int LB, int LC, int LD, bool MIXED, int NSPIN>
@@ -216,6 +266,16 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
     constexpr int RS = R + ((33 - R % 32) % 32);
     constexpr int WAVE_LDS = (kTeamsPerWave + 1) * RS;
     __shared__ double lds[kBlock / kWave][WAVE_LDS];
+    // streaming classes, where the workgroup's LDS leaves room: every team's six density slices in LDS as well (team
+    // stride padded like RS), zeroed once (the idle team's lanes leave some entries unwritten)
+    constexpr int SLS = team_slices<TC>() + ((33 - team_slices<TC>() % 32) % 32);
+    constexpr bool SLDS =
+        TC::STREAM && NSPIN == 1 && (kBlock / kWave) * (WAVE_LDS + (kTeamsPerWave + 1) * SLS) * 8 <= 160 * 1024;
+    __shared__ double slices[kBlock / kWave][SLDS ? (kTeamsPerWave + 1) * SLS : 1];
+    if constexpr (SLDS) {
+        const int w0 = (int)(threadIdx.x / kWave), l0 = (int)(threadIdx.x % kWave);
+        for (int x = l0; x < (kTeamsPerWave + 1) * SLS; x += kWave) slices[w0][x] = 0.0;
+    }
 
     const DieItems di = die_items(nitems, queue);
     for (long long i = next_item(di); i < di.n; i = next_item(di)) {
@@ -328,7 +388,12 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
             const int oc = Kt.off_a[kl], od = Kt.off_b[kl];
             double w = act ? bh[3] * Kt.sdeg[kl] : 0.0;
             if (tk.same && ket == bra) w *= 0.5;
-            if constexpr (TC::STREAM) {
+            if constexpr (SLDS) {
+                team_digest_stream_lds<TC, LA, LB, LC, LD, true>(acc, src, pidx, w, bh, Kt, kl, q0, q1, q2, Dj, Dc, N,
+                                                                 oa, ob, oc, od, pcA, pcB, pcC, pcD,
+                                                                 &slices[wid][team * SLS], tm + R_JAB, tm + R_JCD,
+                                                                 tm + R_KAC, tm + R_KAD, tm + R_KBC, tm + R_KBD);
+            } else if constexpr (TC::STREAM) {
                 team_digest_stream<TC, LA, LB, LC, LD, true>(acc, src, pidx, w, bh, Kt, kl, q0, q1, q2, Dj, Dc, N, oa, ob,
                                                              oc, od, pcA, pcB, pcC, pcD, tm + R_JAB, tm + R_JCD,
                                                              tm + R_KAC, tm + R_KAD, tm + R_KBC, tm + R_KBD);

@@ -164,3 +164,86 @@ def test_team_emulation_matches_oracle(c):
             "kbc": np.einsum("ijkl,il->jk", v, Dad).ravel(), "kbd": np.einsum("ijkl,ik->jl", v, Dac).ravel()}
     for k in refd:
         assert np.max(np.abs(true_dig[k] - refd[k])) <= 1e-12 * max(np.max(np.abs(refd[k])), 1e-300), k
+
+
+def _stream_lds_python(lines):
+    """The generated LDS streaming digest as Python: atomic_add_lds(t_X + i, v) adds v into block X at i."""
+    out = []
+    for line in lines:
+        s = line.strip()
+        if s.startswith("{ const double x = "):
+            out.append("x = " + s[len("{ const double x = "):].rstrip(";"))
+        elif s.startswith("const int ij = "):
+            out += [a.strip() for a in s[len("const int "):].rstrip(";").split(", ")]
+        elif "atomic_add_lds" in s:
+            cond = s.startswith("if constexpr (WITH_J)")
+            calls = re.findall(r"atomic_add_lds\(t_(\w+) \+ (\w+), ([^;]*)\);", s)
+            assert calls, s
+            for blk, idx, val in calls:
+                out.append(("if WITH_J: " if cond else "") + "_add('%s', %s, %s)" % (blk, idx, val))
+        else:
+            s = re.sub(r"^const double ", "", s).rstrip(";")
+            out.append(s)
+    code = "\n".join(out)
+    code = re.sub(r"fetch\(acc\[(\d+)\], src\[(\d+)\]\)", r"_acc[src[\2]][\1]", code)
+    code = re.sub(r"\(\(\((\d+) >> pidx\) & 1\) \? w : 0\.0\)", r"(w if ((\1 >> pidx) & 1) else 0.0)", code)
+    return code
+
+
+@pytest.mark.parametrize("c", sorted(gen.TEAM_STREAM_DIGEST), ids=gen.cname)
+@pytest.mark.parametrize("with_j", [True, False])
+def test_team_stream_lds_digest_matches_oracle(c, with_j):
+    """The streaming digest that reads the team's density slices from, and adds its contributions into, shared
+    true-index blocks (LDS on the device): the six lanes' contributions equal the digest of the oracle block."""
+    la, lb, lc, ld = c
+    t = gen.gen_team(c)
+    rng = np.random.default_rng(sum(x * 3 ** i for i, x in enumerate(c)) + 7)
+    cen = rng.uniform(-1.5, 1.5, size=(4, 3))
+    ex = np.exp(rng.uniform(math.log(0.3), math.log(5.0), size=4))
+    sh = wl.Shells(np.array(c, np.int32), np.ones(4, np.int32), cen, ex, np.ones(4), np.arange(4, dtype=np.int32))
+    ref = oracle.Basis(sh).eri(0, 1, 2, 3)
+    comps = [gen.comps(l) for l in c]
+    scale = np.einsum("i,j,k,l->ijkl", *[np.array([_norm(ex[s], cp) for cp in comps[s]]) for s in range(4)])
+    v = ref / scale
+    geo = _geometry(*cen, *ex)
+    L = la + lb + lc + ld
+    vrr_code = "\n".join(re.sub(r"^const (T|double) ", "", x).rstrip(";").replace("(double)", "") for x in t["vrr"])
+    accs = []
+    for p in gen.PERMS:
+        env = _lane_env(geo, p, L)
+        env["acc"] = np.zeros(t["nrep"])
+        exec(vrr_code, env)
+        accs.append(env["acc"])
+    na, nb, nc, nd = (len(x) for x in comps)
+    Dm = np.random.default_rng(11).standard_normal((na + nb + nc + nd,) * 2)
+    Dm = Dm + Dm.T
+    o = [0, na, na + nb, na + nb + nc]
+    blk = lambda s1, n1, s2, n2: Dm[o[s1]:o[s1] + n1, o[s2]:o[s2] + n2]
+    S = {"s_ab": blk(0, na, 1, nb).ravel(), "s_cd": blk(2, nc, 3, nd).ravel(), "s_ac": blk(0, na, 2, nc).ravel(),
+         "s_ad": blk(0, na, 3, nd).ravel(), "s_bc": blk(1, nb, 2, nc).ravel(), "s_bd": blk(1, nb, 3, nd).ravel()}
+    tot = {k: np.zeros(n) for k, n in [("jab", na * nb), ("jcd", nc * nd), ("kac", na * nc), ("kad", na * nd),
+                                        ("kbc", nb * nc), ("kbd", nb * nd)]}
+
+    def _add(name, i, val):
+        tot[name][i] += val
+
+    comp_tab = [[gen.PERMS.index(gen.perm_compose(p, q)) for q in gen.PERMS] for p in gen.PERMS]
+    pc_tab = gen.perm_comp_table()
+    code = _stream_lds_python(t["hrr_digest_lds"])
+    for ip, p in enumerate(gen.PERMS):
+        env = _lane_env(geo, p, L)
+        env.update(S)
+        env.update(acc=accs[ip], src=comp_tab[ip], pidx=ip, w=1.0, _acc=accs, _add=_add, WITH_J=with_j,
+                   pA=pc_tab[la][ip], pB=pc_tab[lb][ip], pC=pc_tab[lc][ip], pD=pc_tab[ld][ip])
+        exec(code, env)
+    refd = {"jab": np.einsum("ijkl,kl->ij", v, S["s_cd"].reshape(nc, nd)).ravel(),
+            "jcd": np.einsum("ijkl,ij->kl", v, S["s_ab"].reshape(na, nb)).ravel(),
+            "kac": np.einsum("ijkl,jl->ik", v, S["s_bd"].reshape(nb, nd)).ravel(),
+            "kad": np.einsum("ijkl,jk->il", v, S["s_bc"].reshape(nb, nc)).ravel(),
+            "kbc": np.einsum("ijkl,il->jk", v, S["s_ad"].reshape(na, nd)).ravel(),
+            "kbd": np.einsum("ijkl,ik->jl", v, S["s_ac"].reshape(na, nc)).ravel()}
+    for k in refd:
+        if not with_j and k in ("jab", "jcd"):
+            assert not np.any(tot[k]), k
+            continue
+        assert np.max(np.abs(tot[k] - refd[k])) <= 1e-12 * max(np.max(np.abs(refd[k])), 1e-300), k
