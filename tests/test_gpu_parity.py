@@ -56,6 +56,16 @@ def test_boys_fp64_every_order_around_its_asymptotic_cut(ctx, mmax):
     assert rel <= 5e-14, rel
 
 
+def test_boys_fp64_asymptotic_is_exact_to_rounding(ctx):
+    # beyond T_0 = 37, F_0(T) = sqrt(pi / T) / 2 to well below double rounding (erfc(sqrt(37)) ~ 1e-17): this pins
+    # the device reciprocal square root (hardware estimate + one third-order step) to a few rounding errors
+    T = np.geomspace(37.0, 1e8, 4001)
+    got = ctx.boys(T, 0, uqc.FP64)[:, 0]
+    ref = np.sqrt(np.pi / T) / 2
+    rel = np.max(np.abs(got - ref) / ref)
+    assert rel <= 1e-15, rel
+
+
 def test_boys_fp32_matches_oracle(ctx):
     T = np.linspace(0, 30, 3001)
     got = ctx.boys(T, 8, uqc.MIXED)
