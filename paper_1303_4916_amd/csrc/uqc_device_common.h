@@ -43,6 +43,15 @@ __device__ __forceinline__ double rsqrt64(double x) {
     return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
+// A double constant materialised in scalar registers at its use (two scalar moves), so that an FMA takes it as its
+// scalar operand.  Left to itself the compiler keeps the exp(d) coefficients below in vector registers across the
+// primitive loop, and then copies each one before the accumulating FMA that consumes it (six vector moves per
+// evaluation).
+__device__ __forceinline__ double sgpr_const(double c) {
+    asm volatile("" : "+s"(c));
+    return c;
+}
+
 // ------------------------------------------------------------------------------------------------ Boys function
 // F_m(T) = int_0^1 t^{2m} exp(-T t^2) dt, returned multiplied by `pref` (`tab`: the per-order FP64 slices).
 // For T < T_L (L the highest order needed): Taylor series of order 8 around the nearest grid point T_g = g/8
@@ -104,13 +113,13 @@ __device__ __forceinline__ void boys64_eval(double T, int g, double pref, const 
         p = fma(p, d, r[0].x);
         F[L] = p * pref;
         if constexpr (L > 0) {
-            double x = 1.0 / 362880.0;
-            x = fma(x, d, 1.0 / 40320.0);
-            x = fma(x, d, 1.0 / 5040.0);
-            x = fma(x, d, 1.0 / 720.0);
-            x = fma(x, d, 1.0 / 120.0);
-            x = fma(x, d, 1.0 / 24.0);
-            x = fma(x, d, 1.0 / 6.0);
+            double x = sgpr_const(1.0 / 362880.0);
+            x = fma(x, d, sgpr_const(1.0 / 40320.0));
+            x = fma(x, d, sgpr_const(1.0 / 5040.0));
+            x = fma(x, d, sgpr_const(1.0 / 720.0));
+            x = fma(x, d, sgpr_const(1.0 / 120.0));
+            x = fma(x, d, sgpr_const(1.0 / 24.0));
+            x = fma(x, d, sgpr_const(1.0 / 6.0));
             x = fma(x, d, 0.5);
             x = fma(x, d, 1.0);
             x = fma(x, d, 1.0);
