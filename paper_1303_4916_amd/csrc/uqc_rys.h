@@ -17,6 +17,8 @@
 #pragma once
 #include "uqc_device_common.h"
 
+#include <utility>
+
 namespace uqc {
 
 #include "generated/rys_consts.h"
@@ -122,21 +124,20 @@ struct Comps {
     __device__ static constexpr int z(int i) { return L - x(i) - y(i); }
 };
 
-// Block (ab|cd) of quartet q of the list (components row-major, component factors applied), as MODE_STORE.
-template <int LA, int LB, int LC, int LD>
-__global__ __launch_bounds__(kBlock) void k_list_rys(ListDev L, const double* __restrict__ rystab) {
+// Components [I0, I0 + NI) of shell a of the block (ab|cd) of quartet q: every primitive quartet and root is
+// evaluated, and only those outputs are summed and stored (row-major in the whole block, component factors applied).
+template <int LA, int LB, int LC, int LD, int I0, int NI>
+__device__ __forceinline__ void rys_pass(const ListDev& L, int bra, int ket, const double* __restrict__ rystab,
+                                         double* o) {
     constexpr int NR = (LA + LB + LC + LD) / 2 + 1;
-    constexpr int NA = Comps<LA>::N, NB = Comps<LB>::N, NC = Comps<LC>::N, ND = Comps<LD>::N;
-    constexpr int NOUT = NA * NB * NC * ND;
-    const int q = (int)(blockIdx.x * kBlock + threadIdx.x);
-    if (q >= L.n) return;
-    const int bra = L.bra_idx[q], ket = L.ket_idx[q];
+    constexpr int NB = Comps<LB>::N, NC = Comps<LC>::N, ND = Comps<LD>::N;
+    constexpr int NP = NI * NB * NC * ND;
     const BinDev &Bb = L.bra, &Bk = L.ket;
     const double AB[3] = {Bb.AB[bra], Bb.AB[Bb.np + bra], Bb.AB[2 * Bb.np + bra]};
     const double CD[3] = {Bk.AB[ket], Bk.AB[Bk.np + ket], Bk.AB[2 * Bk.np + ket]};
-    double out[NOUT];
+    double out[NP];
 #pragma unroll
-    for (int x = 0; x < NOUT; ++x) out[x] = 0.0;
+    for (int x = 0; x < NP; ++x) out[x] = 0.0;
     const size_t fb = (size_t)Bb.K * Bb.np, fk = (size_t)Bk.K * Bk.np;
     for (int kb = 0; kb < Bb.K; ++kb) {
         const double* bp = Bb.prim + (size_t)kb * Bb.np + bra;
@@ -168,14 +169,15 @@ __global__ __launch_bounds__(kBlock) void k_list_rys(ListDev L, const double* __
                 rys_1d<LA, LB, LC, LD>(PA[2] - roz * PQ[2] * t2, QC[2] + roe * PQ[2] * t2, B10, B01, B00,
                                        pref * wr[r], AB[2], CD[2], Gz);
 #pragma unroll
-                for (int i = 0; i < NA; ++i)
+                for (int ii = 0; ii < NI; ++ii)
 #pragma unroll
                     for (int j = 0; j < NB; ++j)
 #pragma unroll
                         for (int k = 0; k < NC; ++k)
 #pragma unroll
                             for (int l = 0; l < ND; ++l) {
-                                const int x = ((i * NB + j) * NC + k) * ND + l;
+                                const int i = I0 + ii;
+                                const int x = ((ii * NB + j) * NC + k) * ND + l;
                                 out[x] = fma(Gx[Comps<LA>::x(i)][Comps<LB>::x(j)][Comps<LC>::x(k)][Comps<LD>::x(l)] *
                                                  Gy[Comps<LA>::y(i)][Comps<LB>::y(j)][Comps<LC>::y(k)][Comps<LD>::y(l)],
                                              Gz[Comps<LA>::z(i)][Comps<LB>::z(j)][Comps<LC>::z(k)][Comps<LD>::z(l)],
@@ -184,18 +186,40 @@ __global__ __launch_bounds__(kBlock) void k_list_rys(ListDev L, const double* __
             }
         }
     }
-    double* o = L.out + (size_t)q * NOUT;
 #pragma unroll
-    for (int i = 0; i < NA; ++i)
+    for (int ii = 0; ii < NI; ++ii)
 #pragma unroll
         for (int j = 0; j < NB; ++j)
 #pragma unroll
             for (int k = 0; k < NC; ++k)
 #pragma unroll
                 for (int l = 0; l < ND; ++l) {
-                    const int x = ((i * NB + j) * NC + k) * ND + l;
-                    o[x] = out[x] * (comp_factor(LA, i) * comp_factor(LB, j) * comp_factor(LC, k) * comp_factor(LD, l));
+                    const int i = I0 + ii;
+                    o[((i * NB + j) * NC + k) * ND + l] =
+                        out[((ii * NB + j) * NC + k) * ND + l] *
+                        (comp_factor(LA, i) * comp_factor(LB, j) * comp_factor(LC, k) * comp_factor(LD, l));
                 }
+}
+
+template <int LA, int LB, int LC, int LD, int NI, int... P>
+__device__ __forceinline__ void rys_passes(const ListDev& L, int bra, int ket, const double* __restrict__ rystab,
+                                           double* o, std::integer_sequence<int, P...>) {
+    (rys_pass<LA, LB, LC, LD, P * NI, NI>(L, bra, ket, rystab, o), ...);
+}
+
+// Block (ab|cd) of quartet q of the list (components row-major, component factors applied), as MODE_STORE.  Blocks
+// of more than 216 outputs are made in one pass per component of shell a (the primitive quartets and roots evaluated
+// again in each): a whole (dd|dd) block held at once took 27 KB of scratch memory per lane.
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(kBlock) void k_list_rys(ListDev L, const double* __restrict__ rystab) {
+    constexpr int NA = Comps<LA>::N, NB = Comps<LB>::N, NC = Comps<LC>::N, ND = Comps<LD>::N;
+    constexpr int NOUT = NA * NB * NC * ND;
+    constexpr int NI = NOUT > 216 ? 1 : NA;  // components of shell a per pass
+    const int q = (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (q >= L.n) return;
+    const int bra = L.bra_idx[q], ket = L.ket_idx[q];
+    rys_passes<LA, LB, LC, LD, NI>(L, bra, ket, rystab, L.out + (size_t)q * NOUT,
+                                   std::make_integer_sequence<int, NA / NI>{});
 }
 
 }  // namespace uqc
