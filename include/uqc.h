@@ -65,7 +65,8 @@ typedef struct {
     double schwarz_tau;   /* screening threshold tau (>= 0) */
     int precision;        /* uqc_precision.  UQC_MIXED: primitive recursions in FP32 with FP64 accumulation, except
                              quartets with Q_ab Q_cd > fp64_bound (whole quartet in FP64) and Boys arguments
-                             T > 30 (Boys function evaluated in FP64); J, K, G, E2 always accumulated in FP64 */
+                             T > fp64_boys_T (Boys function evaluated in FP64); J, K, G, E2 always accumulated in
+                             FP64 */
     double fp64_bound;    /* default 1e-8 */
     int timing;           /* 1: time every class launch with HIP events on its stream (reported in uqc_stats; with
                              several streams a class's time includes the kernels that run beside it) */
@@ -84,6 +85,9 @@ typedef struct {
                                back into it before the build's final pass, so callers see one stream either way.
                                Kernels of different classes then run side by side, which fills the chip while
                                one class's launch drains.  Default 3; outside 0..4: UQC_E_ARG. */
+    double fp64_boys_T;     /* UQC_MIXED: primitive quartets of FP32 quartets whose Boys argument T exceeds this take
+                               the FP64 Boys evaluation (the recursion stays FP32).  0..30, the range of the FP32 Boys
+                               table (outside, or not finite: UQC_E_ARG); default 30. */
 } uqc_fock_opts;
 
 #define UQC_MAX_CLASS_STATS 96
@@ -106,7 +110,7 @@ typedef struct {
 } uqc_stats;
 
 /* Fills *o with: tau = 1e-12, precision = UQC_FP64, fp64_bound = 1e-8, timing = 0, progress = NULL,
- * max_items_per_launch = 0, exchange_scale = 1, streams = 3. */
+ * max_items_per_launch = 0, exchange_scale = 1, streams = 3, fp64_boys_T = 30. */
 void uqc_fock_opts_default(uqc_fock_opts* o);
 
 /* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t the library launches on (NULL: the
@@ -162,8 +166,8 @@ uqc_status uqc_fock_build(uqc_basis* b, const double* D, double* J, double* K, d
  *     class launches live in a fixed device array of the library (25.7 MB per device, held until the process ends)
  *     instead of the basis's workspace and plan, so
  *     the basis has at most 1024 basis functions (else UQC_E_ARG);
- *   - the screening plan for (opts->schwarz_tau, opts->precision, opts->fp64_bound) must already exist on this
- *     basis: an earlier uqc_fock_build with the same three options makes it (else UQC_E_ARG);
+ *   - the screening plan for (opts->schwarz_tau, opts->precision, opts->fp64_bound, opts->fp64_boys_T) must
+ *     already exist on this basis: an earlier uqc_fock_build with the same four options makes it (else UQC_E_ARG);
  *   - every class launch is queued on the context's stream (opts->streams is not used); opts->timing must be 0.
  * Every call on one device shares that device's array, so calls that overlap on one device (from two host threads,
  * or on two contexts' streams) race and give wrong results; calls in sequence on one stream are safe (each starts by

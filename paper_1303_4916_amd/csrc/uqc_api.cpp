@@ -37,6 +37,7 @@ void uqc_fock_opts_default(uqc_fock_opts* o) {
     o->max_items_per_launch = 0;
     o->exchange_scale = 1.0;
     o->streams = 3;
+    o->fp64_boys_T = (double)kBoysTmax32;
 }
 
 // ---------------------------------------------------------------------------------------------- Boys table
@@ -248,6 +249,8 @@ uqc_status uqc::check_fock_opts(const uqc_fock_opts& o, const std::string& nm) {
     if (!(o.schwarz_tau >= 0) || !std::isfinite(o.schwarz_tau)) return uqc_fail(UQC_E_ARG, nm + ": bad tau");
     if (o.precision != UQC_FP64 && o.precision != UQC_MIXED) return uqc_fail(UQC_E_ARG, nm + ": bad precision");
     if (o.precision == UQC_MIXED && !(o.fp64_bound >= 0)) return uqc_fail(UQC_E_ARG, nm + ": bad fp64_bound");
+    if (o.precision == UQC_MIXED && !(o.fp64_boys_T >= 0 && o.fp64_boys_T <= (double)kBoysTmax32))
+        return uqc_fail(UQC_E_ARG, nm + ": fp64_boys_T must be in 0..30 (the FP32 Boys table's range)");
     if (o.max_items_per_launch < 0) return uqc_fail(UQC_E_ARG, nm + ": negative max_items_per_launch");
     if (!std::isfinite(o.exchange_scale)) return uqc_fail(UQC_E_ARG, nm + ": exchange_scale is not finite");
     if (o.streams < 0 || o.streams > 4) return uqc_fail(UQC_E_ARG, nm + ": streams must be in 0..4");
@@ -816,16 +819,17 @@ static int group_bras(int cls) {
     }
 }
 
-Plan* find_plan(uqc_basis* B, double tau, int prec, double bound) {
+Plan* find_plan(uqc_basis* B, double tau, int prec, double bound, double boys_t) {
     for (auto& kv : B->plans)
-        if (kv.first.tau == tau && kv.first.prec == prec && (prec == UQC_FP64 || kv.first.bound == bound))
+        if (kv.first.tau == tau && kv.first.prec == prec &&
+            (prec == UQC_FP64 || (kv.first.bound == bound && kv.first.boys_t == boys_t)))
             return &kv.second;
     return nullptr;
 }
 
-Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st) {
-    if (Plan* p = find_plan(B, tau, prec, bound)) return p;
-    PlanKey key{tau, prec, prec == UQC_FP64 ? 0.0 : bound};
+Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, double boys_t, uqc_status* st) {
+    if (Plan* p = find_plan(B, tau, prec, bound, boys_t)) return p;
+    PlanKey key{tau, prec, prec == UQC_FP64 ? 0.0 : bound, prec == UQC_FP64 ? 0.0 : boys_t};
     Plan plan;
     struct HostTask {
         int cls, mixed, X, Y, same;
@@ -970,6 +974,7 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st)
         d.item_begin = 0;
         d.nitems = t.nitems;
         d.tau = tau;
+        d.boys_t = key.boys_t;
         d.lo_excl = t.lo_excl;
         d.hi_incl = t.hi_incl;
         d.count = plan.d_count + oi;
@@ -1200,11 +1205,12 @@ uqc_status uqc::fock_run(uqc_basis* B, int nspin, const double* const* Din, doub
         if (out[i] && uqc::is_device_ptr(out[i]) != dev)
             return uqc_fail(UQC_E_ARG, nm + ": mix of host and device pointers");
     uqc_status st = UQC_OK;
-    Plan* plan = ws ? find_plan(B, o.schwarz_tau, o.precision, o.fp64_bound)
-                    : get_plan(B, o.schwarz_tau, o.precision, o.fp64_bound, &st);
+    Plan* plan = ws ? find_plan(B, o.schwarz_tau, o.precision, o.fp64_bound, o.fp64_boys_T)
+                    : get_plan(B, o.schwarz_tau, o.precision, o.fp64_bound, o.fp64_boys_T, &st);
     if (!plan && ws)
         return uqc_fail(UQC_E_ARG, nm + ": no screening plan for these options on this basis (an earlier "
-                                        "uqc_fock_build with the same tau, precision and fp64_bound makes it)");
+                                        "uqc_fock_build with the same tau, precision, fp64_bound and fp64_boys_T "
+                                        "makes it)");
     if (!plan) return st;
     if (ws && plan->ntasks > ws->max_tasks)
         return uqc_fail(UQC_E_ARG, nm + ": the plan has more tasks than the fixed workspace holds");

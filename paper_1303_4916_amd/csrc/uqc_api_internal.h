@@ -81,6 +81,7 @@ struct PlanKey {
     double tau;
     int prec;
     double bound;
+    double boys_t;  // mixed plans: the FP32 Boys evaluation covers T <= boys_t
 };
 
 struct Plan {
@@ -136,9 +137,9 @@ namespace uqc {
 uqc_status check_fock_opts(const uqc_fock_opts& o, const std::string& who);
 }
 
-uqc::Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, uqc_status* st);
+uqc::Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, double boys_t, uqc_status* st);
 // The plan already made for these options, or nullptr (never allocates).
-uqc::Plan* find_plan(uqc_basis* B, double tau, int prec, double bound);
+uqc::Plan* find_plan(uqc_basis* B, double tau, int prec, double bound, double boys_t);
 
 namespace uqc {
 // A caller-chosen device workspace for a closed-shell Fock build: D' (nbf^2), the J and K accumulators (nbf^2 each),

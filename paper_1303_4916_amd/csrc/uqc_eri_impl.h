@@ -110,11 +110,12 @@ __device__ __forceinline__ int accumulate64(const BinDev& B, int bra, int kbn, c
 
 // accumulate64, or for MIXED the same loops with FP32 recursions (and the same SCR screen); returns the primitive
 // quartets evaluated per lane (wavefront-uniform).
+// MIXED: primitive quartets with Boys argument T <= t32 take the FP32 Boys table, the others the FP64 evaluation.
 template <class C, bool MIXED, bool BLDS = false, bool SCR = false>
 __device__ __forceinline__ int accumulate(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
                                           const double* __restrict__ boys64tab, const float* __restrict__ boys32tab,
                                           double* __restrict__ acc, const double2* btab = nullptr,
-                                          cdptr cqk = nullptr) {
+                                          cdptr cqk = nullptr, double t32 = (double)kBoysTmax32) {
     if constexpr (!MIXED) return accumulate64<C, BLDS, SCR>(B, bra, kbn, Kt, ket, kkn, boys64tab, btab, acc, cqk);
     const size_t npk = (size_t)Kt.np;
     const size_t fsk = (size_t)Kt.K * npk;
@@ -158,7 +159,7 @@ __device__ __forceinline__ int accumulate(const BinDev& B, int bra, int kbn, con
                 g.o2z = (float)o2z; g.roz = (float)roz; g.o2e = (float)o2e; g.roe = (float)roe;
                 g.o2ze = (float)(0.5 * inv);
                 float F[C::L + 1];
-                if (T <= (double)kBoysTmax32) {
+                if (T <= t32) {
                     boys32<C::L>(T, boys32tab, F);
                     const float pf = (float)pref;
 #pragma unroll
@@ -455,7 +456,7 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
 #pragma unroll
                 for (int x = 0; x < C::NACC; ++x) acc[x] = 0.0;
                 const int done = accumulate<C, MIXED, BLDS, true>(B, bra, kbn, Kt, kl, kkn, boys64tab, boys32tab, acc,
-                                                                  btab, cqk);
+                                                                  btab, cqk, tk.boys_t);
                 pcnt += (unsigned long long)__popcll(live) * (unsigned long long)done;
                 C::hrr(acc, bh[0], bh[1], bh[2], Kt.AB[kl], Kt.AB[Kt.np + kl],
                        Kt.AB[2 * Kt.np + kl], out);

@@ -37,7 +37,7 @@ template <class TC, bool MIXED>
 __device__ __forceinline__ int team_accumulate(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
                                                int q0, int q1, int q2, const double* __restrict__ boys64tab,
                                                const float* __restrict__ boys32tab, double* __restrict__ acc,
-                                               cdptr cq0, cdptr cq1) {
+                                               cdptr cq0, cdptr cq1, double t32) {
     const size_t npk = (size_t)Kt.np;
     const size_t fsk = (size_t)Kt.K * npk;
     const cdptr brec = as_const(B.rec) + (size_t)bra * B.K * kRec;  // wavefront-uniform: scalar loads
@@ -93,7 +93,7 @@ __device__ __forceinline__ int team_accumulate(const BinDev& B, int bra, int kbn
                 g.o2z = (float)o2z; g.roz = (float)roz; g.o2e = (float)o2e; g.roe = (float)roe;
                 g.o2ze = (float)(0.5 * inv);
                 float F[TC::L + 1];
-                if (T <= (double)kBoysTmax32) {
+                if (T <= t32) {
                     boys32<TC::L>(T, boys32tab, F);
                     const float pf = (float)pref;
 #pragma unroll
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
 #pragma unroll
             for (int x = 0; x < TC::NREP; ++x) acc[x] = 0.0;
             const int done = team_accumulate<TC, MIXED>(B, bra, kbn, Kt, kl, kkn, q0, q1, q2, boys64tab, boys32tab, acc,
-                                                        cq0, cq1);
+                                                        cq0, cq1, tk.boys_t);
             pcnt += (unsigned long long)(__popcll(live) / kTeam) * (unsigned long long)done;
 
             int src[kTeam];

@@ -74,6 +74,7 @@ struct TaskDev {
     long long nitems;
     double tau;                // a quartet in the range is computed iff Q_ab Q_cd >= tau
     double lo_excl, hi_incl;   //   and lo_excl < Q_ab Q_cd <= hi_incl (precision routing)
+    double boys_t;             // mixed tasks: primitive quartets with Boys argument T <= boys_t use the FP32 table
     unsigned long long* count; // quartets computed by this task (one atomic per wavefront)
     unsigned long long* pcount;  // primitive quartets computed by this task
     int nbra;

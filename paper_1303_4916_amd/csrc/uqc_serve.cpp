@@ -167,7 +167,8 @@ bool uqc_server::admit_one(Req* r) {
         retire(r, st, uqc_last_error());
         return false;
     }
-    r->plan = get_plan(r->basis, r->opts.schwarz_tau, r->opts.precision, r->opts.fp64_bound, &st);
+    r->plan = get_plan(r->basis, r->opts.schwarz_tau, r->opts.precision, r->opts.fp64_bound, r->opts.fp64_boys_T,
+                       &st);
     const size_t NN = (size_t)r->nbf * r->nbf;
     if (!r->plan) {
         retire(r, st, uqc_last_error());

@@ -46,7 +46,7 @@ class FockOpts(ctypes.Structure):
     _fields_ = [("schwarz_tau", ctypes.c_double), ("precision", ctypes.c_int), ("fp64_bound", ctypes.c_double),
                 ("timing", ctypes.c_int), ("progress", PROGRESS_FN), ("progress_user", ctypes.c_void_p),
                 ("max_items_per_launch", ctypes.c_longlong), ("exchange_scale", ctypes.c_double),
-                ("streams", ctypes.c_int)]
+                ("streams", ctypes.c_int), ("fp64_boys_T", ctypes.c_double)]
 
 
 class ScfOpts(ctypes.Structure):
@@ -208,12 +208,13 @@ def scf_opts(max_iter: int = 100, e_conv: float = 1e-10, d_conv: float = 1e-8, d
 
 def default_opts(tau: float = 1e-12, precision: int = FP64, fp64_bound: float = 1e-8, timing: bool = False,
                  progress=None, max_items_per_launch: int = 0, exchange_scale: float = 1.0,
-                 streams: int | None = None):
+                 streams: int | None = None, fp64_boys_T: float | None = None):
     """Fock-build options.  progress: None or a callable(class_id, items_done, items_total) called after every
     class sub-launch has completed on the device (on one stream the build then waits for each one).
     max_items_per_launch: cap on the work items of one class-kernel launch (0: the library default).
     exchange_scale: weight x of exchange (G = J - (x/2) K; spin densities G^s = J - x K^s).  streams: HIP streams
-    the class launches are spread over (None: the library default)."""
+    the class launches are spread over (None: the library default).  fp64_boys_T: mixed precision, Boys arguments
+    above it evaluated in FP64 (None: the library default, 30)."""
     o = FockOpts()
     load().uqc_fock_opts_default(ctypes.byref(o))
     o.schwarz_tau = float(tau)
@@ -224,6 +225,8 @@ def default_opts(tau: float = 1e-12, precision: int = FP64, fp64_bound: float = 
     o.exchange_scale = float(exchange_scale)
     if streams is not None:
         o.streams = int(streams)
+    if fp64_boys_T is not None:
+        o.fp64_boys_T = float(fp64_boys_T)
     if progress is not None:
         fn = PROGRESS_FN(lambda user, cid, done, total: progress(int(cid), int(done), int(total)))
         o.progress = fn

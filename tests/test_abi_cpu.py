@@ -35,8 +35,9 @@ def test_library_has_gfx950_code_object():
 def test_default_options():
     o = uqc.default_opts()
     assert o.schwarz_tau == 1e-12 and o.precision == uqc.FP64 and o.fp64_bound == 1e-8 and o.timing == 0
-    assert o.streams == 3
+    assert o.streams == 3 and o.fp64_boys_T == 30.0  # the last field: the Python mirror matches the C layout
     assert not o.progress and o.max_items_per_launch == 0 and o.exchange_scale == 1.0
+    assert uqc.default_opts(fp64_boys_T=12.5).fp64_boys_T == 12.5
 
 
 def test_null_arguments_rejected_before_device_use():

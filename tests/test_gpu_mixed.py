@@ -152,6 +152,30 @@ def test_mixed_fock_small_lattice_vs_oracle(small_lattice, bound):
     assert np.max(np.abs(G - G6)) <= G_MAX
 
 
+@pytest.mark.parametrize("boys_t", [0.0, 10.0, 30.0])
+def test_mixed_fock_boys_cutoff_option(small_lattice, boys_t):
+    """fp64_boys_T moves the FP32/FP64 split of the Boys evaluation (0: every Boys argument in FP64, 30: the FP32
+    table's whole range); at every setting the mixed build meets the same bounds against the oracle and the FP64
+    build, and a setting below 30 changes the result (it takes effect)."""
+    w, B, (Jr, Kr, Gr, E2r), (J6, K6, G6, st6) = small_lattice
+    D = w.densities[0]
+    J, K, G, st = B.fock_build(D, uqc.default_opts(tau=w.tau, precision=uqc.MIXED, fp64_boys_T=boys_t))
+    assert abs(st.E2 - E2r) <= E2_BOUND and abs(st.E2 - st6.E2) <= E2_BOUND
+    assert np.linalg.norm(G - G6) <= G_FROB * np.linalg.norm(G6)
+    assert np.max(np.abs(G - Gr)) <= 1e-6 * np.max(np.abs(Gr))
+    if boys_t < 30.0:
+        _, _, G30, _ = B.fock_build(D, uqc.default_opts(tau=w.tau, precision=uqc.MIXED))
+        assert np.any(G != G30)
+
+
+@pytest.mark.parametrize("boys_t", [-1.0, 30.5, float("nan")])
+def test_mixed_fock_boys_cutoff_out_of_range(small_lattice, boys_t):
+    w, B, _, _ = small_lattice
+    with pytest.raises(uqc.UqcError) as e:
+        B.fock_build(w.densities[0], uqc.default_opts(tau=w.tau, precision=uqc.MIXED, fp64_boys_T=boys_t))
+    assert e.value.status == uqc.UQC_E_ARG and "fp64_boys_T" in str(e.value)
+
+
 @pytest.fixture(scope="module")
 def mixed150(ctx):
     """150 atoms, N = 1650, first s shell K = 6, tau = 1e-12: one FP64 and one mixed build of the same density."""
