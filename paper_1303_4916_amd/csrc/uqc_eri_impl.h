@@ -226,27 +226,31 @@ __device__ __forceinline__ void contract_pair(const double* __restrict__ v, cons
 }
 
 // Work items of a launch of nitems items.  Workgroups are dealt to the kXcds dies round-robin (workgroup b runs on
-// die b mod kXcds).  The item list is cut into segments of kSegItems consecutive items, also dealt to the dies
-// round-robin, so items that read the same ket chunk mostly share one die's L2 while every die gets a like mix of
-// cheap and costly items (item costs drift along the list: a die owning one contiguous share of it finished long
-// before the others).  Inside a die the items are handed out one at a time from the die's counter in the launch's
-// queue (cleared before the launch), so a wavefront takes its next item when it finishes one: item costs are too
-// uneven for a fixed share per wavefront.  The host sizes the launch to the workgroups that fit on the chip at
-// once; a workgroup keeps its LDS until its last wavefront ends, which with one item per wavefront left most of the
-// LDS held by finished wavefronts.
+// die b mod kXcds).  The item list is cut into segments of consecutive items, also dealt to the dies round-robin,
+// so items that read the same ket chunk mostly share one die's L2 while every die gets a like mix of cheap and
+// costly items (item costs drift along the list: a die owning one contiguous share of it finished long before the
+// others).  A segment holds kSegItems items, fewer in launches too short to give every die eight segments (with a
+// single 256-item segment for a 300-item launch, one die did nearly all the work).  Inside a die the items are
+// handed out one at a time from the die's counter in the launch's queue (cleared before the launch), so a
+// wavefront takes its next item when it finishes one: item costs are too uneven for a fixed share per wavefront.
+// The host sizes the launch to the workgroups that fit on the chip at once; a workgroup keeps its LDS until its
+// last wavefront ends, which with one item per wavefront left most of the LDS held by finished wavefronts.
 constexpr long long kSegItems = 256;
 struct DieItems {
-    long long n;           // items of this die; its local item i is global item ((i / kSegItems) dies + die)
-    long long die, dies;   //   kSegItems + i % kSegItems
+    long long n;           // items of this die; its local item i is global item ((i / seg) dies + die) seg
+    long long die, dies;   //   + i % seg
+    long long seg;         // items per segment
     unsigned* counter;     // the die's counter in the launch's queue
 };
 __device__ __forceinline__ DieItems die_items(long long nitems, unsigned* queue) {
     const long long nb = gridDim.x;
     const long long dies = nb < kXcds ? nb : kXcds;  // dies holding workgroups
     const long long x = blockIdx.x % kXcds;
-    const long long full = nitems / kSegItems, tail = nitems % kSegItems;
-    const long long n = (full / dies + (x < full % dies ? 1 : 0)) * kSegItems + (x == full % dies ? tail : 0);
-    return {n, x, dies, queue + x};
+    long long seg = nitems / (8 * dies);
+    seg = seg < 1 ? 1 : (seg > kSegItems ? kSegItems : seg);
+    const long long full = nitems / seg, tail = nitems % seg;
+    const long long n = (full / dies + (x < full % dies ? 1 : 0)) * seg + (x == full % dies ? tail : 0);
+    return {n, x, dies, seg, queue + x};
 }
 // The wavefront's next local item (every lane gets the same value; n or more once the die's items are gone).
 __device__ __forceinline__ long long next_item(const DieItems& di) {
@@ -256,7 +260,7 @@ __device__ __forceinline__ long long next_item(const DieItems& di) {
     return (long long)(unsigned)__builtin_amdgcn_readfirstlane((int)t);
 }
 __device__ __forceinline__ long long global_item(const DieItems& di, long long i) {
-    return ((i / kSegItems) * di.dies + di.die) * kSegItems + i % kSegItems;
+    return ((i / di.seg) * di.dies + di.die) * di.seg + i % di.seg;
 }
 
 // Task holding launch-wide item `item` (task_begin ascending, task_begin[0] == 0).
