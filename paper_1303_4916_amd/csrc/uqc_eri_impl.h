@@ -580,8 +580,26 @@ __global__ __launch_bounds__(kBlock) void k_list(ListDev L, const double* __rest
                                                  const float* __restrict__ boys32tab) {
     using C = EriClass<LA, LB, LC, LD>;
     const int q = (int)(blockIdx.x * kBlock + threadIdx.x);
-    if (q >= L.n) return;
-    const int bra = L.bra_idx[q], ket = L.ket_idx[q];
+    int bra, ket, col = 0;
+    if constexpr (MODE == MODE_BATCH) {  // implicit quartet list, screened and counted here
+        const bool in = q < L.n;
+        const int p = in ? q / L.nket : 0, t = in ? q % L.nket : 0;
+        const int kp = in ? L.kpos[t] : 0;
+        const BinDev& PB = L.swap ? L.ket : L.bra;  // the physical bra and ket bins
+        const BinDev& PK = L.swap ? L.bra : L.ket;
+        const bool ok = in && PB.Q[p] * PK.Q[kp] >= L.tau;
+        const unsigned long long m = __ballot(ok);
+        if (threadIdx.x % kWave == 0 && m) atomicAdd(L.count, (unsigned long long)__popcll(m));
+        if (!ok) return;
+        bra = L.swap ? kp : p;
+        ket = L.swap ? p : kp;
+        col = L.col[t];
+    } else {
+        if (q >= L.n) return;
+        bra = L.bra_idx[q];
+        ket = L.ket_idx[q];
+        (void)col;
+    }
     double acc[C::NACC];
 #pragma unroll
     for (int x = 0; x < C::NACC; ++x) acc[x] = 0.0;
@@ -619,7 +637,7 @@ __global__ __launch_bounds__(kBlock) void k_list(ListDev L, const double* __rest
         const int oa = L.bra.off_a[bra], ob = L.bra.off_b[bra], oc = L.ket.off_a[ket], od = L.ket.off_b[ket];
         const bool sab = LA == LB && oa == ob, scd = LC == LD && oc == od;  // a pair of one shell: both orders
         const size_t N = (size_t)L.nbf, W = (size_t)L.ncols;              // already among its components
-        const size_t col0 = (size_t)L.col[q];
+        const size_t col0 = (size_t)col;
         double* T = L.out;
 #pragma unroll
         for (int i = 0; i < C::NA; ++i)

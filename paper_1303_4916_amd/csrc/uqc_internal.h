@@ -108,15 +108,22 @@ struct ListDev {
     int n;
     double* out;               // STORE: [n][NA*NB*NC*ND]; SCHWARZ: [n]; SCATTER: the nbf^4 tensor; BATCH: see Mode
     int nbf;                   // SCATTER and BATCH
-    const int* col;            // BATCH: [n] first column of the quartet's ket pair in the batch
+    // BATCH: the quartets are implicit, every pair p of the physical bra bin times the nket ket pairs kpos[t] of the
+    // physical ket bin (q = p nket + t, n = np nket), those with Q_p Q_kpos[t] >= tau computed and counted in
+    // *count (bra_idx and ket_idx unused)
+    const int* col;            // BATCH: [nket] first column of ket pair t in the batch
     int ncols;                 // BATCH: columns of the batch
     int swap;                  // BATCH: 1 if the kernel's bra pair is the physical ket pair (class order)
+    const int* kpos;           // BATCH: [nket] positions of the batch's ket pairs in the physical ket bin
+    int nket;
+    double tau;
+    unsigned long long* count;
 };
 
 // STORE: each quartet's block; SCHWARZ: sqrt of the largest diagonal element; SCATTER: every element of the block
 // written to the dense tensor out[((i nbf + j) nbf + k) nbf + l] at its eight permutationally equivalent places;
 // BATCH: every element (mu nu|lam sig) written to out[(mu nbf + nu) ncols + col(lam sig)] for both orders of the bra
-// pair and both orders of the ket pair, where the ket pair's columns start at col[q]: (lam in c, sig in d) at
+// pair and both orders of the ket pair, where the ket pair's columns start at col[t]: (lam in c, sig in d) at
 // col + k n_d + l, then, for c != d, (lam in d, sig in c) at col + n_c n_d + l n_c + k.
 enum Mode { MODE_STORE = 0, MODE_SCHWARZ = 1, MODE_SCATTER = 2, MODE_BATCH = 3 };
 

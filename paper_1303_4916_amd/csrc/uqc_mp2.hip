@@ -182,7 +182,19 @@ uqc_status uqc_mp2(uqc_basis* B, const double* C, const double* eps, int nocc, i
         double* T0b = (double*)tbuf.p;
         double* P = (double*)pbuf.p;
         int* dmap = (int*)mbuf.p;
+        // the quartet counter, then each batch's ket positions and columns (2 ints per ket pair of the widest batch)
+        size_t maxk = 1;
+        for (const auto& b : batches) maxk = std::max(maxk, b.size());
+        DevBuf kbuf;
+        if (hipMalloc(&kbuf.p, sizeof(unsigned long long) + 2 * maxk * sizeof(int)) != hipSuccess)
+            return uqc_fail(UQC_E_NOMEM, "uqc_mp2: batch ket lists");
+        unsigned long long* dcount = (unsigned long long*)kbuf.p;
+        int* dkp = (int*)(dcount + 1);
+        UQC_HIP(launch_zero((double*)dcount, 1, s));
         UQC_HIP(launch_zero(T1, nT1, s));
+        std::vector<double> qmax_bin(B->bins.size(), 0.0);  // largest pair bound of each bin
+        for (size_t X = 0; X < B->bins.size(); ++X)
+            for (int i = 0; i < B->bins[X].np; ++i) qmax_bin[X] = std::max(qmax_bin[X], B->bins[X].Q[i]);
         constexpr int kStreams = 3;
         hipStream_t S[kStreams] = {s, nullptr, nullptr};
         for (int k = 1; k < kStreams; ++k)
@@ -205,71 +217,57 @@ uqc_status uqc_mp2(uqc_basis* B, const double* C, const double* eps, int nocc, i
                         if (!same) map[k.col + nc * nd + y * nc + x] = (od + y) * N + (oc + x);
                     }
             }
-            // quartets: every bra shell pair (all bins) x every ket shell pair of the batch, in the kernel's class
-            // order (swap: the kernel's bra is the ket pair); segments per (kernel bra bin, kernel ket bin, swap),
-            // lanes running along the batch's ket pairs for one bra pair so that their columns are adjacent
-            struct Seg {
-                int kb, kk, swap;
-                size_t off;
-                int n;
-            };
-            std::vector<Seg> segs;
-            std::vector<int> hb, hk, hc;
+            // quartets: every bra shell pair (all bins) x every ket shell pair of the batch, one launch per (bra bin,
+            // ket bin) in the kernel's class order (swap: the kernel's bra is the ket pair), lanes running along the
+            // batch's ket pairs of the bin for one bra pair so that their columns are adjacent; the kernels screen
+            // and count the quartets themselves from the batch's ket positions and columns per bin
             std::vector<std::vector<const KetPair*>> by_bin(B->bins.size());
             for (const KetPair& k : kp) by_bin[k.bin].push_back(&k);
-            for (size_t X = 0; X < B->bins.size(); ++X) {
-                const Bin& bx = B->bins[X];
-                for (size_t Y = 0; Y < B->bins.size(); ++Y) {
-                    if (by_bin[Y].empty()) continue;
-                    const Bin& by = B->bins[Y];
-                    const int swap = class_index(bx.la, bx.lb, by.la, by.lb) < 0 ? 1 : 0;  // not in class order
-                    const size_t off = hb.size();
-                    for (int p = 0; p < bx.np; ++p)
-                        for (const KetPair* k : by_bin[Y])
-                            if (bx.Q[p] * by.Q[k->pos] >= tau) {
-                                hb.push_back(swap ? k->pos : p);
-                                hk.push_back(swap ? p : k->pos);
-                                hc.push_back(k->col);
-                            }
-                    if (hb.size() > off)
-                        segs.push_back(Seg{swap ? (int)Y : (int)X, swap ? (int)X : (int)Y, swap, off,
-                                           (int)(hb.size() - off)});
+            std::vector<int> hk(2 * kp.size());  // per ket bin in turn: positions, then (after all) columns
+            std::vector<size_t> koff(B->bins.size(), 0);
+            size_t nk = 0;
+            for (size_t Y = 0; Y < B->bins.size(); ++Y) {
+                koff[Y] = nk;
+                for (const KetPair* k : by_bin[Y]) {
+                    hk[nk] = k->pos;
+                    hk[kp.size() + nk] = k->col;
+                    ++nk;
                 }
             }
-            const size_t total = hb.size();
-            quartets += (long long)total;
-            DevBuf ib;
-            if (hipMalloc(&ib.p, 3 * std::max<size_t>(total, 1) * sizeof(int)) != hipSuccess)
-                return uqc_fail(UQC_E_NOMEM, "uqc_mp2: quartet list");
-            int* dbra = (int*)ib.p;
-            int* dket = dbra + total;
-            int* dcol = dket + total;
-            if (total) {
-                UQC_HIP(hipMemcpyAsync(dbra, hb.data(), total * sizeof(int), hipMemcpyHostToDevice, s));
-                UQC_HIP(hipMemcpyAsync(dket, hk.data(), total * sizeof(int), hipMemcpyHostToDevice, s));
-                UQC_HIP(hipMemcpyAsync(dcol, hc.data(), total * sizeof(int), hipMemcpyHostToDevice, s));
-            }
+            UQC_HIP(hipMemcpyAsync(dkp, hk.data(), hk.size() * sizeof(int), hipMemcpyHostToDevice, s));
             UQC_HIP(hipMemcpyAsync(dmap, map.data(), ncols * sizeof(int), hipMemcpyHostToDevice, s));
             UQC_HIP(launch_zero(T0b, NN * (size_t)ncols, s));
             // the class launches side by side (the batch positions they write are disjoint)
             UQC_HIP(hipEventRecord(ctx->fork, s));
             for (int k = 1; k < kStreams; ++k) UQC_HIP(hipStreamWaitEvent(S[k], ctx->fork, 0));
-            for (size_t i = 0; i < segs.size(); ++i) {
-                const Seg& g = segs[i];
-                const Bin &bb = B->bins[g.kb], &bk = B->bins[g.kk];
-                ListDev L{};
-                L.bra = bb.dev;
-                L.ket = bk.dev;
-                L.bra_idx = dbra + g.off;
-                L.ket_idx = dket + g.off;
-                L.col = dcol + g.off;
-                L.n = g.n;
-                L.out = T0b;
-                L.nbf = N;
-                L.ncols = ncols;
-                L.swap = g.swap;
-                UQC_HIP(launch_list(class_index(bb.la, bb.lb, bk.la, bk.lb), false, MODE_BATCH, L, ctx->boys64,
-                                    ctx->boys32, S[i % kStreams]));
+            std::vector<double> kqmax(B->bins.size(), 0.0);  // largest bound among the batch's kets of each bin
+            for (const KetPair& k : kp) kqmax[k.bin] = std::max(kqmax[k.bin], B->bins[k.bin].Q[k.pos]);
+            size_t seg = 0;
+            for (size_t X = 0; X < B->bins.size(); ++X) {
+                const Bin& bx = B->bins[X];
+                for (size_t Y = 0; Y < B->bins.size(); ++Y) {
+                    if (by_bin[Y].empty() || bx.np == 0 || qmax_bin[X] * kqmax[Y] < tau) continue;
+                    const Bin& by = B->bins[Y];
+                    const int swap = class_index(bx.la, bx.lb, by.la, by.lb) < 0 ? 1 : 0;  // not in class order
+                    const Bin &bb = swap ? by : bx, &bk = swap ? bx : by;
+                    const long long n = (long long)bx.np * (long long)by_bin[Y].size();
+                    if (n > 0x7fffffffLL) return uqc_fail(UQC_E_UNSUPPORTED, "uqc_mp2: too many quartets per launch");
+                    ListDev L{};
+                    L.bra = bb.dev;
+                    L.ket = bk.dev;
+                    L.n = (int)n;
+                    L.out = T0b;
+                    L.nbf = N;
+                    L.ncols = ncols;
+                    L.swap = swap;
+                    L.kpos = dkp + koff[Y];
+                    L.col = dkp + kp.size() + koff[Y];
+                    L.nket = (int)by_bin[Y].size();
+                    L.tau = tau;
+                    L.count = dcount;
+                    UQC_HIP(launch_list(class_index(bb.la, bb.lb, bk.la, bk.lb), false, MODE_BATCH, L, ctx->boys64,
+                                        ctx->boys32, S[seg++ % kStreams]));
+                }
             }
             for (int k = 1; k < kStreams; ++k) {
                 UQC_HIP(hipEventRecord(ctx->join[k - 1], S[k]));
@@ -288,9 +286,12 @@ uqc_status uqc_mp2(uqc_basis* B, const double* C, const double* eps, int nocc, i
                 hipLaunchKernelGGL(k_mp2_place, dim3(grid), dim3(kBlock), 0, s, P, dmap, ncols, N, o, T1);
                 UQC_HIP(hipGetLastError());
             }
-            UQC_HIP(hipStreamSynchronize(s));  // the batch's lists are freed at the end of this iteration
+            UQC_HIP(hipStreamSynchronize(s));  // the batch's ket lists are rewritten by the next batch
             q1_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tq).count();
         }
+        unsigned long long nq = 0;
+        UQC_HIP(hipMemcpy(&nq, dcount, sizeof(nq), hipMemcpyDeviceToHost));
+        quartets = (long long)nq;
     }
     const auto t1 = std::chrono::steady_clock::now();
 
