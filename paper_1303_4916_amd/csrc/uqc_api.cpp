@@ -808,6 +808,11 @@ void uqc::plan_account(Plan& p) {
 // classes measured faster with larger groups (the item's ket loads, J_cd flush and task lookup spread over more bra
 // pairs, at the price of fewer wavefronts): (ds|ss), (dp|ss), (dd|ss), (ds|ds), (ds|pp), (dp|ds) take 16 (32 is
 // slower); the team kernels of (dp|dp) and (dd|dp) take 8, (dd|ds) 12.
+// A task (bin pair and precision) with few (bra pair, ket chunk) entries gets smaller groups, down to one bra pair,
+// so that it still has about kItemTarget items: a small molecule's class launch would otherwise occupy a fraction
+// of the resident wavefronts, each for the whole length of one long item.
+constexpr long long kItemTarget = 2048;
+
 static int group_bras(int cls) {
     int la, lb, lc, ld;
     class_ls(cls, &la, &lb, &lc, &ld);
@@ -878,7 +883,7 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, double boys_t, 
             std::iota(by_a.begin(), by_a.end(), 0);
             std::stable_sort(by_a.begin(), by_a.end(), [&](int x, int y) { return bx.off_a[x] < bx.off_a[y]; });
             const int S = class_team(cls) ? kTeamKets : kWave;
-            const int GB = group_bras(cls);
+            const int GB0 = group_bras(cls);
             for (HostTask* t : {&t64, &t32}) {
                 if (t->mixed && !mixed) continue;
                 int nch = 0;
@@ -894,6 +899,7 @@ Plan* get_plan(uqc_basis* B, double tau, int prec, double bound, double boys_t, 
                     return nullptr;
                 }
                 t->blist.resize(start[nch]);
+                const int GB = (int)std::max(1LL, std::min((long long)GB0, start[nch] / kItemTarget));
                 std::vector<long long> fill(start.begin(), start.end() - 1);
                 for (int i : by_a)
                     if (t->hi[i] > t->lo[i])
