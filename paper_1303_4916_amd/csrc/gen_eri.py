@@ -648,6 +648,10 @@ def main(outdir):
         th.append("  }")
         th.append("  static constexpr int NOUT = %d;  // representative outputs held by a lane" % len(t["out_reps"]))
         th.append("  static constexpr bool STREAM = %s;" % ("true" if c in TEAM_STREAM_DIGEST else "false"))
+        cab = [comps(x) for x in c]
+        th.append("  // frame component indices (a, b, c, d) of each representative output (the order of hrr's out)")
+        th.append("  static constexpr unsigned char OUT_IDX[%d][4] = {%s};" % (len(t["out_reps"]), ", ".join(
+            "{%s}" % ", ".join(str(cab[x].index(o[x])) for x in range(4)) for o in t["out_reps"])))
         if c in TEAM_STREAM_DIGEST:
             th.append("  __device__ static __forceinline__ void hrr_digest(const double* __restrict__ acc, "
                       "const int* __restrict__ src, int pidx, double w, double ABx, double ABy, double ABz, "

@@ -32,8 +32,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Contracted representative accumulators of one lane: the recursion of class TC with the geometry relabelled by
 // the axis permutation (q0, q1, q2).  The primitive screen of accumulate64 (SCR) with the ket bound at position kk
 // taken as the larger of the rows cq0, cq1 of Kt.cq (the 64-pair chunks that hold the item's ten kets).  Returns
-// the primitive quartets evaluated per lane (wavefront-uniform).
-template <class TC, bool MIXED>
+// the primitive quartets evaluated per lane (wavefront-uniform).  SCR false: every primitive quartet (cq0, cq1
+// unused).
+template <class TC, bool MIXED, bool SCR = true>
 __device__ __forceinline__ int team_accumulate(const BinDev& B, int bra, int kbn, const BinDev& Kt, int ket, int kkn,
                                                int q0, int q1, int q2, const double* __restrict__ boys64tab,
                                                const float* __restrict__ boys32tab, double* __restrict__ acc,
@@ -43,7 +44,7 @@ __device__ __forceinline__ int team_accumulate(const BinDev& B, int bra, int kbn
     const cdptr brec = as_const(B.rec) + (size_t)bra * B.K * kRec;  // wavefront-uniform: scalar loads
     int nb = kbn, done = 0;
     for (int kk = 0; kk < kkn; ++kk) {
-        {
+        if constexpr (SCR) {
             const double qf = fmax(cq0[kk], cq1[kk]);
             while (nb > 0 && brec[(nb - 1) * kRec + kRecQ] * qf <= kPrimEps) --nb;
             if (nb == 0) break;
@@ -510,6 +511,89 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
         }
         wave_lds_sync();  // the next item clears the wavefront's LDS blocks
     }  // items
+}
+
+// k_list's BATCH form (implicit quartets of the physical bra bin x the batch's ket pairs of the physical ket bin,
+// each (mu nu|lam sig) stored at its row and columns of the batch buffer) for the team classes whose representative
+// outputs a lane holds (STREAM false): ten quartets per wavefront, lane 6t+p evaluating quartet t with the axes
+// relabelled by permutation p (every primitive, no primitive screen), then storing the outputs it owns at their true
+// component indices.  The other lanes' copies of an output are zero (the owner mask of hrr), and so are outputs that
+// vanish; the buffer is zero beforehand, so zeros are not stored and every element is written by one lane.
+template <int LA, int LB, int LC, int LD>
+__global__ __launch_bounds__(kBlock) void k_list_team_batch(ListDev L, const double* __restrict__ boys64tab) {
+    using TC = TeamClass<LA, LB, LC, LD>;
+    static_assert(!TC::STREAM, "the batch form holds the lane's representative outputs");
+    constexpr int NA = TC::NA, NB = TC::NB, NC = TC::NC, ND = TC::ND;
+    const int lane = (int)(threadIdx.x % kWave);
+    const int team = lane / kTeam;
+    const int pidx = lane - team * kTeam;  // lanes 60..63 (team 10): 0..3, idle
+    const long long wave = ((long long)blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const long long q = wave * kTeamsPerWave + team;
+    const bool in = team < kTeamsPerWave && q < L.n;
+    const int qq = in ? (int)q : 0;  // idle lanes evaluate quartet 0 and store nothing
+    const int p = qq / L.nket, t = qq % L.nket;
+    const int kp = L.kpos[t];
+    const BinDev& PB = L.swap ? L.ket : L.bra;  // the physical bra and ket bins
+    const BinDev& PK = L.swap ? L.bra : L.ket;
+    const bool ok = in && PB.Q[p] * PK.Q[kp] >= L.tau;
+    const unsigned long long m = __ballot(ok && pidx == 0);
+    if (m == 0ULL) return;  // wavefront-uniform
+    if (lane == 0) atomicAdd(L.count, (unsigned long long)__popcll(m));
+    const int bra = L.swap ? kp : p, ket = L.swap ? p : kp;
+    const int q0 = kPermAxes[pidx][0], q1 = kPermAxes[pidx][1], q2 = kPermAxes[pidx][2];
+    double acc[TC::NREP];
+#pragma unroll
+    for (int x = 0; x < TC::NREP; ++x) acc[x] = 0.0;
+    team_accumulate<TC, false, false>(L.bra, bra, L.bra.K, L.ket, ket, L.ket.K, q0, q1, q2, boys64tab, nullptr, acc,
+                                      nullptr, nullptr, 0.0);
+    int src[kTeam];
+#pragma unroll
+    for (int x = 0; x < kTeam; ++x) src[x] = team * kTeam + kPermCompose[pidx][x];
+    double out[TC::NOUT];
+    {
+        const double* ab = L.bra.AB;
+        const double* cd = L.ket.AB;
+        const size_t nb = (size_t)L.bra.np, nk = (size_t)L.ket.np;
+        const double ABx = sel3(ab[bra], ab[nb + bra], ab[2 * nb + bra], q0);
+        const double ABy = sel3(ab[bra], ab[nb + bra], ab[2 * nb + bra], q1);
+        const double ABz = sel3(ab[bra], ab[nb + bra], ab[2 * nb + bra], q2);
+        const double CDx = sel3(cd[ket], cd[nk + ket], cd[2 * nk + ket], q0);
+        const double CDy = sel3(cd[ket], cd[nk + ket], cd[2 * nk + ket], q1);
+        const double CDz = sel3(cd[ket], cd[nk + ket], cd[2 * nk + ket], q2);
+        TC::hrr(acc, src, pidx, 1.0, ABx, ABy, ABz, CDx, CDy, CDz, out);
+    }
+    if (!ok) return;
+    const int oa = L.bra.off_a[bra], ob = L.bra.off_b[bra], oc = L.ket.off_a[ket], od = L.ket.off_b[ket];
+    const bool sab = LA == LB && oa == ob, scd = LC == LD && oc == od;  // a pair of one shell: both orders
+    const size_t N = (size_t)L.nbf, W = (size_t)L.ncols, col0 = (size_t)L.col[t];
+    double* T = L.out;
+#pragma unroll
+    for (int n = 0; n < TC::NOUT; ++n) {
+        const double o = out[n];
+        if (o == 0.0) continue;
+        const int i = kPermComp[LA][pidx][TC::OUT_IDX[n][0]], j = kPermComp[LB][pidx][TC::OUT_IDX[n][1]];
+        const int k = kPermComp[LC][pidx][TC::OUT_IDX[n][2]], l = kPermComp[LD][pidx][TC::OUT_IDX[n][3]];
+        const double v = o * (comp_factor(LA, i) * comp_factor(LB, j) * comp_factor(LC, k) * comp_factor(LD, l));
+        if (!L.swap) {  // rows from the kernel's bra pair, columns from its ket pair
+            const size_t r1 = (oa + i) * N + (ob + j), r2 = (ob + j) * N + (oa + i);
+            const size_t c1 = col0 + k * ND + l, c2 = col0 + NC * ND + l * NC + k;
+            T[r1 * W + c1] = v;
+            if (!scd) T[r1 * W + c2] = v;
+            if (!sab) {
+                T[r2 * W + c1] = v;
+                if (!scd) T[r2 * W + c2] = v;
+            }
+        } else {  // rows from the kernel's ket pair, columns from its bra pair
+            const size_t r1 = (oc + k) * N + (od + l), r2 = (od + l) * N + (oc + k);
+            const size_t c1 = col0 + i * NB + j, c2 = col0 + NA * NB + j * NA + i;
+            T[r1 * W + c1] = v;
+            if (!sab) T[r1 * W + c2] = v;
+            if (!scd) {
+                T[r2 * W + c1] = v;
+                if (!sab) T[r2 * W + c2] = v;
+            }
+        }
+    }
 }
 
 }  // namespace uqc
