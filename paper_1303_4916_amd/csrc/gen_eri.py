@@ -396,6 +396,7 @@ def gen_team(c):
     masks = []
     stream = []   # the same outputs, each digested at once into all six partial blocks (streaming form)
     stream_lds = []  # streaming form against the team's LDS copies of the density slices and partial blocks
+    emits = []  # each output handed to a caller's functor as soon as it is formed: e(output index, weighted value)
     for o in out_reps:
         a, b, cx, d = o
         terms = []
@@ -424,6 +425,7 @@ def gen_team(c):
         masks.append(mask)
         wexpr = "w" if mask == (1 << TEAM_SIZE) - 1 else "(((%d >> pidx) & 1) ? w : 0.0)" % mask
         hl.append("out[%d] = (%s) * %s;" % (len(masks) - 1, expr, wexpr))
+        emits.append("e(%d, (%s) * %s);" % (len(masks) - 1, expr, wexpr))
         i, j, k, l = ia[a], ib[b], ic[cx], idd[d]
         stream.append("{ const double x = (%s) * %s;" % (expr, wexpr))
         stream.append("  jab[%d] = fma(x, dcd[%d], jab[%d]); jcd[%d] = fma(x, dab[%d], jcd[%d]);"
@@ -473,18 +475,20 @@ def gen_team(c):
     # the streaming form shares the memoised intermediate lines of the horizontal recursion
     hrr_stream = [x for x in hl if not x.startswith("out[")]
     pos = 0
-    merged, merged_lds = [], []
+    merged, merged_lds, merged_emit = [], [], []
     for x in hl:
         if x.startswith("out["):
             merged += stream[4 * pos:4 * pos + 4]
             merged_lds += stream_lds[4 * pos:4 * pos + 4]
+            merged_emit.append(emits[pos])
             pos += 1
         else:
             merged.append(x)
             merged_lds.append(x)
+            merged_emit.append(x)
     return {"vrr": vrr_lines, "nrep": len(reps), "reps": reps, "out_reps": out_reps, "hrr": hl,
-            "digest": digest, "hrr_digest": merged, "hrr_digest_lds": merged_lds, "masks": masks, "v": v,
-            "hrr_flops": flops[0]}
+            "digest": digest, "hrr_digest": merged, "hrr_digest_lds": merged_lds, "hrr_emit": merged_emit,
+            "masks": masks, "v": v, "hrr_flops": flops[0]}
 
 
 def perm_comp_table():
@@ -678,6 +682,15 @@ def main(outdir):
                 th.append("    " + line)
             th.append("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz; (void)src; (void)pidx;")
             th.append("  }")
+        # the same outputs handed one by one to e(n, value) as they are formed (nothing held for all of them)
+        th.append("  template <class E>")
+        th.append("  __device__ static __forceinline__ void hrr_emit(const double* __restrict__ acc, "
+                  "const int* __restrict__ src, int pidx, double w, double ABx, double ABy, double ABz, "
+                  "double CDx, double CDy, double CDz, E& e) {")
+        for line in t["hrr_emit"]:
+            th.append("    " + line)
+        th.append("    (void)ABx; (void)ABy; (void)ABz; (void)CDx; (void)CDy; (void)CDz; (void)src; (void)pidx;")
+        th.append("  }")
         th.append("  __device__ static __forceinline__ void hrr(const double* __restrict__ acc, "
                   "const int* __restrict__ src, int pidx, double w, double ABx, double ABy, double ABz, "
                   "double CDx, double CDy, double CDz, double* __restrict__ out) {")

@@ -70,19 +70,11 @@ static hipError_t launch_digest_cls(bool mixed, int nspin, const TaskDev* d_task
 }
 
 #if UQC_TEAM
-// The MP2 batch form of a team class that holds its representative outputs (ten quartets per wavefront); false
-// for the streaming classes, which take the one-lane kernel.
-template <class TC>
-static bool launch_team_batch(const ListDev& L, const double* b64, hipStream_t s) {
-    if constexpr (TC::STREAM) {
-        return false;
-    } else {
-        const long long waves = ((long long)L.n + kTeamsPerWave - 1) / kTeamsPerWave;
-        const unsigned nblocks = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
-        hipLaunchKernelGGL((k_list_team_batch<UQC_LA, UQC_LB, UQC_LC, UQC_LD>), dim3(nblocks), dim3(kBlock), 0, s, L,
-                           b64);
-        return true;
-    }
+// The MP2 batch form of a team class: ten quartets per wavefront.
+static void launch_team_batch(const ListDev& L, const double* b64, hipStream_t s) {
+    const long long waves = ((long long)L.n + kTeamsPerWave - 1) / kTeamsPerWave;
+    const unsigned nblocks = (unsigned)((waves + kBlock / kWave - 1) / (kBlock / kWave));
+    hipLaunchKernelGGL((k_list_team_batch<UQC_LA, UQC_LB, UQC_LC, UQC_LD>), dim3(nblocks), dim3(kBlock), 0, s, L, b64);
 }
 #endif
 
@@ -90,8 +82,10 @@ static hipError_t launch_list_cls(bool mixed, int mode, const ListDev& L, const 
                                   hipStream_t s) {
     if (L.n <= 0) return hipSuccess;
 #if UQC_TEAM
-    if (mode == MODE_BATCH && launch_team_batch<TeamClass<UQC_LA, UQC_LB, UQC_LC, UQC_LD>>(L, b64, s))
+    if (mode == MODE_BATCH) {
+        launch_team_batch(L, b64, s);
         return hipGetLastError();
+    }
 #endif
     const unsigned nblocks = (unsigned)((L.n + kBlock - 1) / kBlock);
     if (mode == MODE_SCHWARZ)

@@ -514,15 +514,14 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest_team(const Tas
 }
 
 // k_list's BATCH form (implicit quartets of the physical bra bin x the batch's ket pairs of the physical ket bin,
-// each (mu nu|lam sig) stored at its row and columns of the batch buffer) for the team classes whose representative
-// outputs a lane holds (STREAM false): ten quartets per wavefront, lane 6t+p evaluating quartet t with the axes
-// relabelled by permutation p (every primitive, no primitive screen), then storing the outputs it owns at their true
-// component indices.  The other lanes' copies of an output are zero (the owner mask of hrr), and so are outputs that
+// each (mu nu|lam sig) stored at its row and columns of the batch buffer) for the team classes: ten quartets per
+// wavefront, lane 6t+p evaluating quartet t with the axes relabelled by permutation p (every primitive, no
+// primitive screen), then storing each output it owns at its true component indices as soon as the horizontal
+// recursion forms it.  The other lanes' copies of an output are zero (the owner mask), and so are outputs that
 // vanish; the buffer is zero beforehand, so zeros are not stored and every element is written by one lane.
 template <int LA, int LB, int LC, int LD>
 __global__ __launch_bounds__(kBlock) void k_list_team_batch(ListDev L, const double* __restrict__ boys64tab) {
     using TC = TeamClass<LA, LB, LC, LD>;
-    static_assert(!TC::STREAM, "the batch form holds the lane's representative outputs");
     constexpr int NA = TC::NA, NB = TC::NB, NC = TC::NC, ND = TC::ND;
     const int lane = (int)(threadIdx.x % kWave);
     const int team = lane / kTeam;
@@ -549,32 +548,26 @@ __global__ __launch_bounds__(kBlock) void k_list_team_batch(ListDev L, const dou
     int src[kTeam];
 #pragma unroll
     for (int x = 0; x < kTeam; ++x) src[x] = team * kTeam + kPermCompose[pidx][x];
-    double out[TC::NOUT];
-    {
-        const double* ab = L.bra.AB;
-        const double* cd = L.ket.AB;
-        const size_t nb = (size_t)L.bra.np, nk = (size_t)L.ket.np;
-        const double ABx = sel3(ab[bra], ab[nb + bra], ab[2 * nb + bra], q0);
-        const double ABy = sel3(ab[bra], ab[nb + bra], ab[2 * nb + bra], q1);
-        const double ABz = sel3(ab[bra], ab[nb + bra], ab[2 * nb + bra], q2);
-        const double CDx = sel3(cd[ket], cd[nk + ket], cd[2 * nk + ket], q0);
-        const double CDy = sel3(cd[ket], cd[nk + ket], cd[2 * nk + ket], q1);
-        const double CDz = sel3(cd[ket], cd[nk + ket], cd[2 * nk + ket], q2);
-        TC::hrr(acc, src, pidx, 1.0, ABx, ABy, ABz, CDx, CDy, CDz, out);
-    }
-    if (!ok) return;
+    int pcA[NA], pcB[NB], pcC[NC], pcD[ND];  // frame component -> true component
+#pragma unroll
+    for (int k = 0; k < NA; ++k) pcA[k] = kPermComp[LA][pidx][k];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) pcB[k] = kPermComp[LB][pidx][k];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) pcC[k] = kPermComp[LC][pidx][k];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) pcD[k] = kPermComp[LD][pidx][k];
     const int oa = L.bra.off_a[bra], ob = L.bra.off_b[bra], oc = L.ket.off_a[ket], od = L.ket.off_b[ket];
     const bool sab = LA == LB && oa == ob, scd = LC == LD && oc == od;  // a pair of one shell: both orders
-    const size_t N = (size_t)L.nbf, W = (size_t)L.ncols, col0 = (size_t)L.col[t];
+    const size_t N = (size_t)L.nbf, W = (size_t)L.ncols, col0 = ok ? (size_t)L.col[t] : 0;
     double* T = L.out;
-#pragma unroll
-    for (int n = 0; n < TC::NOUT; ++n) {
-        const double o = out[n];
-        if (o == 0.0) continue;
-        const int i = kPermComp[LA][pidx][TC::OUT_IDX[n][0]], j = kPermComp[LB][pidx][TC::OUT_IDX[n][1]];
-        const int k = kPermComp[LC][pidx][TC::OUT_IDX[n][2]], l = kPermComp[LD][pidx][TC::OUT_IDX[n][3]];
+    const bool swap = L.swap != 0;
+    const auto put = [&](int n, double o) {
+        if (!ok || o == 0.0) return;
+        const int i = pcA[TC::OUT_IDX[n][0]], j = pcB[TC::OUT_IDX[n][1]];
+        const int k = pcC[TC::OUT_IDX[n][2]], l = pcD[TC::OUT_IDX[n][3]];
         const double v = o * (comp_factor(LA, i) * comp_factor(LB, j) * comp_factor(LC, k) * comp_factor(LD, l));
-        if (!L.swap) {  // rows from the kernel's bra pair, columns from its ket pair
+        if (!swap) {  // rows from the kernel's bra pair, columns from its ket pair
             const size_t r1 = (oa + i) * N + (ob + j), r2 = (ob + j) * N + (oa + i);
             const size_t c1 = col0 + k * ND + l, c2 = col0 + NC * ND + l * NC + k;
             T[r1 * W + c1] = v;
@@ -593,7 +586,17 @@ __global__ __launch_bounds__(kBlock) void k_list_team_batch(ListDev L, const dou
                 if (!sab) T[r2 * W + c2] = v;
             }
         }
-    }
+    };
+    const double* ab = L.bra.AB;
+    const double* cd = L.ket.AB;
+    const size_t nb = (size_t)L.bra.np, nk = (size_t)L.ket.np;
+    const double ABx = sel3(ab[bra], ab[nb + bra], ab[2 * nb + bra], q0);
+    const double ABy = sel3(ab[bra], ab[nb + bra], ab[2 * nb + bra], q1);
+    const double ABz = sel3(ab[bra], ab[nb + bra], ab[2 * nb + bra], q2);
+    const double CDx = sel3(cd[ket], cd[nk + ket], cd[2 * nk + ket], q0);
+    const double CDy = sel3(cd[ket], cd[nk + ket], cd[2 * nk + ket], q1);
+    const double CDz = sel3(cd[ket], cd[nk + ket], cd[2 * nk + ket], q2);
+    TC::hrr_emit(acc, src, pidx, 1.0, ABx, ABy, ABz, CDx, CDy, CDz, put);
 }
 
 }  // namespace uqc
