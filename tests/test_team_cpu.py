@@ -247,3 +247,80 @@ def test_team_stream_lds_digest_matches_oracle(c, with_j):
             assert not np.any(tot[k]), k
             continue
         assert np.max(np.abs(tot[k] - refd[k])) <= 1e-12 * max(np.max(np.abs(refd[k])), 1e-300), k
+
+
+@pytest.mark.parametrize("c", gen.TEAM_CLASSES, ids=gen.cname)
+def test_team_emit_stores_match_oracle(c):
+    """The per-output form used for the MP2 batch stores (hrr_emit): each lane hands every representative output to
+    e(n, value) as it is formed; the device stores the nonzero ones at the true components of the frame indices
+    OUT_IDX[n] (the order of out_reps).  Emulated for the six lanes: the stored elements cover the true block once,
+    with the oracle's values, and the copies of the non-owning lanes are zero."""
+    la, lb, lc, ld = c
+    t = gen.gen_team(c)
+    rng = np.random.default_rng(sum(x * 5 ** i for i, x in enumerate(c)) + 7)
+    cen = rng.uniform(-1.5, 1.5, size=(4, 3))
+    ex = np.exp(rng.uniform(math.log(0.3), math.log(5.0), size=4))
+    sh = wl.Shells(np.array(c, np.int32), np.ones(4, np.int32), cen, ex, np.ones(4), np.arange(4, dtype=np.int32))
+    ref = oracle.Basis(sh).eri(0, 1, 2, 3)
+    comps = [gen.comps(l) for l in c]
+    scale = np.einsum("i,j,k,l->ijkl", *[np.array([_norm(ex[s], cp) for cp in comps[s]]) for s in range(4)])
+    raw_ref = ref / scale
+    geo = _geometry(*cen, *ex)
+    L = la + lb + lc + ld
+    vrr_code = "\n".join(re.sub(r"^const (T|double) ", "", x).rstrip(";").replace("(double)", "") for x in t["vrr"])
+    accs = []
+    for p in gen.PERMS:
+        env = _lane_env(geo, p, L)
+        env["acc"] = np.zeros(t["nrep"])
+        exec(vrr_code, env)
+        accs.append(env["acc"])
+    comp_tab = [[gen.PERMS.index(gen.perm_compose(p, q)) for q in gen.PERMS] for p in gen.PERMS]
+    pc_tab = gen.perm_comp_table()
+    # the frame component indices the generator writes as OUT_IDX
+    out_idx = [tuple(comps[s].index(o[s]) for s in range(4)) for o in t["out_reps"]]
+    code = []
+    for line in t["hrr_emit"]:
+        line = re.sub(r"^const double ", "", line).rstrip(";")
+        line = re.sub(r"fetch\(acc\[(\d+)\], src\[(\d+)\]\)", r"_acc[src[\2]][\1]", line)
+        line = re.sub(r"\(\(\((\d+) >> pidx\) & 1\) \? w : 0\.0\)", r"(w if ((\1 >> pidx) & 1) else 0.0)", line)
+        code.append(line)
+    assert sum(1 for x in code if x.startswith("e(")) == len(t["out_reps"])
+    written = np.zeros(raw_ref.shape, dtype=int)
+    got = np.zeros(raw_ref.shape)
+    for ip, p in enumerate(gen.PERMS):
+        env = _lane_env(geo, p, L)
+        env.update({"acc": accs[ip], "src": comp_tab[ip], "pidx": ip, "w": 1.0, "_acc": accs})
+        pcs = [pc_tab[l][ip] for l in c]
+        seen = []
+
+        def e(n, v, ip=ip, pcs=pcs, seen=seen):
+            seen.append(n)
+            owner = (t["masks"][n] >> ip) & 1
+            if not owner:
+                assert v == 0.0
+            if v == 0.0:  # not stored (the buffer is zero beforehand)
+                return
+            idx = tuple(pcs[s][out_idx[n][s]] for s in range(4))
+            written[idx] += 1
+            got[idx] = v
+
+        env["e"] = e
+        exec("\n".join(code), env)
+        assert seen == list(range(len(t["out_reps"])))
+    tol = 1e-12 * np.max(np.abs(raw_ref))
+    assert np.all(written <= 1)
+    assert np.all((written == 1) | (np.abs(raw_ref) <= tol))  # an element never stored is a vanishing integral
+    assert np.max(np.abs(got - raw_ref)) <= tol
+
+
+def test_generated_headers_are_current(tmp_path):
+    """The committed generated headers (recursions, team forms with their OUT_IDX tables, FLOP tables) are what
+    the generator writes now, byte for byte."""
+    gen.main(str(tmp_path))
+    made = sorted(os.listdir(tmp_path))
+    assert made
+    for name in made:
+        with open(os.path.join(tmp_path, name), "rb") as f:
+            new = f.read()
+        with open(os.path.join(ROOT, "paper_1303_4916_amd", "csrc", "generated", name), "rb") as f:
+            assert f.read() == new, name
