@@ -719,7 +719,9 @@ def bench_mp2(a):
            "ao_ms": m["ao_ms"], "transform_ms": m["transform_ms"], "energy_ms": m["energy_ms"],
            "ao_quartets": m["quartets"], "transform_flops": m["transform_flops"],
            "roofline_transform": {"bound": "mfma", "achieved": tf, "peak": 78.6, "unit": "TFLOP/s",
-                                  "frac": tf / 78.6, "note": "four rocBLAS FP64 GEMMs, timed together"}}
+                                  "frac": tf / 78.6,
+                                  "note": "the four quarter transformations timed together: the first (k_mp2_q1, "
+                                          "HBM-bound) and three rocBLAS FP64 GEMMs"}}
     print(json.dumps(out), flush=True)
     B.close()
     ctx.close()

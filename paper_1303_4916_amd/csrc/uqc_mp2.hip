@@ -4,9 +4,11 @@
 // (mu nu|lam sig) for every (mu nu) and every (lam sig) of the batch into a dense buffer T0b[mu][nu][col] (each
 // canonical bra shell pair times each ket shell pair of the batch, both index orders of each pair, so a shell
 // quartet is evaluated once for each of its two pairs' batches); the first quarter transformation is applied to
-// the batch at once and its columns are put in place in T1.  Then the remaining transformations run as GEMMs on
-// the matrix cores (rocBLAS; row-major tensors are handed over as their column-major transposes):
-//   Q1  T1[i][nu lam sig] = sum_mu C[mu][i] T0[mu][nu lam sig]          per batch, m = nbf cols, n = o, k = nbf
+// the batch at once by a bandwidth-bound kernel that writes its columns straight to their places in T1 (a GEMM
+// with n = o this thin would pad its tiles):
+//   Q1  T1[i][nu lam sig] = sum_mu C[mu][i] T0[mu][nu lam sig]          per batch, k_mp2_q1
+// Then the remaining transformations run as GEMMs on the matrix cores (rocBLAS; row-major tensors are handed over
+// as their column-major transposes):
 //   Q2  T2[i][a][lam sig] = sum_nu C[nu][a] T1[i][nu][lam sig]          batched over i, m = nbf^2, n = v, k = nbf
 //   Q3  Z[i a lam][b]     = sum_sig T2[i a lam][sig] C[sig][b]          one GEMM, m = v, n = o v nbf, k = nbf
 //   Q4  V[i][a][j][b]     = sum_lam C[lam][j] Z[i a][lam][b]           batched over (i a), m = v, n = o, k = nbf
@@ -59,18 +61,52 @@ struct DevBuf {
     ~DevBuf() { if (p) (void)hipFree(p); }
 };
 
-// Columns of a batch into their places in T1[i][nu][lam sig]: T1[i nbf^3 + nu nbf^2 + map[col]] = P[i R + nu ncols +
-// col], R = nbf ncols (P: the batch's first quarter transformation, column-major R x o).
-__global__ __launch_bounds__(kBlock) void k_mp2_place(const double* __restrict__ P, const int* __restrict__ map,
-                                                      int ncols, int nbf, int o, double* __restrict__ T1) {
-    const long long n = (long long)o * nbf * ncols;
+// First quarter transformation of one batch, written straight to the batch columns' places in T1:
+//   T1[i nbf^3 + nu nbf^2 + map[col]] = sum_mu C[mu][nfrozen + i] T0b[mu][nu ncols + col],  i0 <= i < i0 + ib,
+// ib <= kQ1Orb.  Each thread takes kQ1Cols batch columns j = nu ncols + col, 64 apart, so that a wavefront reads
+// kQ1Cols x 512 contiguous bytes of every row mu; the columns' values are read once per block of orbitals (HBM-bound:
+// 2 ib FLOPs per 8 bytes), the coefficients Co[mu nbf + i] (the active occupied orbitals of mu, contiguous) as
+// wavefront-uniform scalar loads shared by the thread's columns.
+constexpr int kQ1Orb = 16, kQ1Cols = 4;
+__global__ __launch_bounds__(kBlock) void k_mp2_q1(const double* __restrict__ T0b, const double* __restrict__ Co,
+                                                   const int* __restrict__ map, int ncols, int nbf, int i0, int ib,
+                                                   double* __restrict__ T1) {
     const long long R = (long long)nbf * ncols;
+    const long long j0 = ((long long)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) * (kWave * kQ1Cols) +
+                         threadIdx.x % kWave;
+    if (j0 >= R) return;
+    double a[kQ1Cols][kQ1Orb];
+#pragma unroll
+    for (int r = 0; r < kQ1Cols; ++r)
+#pragma unroll
+        for (int k = 0; k < kQ1Orb; ++k) a[r][k] = 0.0;
+    const cdptr c = as_const(Co) + i0;
+    for (int mu = 0; mu < nbf; ++mu) {
+        const double* row = T0b + (long long)mu * R;
+        double t[kQ1Cols];
+#pragma unroll
+        for (int r = 0; r < kQ1Cols; ++r) {
+            const long long j = j0 + (long long)r * kWave;
+            t[r] = j < R ? row[j] : 0.0;
+        }
+        const cdptr cm = c + (size_t)mu * nbf;
+#pragma unroll
+        for (int k = 0; k < kQ1Orb; ++k)
+            if (k < ib) {
+                const double ck = cm[k];
+#pragma unroll
+                for (int r = 0; r < kQ1Cols; ++r) a[r][k] = fma(ck, t[r], a[r][k]);
+            }
+    }
     const long long N2 = (long long)nbf * nbf, N3 = N2 * nbf;
-    for (long long x = (long long)blockIdx.x * kBlock + threadIdx.x; x < n; x += (long long)gridDim.x * kBlock) {
-        const int col = (int)(x % ncols);
-        const long long r = x / ncols;
-        const int nu = (int)(r % nbf), i = (int)(r / nbf);
-        T1[(long long)i * N3 + (long long)nu * N2 + map[col]] = P[(long long)i * R + (long long)nu * ncols + col];
+#pragma unroll
+    for (int r = 0; r < kQ1Cols; ++r) {
+        const long long j = j0 + (long long)r * kWave;
+        if (j >= R) break;
+        const long long to = (j / ncols) * N2 + map[j % ncols];
+#pragma unroll
+        for (int k = 0; k < kQ1Orb; ++k)
+            if (k < ib) T1[(long long)(i0 + k) * N3 + to] = a[r][k];
     }
 }
 
@@ -105,11 +141,11 @@ uqc_status uqc_mp2(uqc_basis* B, const double* C, const double* eps, int nocc, i
     UQC_HIP(hipSetDevice(ctx->device));
     size_t free_b = 0, total_b = 0;
     UQC_HIP(hipMemGetInfo(&free_b, &total_b));
-    // memory: T1 through the first two stages, then T2 + Z + V; a batch takes (nbf^2 + o nbf) doubles per column
-    // plus its lists; the widest shell pair has 2 x 6 x 6 columns
+    // memory: T1 through the first two stages, then T2 + Z + V; a batch takes nbf^2 doubles per column plus its
+    // lists; the widest shell pair has 2 x 6 x 6 columns
     const double avail = 0.9 * (double)free_b - 8.0 * ((double)NN + N + 64);
     const double later = 8.0 * std::max((double)nT1 + (double)nT2, (double)nT2 + (double)nZ + (double)nV);
-    const double per_col = 8.0 * ((double)NN + (double)o * N) + 64.0 * N;
+    const double per_col = 8.0 * (double)NN + 64.0 * N;
     double for_batch = avail - 8.0 * (double)nT1;
     if (batch_bytes > 0) for_batch = std::min(for_batch, (double)batch_bytes);
     long long wmax = 1;  // columns of the widest ket shell pair (a batch holds at least one)
@@ -121,7 +157,7 @@ uqc_status uqc_mp2(uqc_basis* B, const double* C, const double* eps, int nocc, i
     // supported
     if ((double)nT2 >= 2147483647.0 || (double)nZ >= 2147483647.0 || (double)N3 >= 2147483647.0)
         return uqc_fail(UQC_E_UNSUPPORTED, "uqc_mp2: an intermediate of the transformation exceeds 2^31 doubles");
-    // a batch buffer, the first GEMM's operand, stays below 2^31 doubles
+    // a batch buffer stays below 2^31 doubles
     const long long max_cols =
         (long long)std::min({for_batch / per_col, (double)NN, (double)(((1LL << 31) - 1) / (long long)NN)});
     if (later > avail || max_cols < std::min<long long>(wmax, (long long)NN))
@@ -132,7 +168,10 @@ uqc_status uqc_mp2(uqc_basis* B, const double* C, const double* eps, int nocc, i
     uqc_status st = uqc::ensure_blas(ctx, &h);
     if (st != UQC_OK) return st;
     DevBuf cbuf, vbuf;
-    if (hipMalloc(&cbuf.p, (NN + N + 8) * sizeof(double)) != hipSuccess) return uqc_fail(UQC_E_NOMEM, "uqc_mp2: C");
+    // C, the orbital energies, the energy sums, and kQ1Orb doubles of slack after them (k_mp2_q1 reads the
+    // coefficients in blocks of kQ1Orb)
+    if (hipMalloc(&cbuf.p, (NN + N + 8 + kQ1Orb) * sizeof(double)) != hipSuccess)
+        return uqc_fail(UQC_E_NOMEM, "uqc_mp2: C");
     double* Cd = (double*)cbuf.p;
     double* ed = Cd + NN;
     double* acc = ed + N;
@@ -174,13 +213,11 @@ uqc_status uqc_mp2(uqc_basis* B, const double* C, const double* eps, int nocc, i
         }
         long long widest = 0;
         for (long long c : bcols) widest = std::max(widest, c);
-        DevBuf tbuf, pbuf, mbuf;
+        DevBuf tbuf, mbuf;
         if (hipMalloc(&tbuf.p, std::max<size_t>((size_t)(NN * widest), 1) * sizeof(double)) != hipSuccess ||
-            hipMalloc(&pbuf.p, std::max<size_t>((size_t)o * N * widest, 1) * sizeof(double)) != hipSuccess ||
             hipMalloc(&mbuf.p, std::max<size_t>((size_t)widest, 1) * sizeof(int)) != hipSuccess)
             return uqc_fail(UQC_E_NOMEM, "uqc_mp2: batch buffers");
         double* T0b = (double*)tbuf.p;
-        double* P = (double*)pbuf.p;
         int* dmap = (int*)mbuf.p;
         // the quartet counter, then each batch's ket positions and columns (2 ints per ket pair of the widest batch)
         size_t maxk = 1;
@@ -273,17 +310,15 @@ uqc_status uqc_mp2(uqc_basis* B, const double* C, const double* eps, int nocc, i
                 UQC_HIP(hipEventRecord(ctx->join[k - 1], S[k]));
                 UQC_HIP(hipStreamWaitEvent(s, ctx->join[k - 1], 0));
             }
-            // Q1 of the batch: P (R x o) = T0b^T-view (R x N) * Co^T (N x o), R = nbf ncols; then into T1 (timed as
-            // part of the transformations once the batch's integrals are done)
+            // Q1 of the batch, straight into T1 (timed as part of the transformations once the batch's integrals
+            // are done)
             const long long R = (long long)N * ncols;
             UQC_HIP(hipStreamSynchronize(s));
             const auto tq = std::chrono::steady_clock::now();
-            UQC_BLAS_MP2(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_transpose, (rocblas_int)R, o, N,
-                                       &one, T0b, (rocblas_int)R, Co, N, &zero, P, (rocblas_int)R));
-            {
-                const long long n = (long long)o * R;
-                const unsigned grid = (unsigned)std::min<long long>((n + kBlock - 1) / kBlock, 65536);
-                hipLaunchKernelGGL(k_mp2_place, dim3(grid), dim3(kBlock), 0, s, P, dmap, ncols, N, o, T1);
+            for (int i0 = 0; i0 < o; i0 += kQ1Orb) {
+                const unsigned grid = (unsigned)((R + kBlock * kQ1Cols - 1) / (kBlock * kQ1Cols));
+                hipLaunchKernelGGL(k_mp2_q1, dim3(grid), dim3(kBlock), 0, s, T0b, Co, dmap, ncols, N, i0,
+                                   std::min(kQ1Orb, o - i0), T1);
                 UQC_HIP(hipGetLastError());
             }
             UQC_HIP(hipStreamSynchronize(s));  // the batch's ket lists are rewritten by the next batch
