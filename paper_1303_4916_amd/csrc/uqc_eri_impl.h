@@ -128,7 +128,7 @@ __device__ __forceinline__ int accumulate(const BinDev& B, int bra, int kbn, con
             if (nb == 0) break;
         }
         done += nb;
-        const double* kp = Kt.prim + (size_t)kk * npk + ket;
+        const cdptr kp = as_const(Kt.prim) + (size_t)kk * npk + ket;  // per-lane: vector loads
         const double eta = kp[F_Z * fsk];
         const double Qx = kp[F_PX * fsk], Qy = kp[F_PY * fsk], Qz = kp[F_PZ * fsk];
         const double QCx = kp[F_PAX * fsk], QCy = kp[F_PAY * fsk], QCz = kp[F_PAZ * fsk];
@@ -332,6 +332,18 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
         for (int i = (int)threadIdx.x; i < BROWS * (kBoysRow / 2); i += kBlock) btab[i] = src[i];
         __syncthreads();
     }
+    // MIXED, same classes: the FP32 table's rows of the grid points an FP32 evaluation can use (T <= kBoysTmax32,
+    // every order of a point in one row) in LDS as well
+    constexpr int B32ROWS = kBoysTmax32 * kBoysGridPerUnit + 1;
+    constexpr bool B32LDS = UQC_BOYS_LDS != 0 && MIXED &&
+                            (kBlock / kWave) * (SLOTS > 0 ? SLOTS * kWave : 1) * 8 + B32ROWS * kBoysNm * 4 <=
+                                160 * 1024 - 1024;
+    __shared__ float b32tab[B32LDS ? B32ROWS * kBoysNm : 1];
+    if constexpr (B32LDS) {
+        for (int i = (int)threadIdx.x; i < B32ROWS * kBoysNm; i += kBlock) b32tab[i] = boys32tab[i];
+        __syncthreads();
+    }
+    const float* const b32 = B32LDS ? b32tab : boys32tab;
     const DieItems di = die_items(nitems, queue);
     for (long long i = next_item(di); i < di.n; i = next_item(di)) {
         const long long item = item0 + global_item(di, i);
@@ -459,8 +471,8 @@ __global__ __launch_bounds__(kBlock) UQC_WAVES_ATTR void k_digest(const TaskDev*
                 double acc[C::NACC];
 #pragma unroll
                 for (int x = 0; x < C::NACC; ++x) acc[x] = 0.0;
-                const int done = accumulate<C, MIXED, BLDS, true>(B, bra, kbn, Kt, kl, kkn, boys64tab, boys32tab, acc,
-                                                                  btab, cqk, tk.boys_t);
+                const int done = accumulate<C, MIXED, BLDS, true>(B, bra, kbn, Kt, kl, kkn, boys64tab, b32, acc, btab,
+                                                                  cqk, tk.boys_t);
                 pcnt += (unsigned long long)__popcll(live) * (unsigned long long)done;
                 C::hrr(acc, bh[0], bh[1], bh[2], Kt.AB[kl], Kt.AB[Kt.np + kl],
                        Kt.AB[2 * Kt.np + kl], out);
