@@ -50,7 +50,7 @@ __device__ __forceinline__ int team_accumulate(const BinDev& B, int bra, int kbn
             if (nb == 0) break;
         }
         done += nb;
-        const double* kp = Kt.prim + (size_t)kk * npk + ket;
+        const cdptr kp = as_const(Kt.prim) + (size_t)kk * npk + ket;  // per-lane: vector loads
         const double eta = kp[F_Z * fsk];
         const double Qx = kp[F_PX * fsk], Qy = kp[F_PY * fsk], Qz = kp[F_PZ * fsk];
         const double QC0 = kp[F_PAX * fsk], QC1 = kp[F_PAY * fsk], QC2 = kp[F_PAZ * fsk];
