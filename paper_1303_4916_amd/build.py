@@ -34,8 +34,10 @@ PAIR = [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]
 # own register choice gives (none to a few dozen bytes of spill, measured faster per class); the others keep the
 # compiler's choice (for them one more wavefront costs 130-340 bytes of spill per lane and was slower)
 WAVES_PER_EU = {(2, 0, 1, 1): 2, (2, 1, 2, 1): 2, (2, 2, 1, 1): 2, (1, 1, 0, 0): 4, (1, 0, 1, 0): 4, (2, 0, 1, 0): 3}
-# classes that do not keep their K_ac sums in LDS (the slots would cost them a wavefront per SIMD)
-KAC_NOT_IN_LDS = {(2, 1, 1, 0)}
+# classes that do not keep their K_ac sums in LDS (the slots cost a wavefront per SIMD); none since the ket pairs
+# of a bin are ordered by their kept primitive count: (dp|ps) had been the one, and with its kets' first-shell runs
+# shorter its K_ac atomics doubled without the slots (275.6 ms per 150-atom build; 181.6 ms with them)
+KAC_NOT_IN_LDS = set()
 # classes whose FP64 Fock-build kernel reads the Boys rows from an LDS copy of its slice (measured per class: every
 # plain class gains or breaks even except (ds|ps), (ds|pp) and (ds|ds), which run more wavefronts per SIMD without
 # the rows' LDS and lose with it; (ds|ds): one workgroup per CU with the rows, two without, 132 vs 98.5 ms at 150

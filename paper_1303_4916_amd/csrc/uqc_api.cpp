@@ -696,11 +696,14 @@ uqc_status uqc_basis_create(uqc_ctx* ctx, int nshell, const int* l, const int* n
         Bin& bn = B->bins[bi];
         std::vector<int> perm(bn.np);
         std::iota(perm.begin(), perm.end(), 0);
-        // decade of the bound (descending), then first shell, then the second shell along the space-filling curve
-        // (then bound, descending)
+        // decade of the bound (descending), then the number of primitive pairs kept (descending: the ket loop of a
+        // 64-pair chunk runs to its largest count, and the per-chunk primitive screen ends it sooner when the chunk's
+        // pairs keep similar numbers), then first shell, then the second shell along the space-filling curve (then
+        // bound, descending)
         std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) {
             const int dx = decade(bn.Q[x]), dy = decade(bn.Q[y]);
             if (dx != dy) return dx > dy;
+            if (bn.kp[x] != bn.kp[y]) return bn.kp[x] > bn.kp[y];
             if (bn.off_a[x] != bn.off_a[y]) return bn.off_a[x] < bn.off_a[y];
             const uint32_t mx = morton[bn.sb[x]], my = morton[bn.sb[y]];
             if (mx != my) return mx < my;
